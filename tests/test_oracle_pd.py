@@ -1,0 +1,177 @@
+"""Pins of the FP64 primal-dual oracle (Algorithm 2) and the HyperSARA loop (Algorithm 1)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nufft, pd, prox, wavelets
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "appendix_a_constants.json")
+
+
+def _tiny_problem(seed=0, nx=16, ny=16, L=2, m=120, B=2, eps_scale=1.0, y_zero=False, precond=True):
+    rng = np.random.default_rng(seed)
+    uv = [rng.normal(0, 0.12, (m, 2)).astype(np.float32).astype(np.float64) for _ in range(L)]
+    th = [np.full(m, 2.0) for _ in range(L)]
+    X0 = np.zeros((L, ny, nx))
+    X0[:, ny // 2, nx // 2] = [1.0, 0.7][:L]
+    X0[:, 5, 9] = 0.4
+    bp = [np.array([(b * m) // B for b in range(B + 1)]) for _ in range(L)]
+    y = []
+    for l in range(L):
+        yl = nufft.phi(X0[l], uv[l], th[l]) + 0.05 * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+        y.append(np.zeros(m, complex) if y_zero else yl)
+    from oracle.precond import density_precond
+    u = [density_precond(uv[l], nx, ny) if precond else np.ones(m) for l in range(L)]
+    eps = [eps_scale * np.sqrt(np.diff(bp[l]) * 0.05 ** 2 * 2 * 1.3) for l in range(L)]
+    return pd.Problem(nx=nx, ny=ny, uv=uv, y=y, theta=th, u=u, eps=eps, block_ptr=bp), X0
+
+
+def test_golden_constants_match_defaults():
+    g = json.load(open(GOLD))
+    prm = pd.Params(mu=0.01)
+    assert (prm.lam1, prm.lam2, prm.lam3, prm.vartheta_bar) == (g["lambda1"], g["lambda2"], g["lambda3"], g["vartheta_bar"])
+    assert 0 < prm.tau < g["tau_upper_bound_exclusive"]
+    prob, _ = _tiny_problem()
+    assert prob.D == g["dictionary_size_D"]
+    k = pd.step_sizes(prob, prm, 4.0)
+    assert k == (g["kappa1"], 1.0 / 9.0, 0.25)
+    # convergence condition of Sec. 3.4: tau (k1 + k2 ||Psi^dag||^2 + k3 ||U^1/2 Phi||^2) < 1
+    assert prm.tau * (k[0] + k[1] * 9.0 + k[2] * 4.0) < 1.0
+
+
+def test_one_iteration_pieces_and_positivity():
+    prob, X0 = _tiny_problem(1)
+    cfg = W.CONFIGS["t1"].scaled(nx=16, ny=16, L=2)
+    st0 = W.make_state(cfg, X0, [len(y) for y in prob.y])
+    st = pd.State(X=st0["X"], Xt=st0["Xt"], P=st0["P"], A=st0["A"], v=st0["v"],
+                  eps=[e.copy() for e in prob.eps], vartheta=[np.zeros(2, np.int64)] * 2)
+    prm = pd.Params(mu=0.05, tau=0.3)
+    nrm, _, _ = pd.op_norm_phi(prob, W.synth.power_start(cfg), tol=1e-12)
+    kap = pd.step_sizes(prob, prm, nrm)
+    out = pd.pd_iteration(st, prob, prm, kap, return_parts=True)
+    assert np.all(out.X >= 0)
+    # recompute Step 20 with the pieces and an independent U = I-free path check
+    G = kap[0] * out.P + kap[1] * out.extra["At_sum"] + kap[2] * out.extra["data_adj"]
+    assert np.allclose(out.X, np.maximum(st.X - prm.tau * G, 0))
+    assert np.allclose(out.Xt, 2 * out.X - st.X)
+    # dual residual rows have norm <= mu * D * wbar (l2,1 dual is a ball projection)
+    rn = np.sqrt(np.sum(out.A ** 2, axis=1))
+    assert np.all(rn <= prm.mu * 9.0 * (1 + 1e-12))
+    # every data dual v = vbar - U q with ||q - y|| <= eps
+    for l in range(prob.L):
+        vbar = st.v[l] + prob.u[l] * nufft.phi(st.Xt[l], prob.uv[l], prob.theta[l])
+        q = (vbar - out.v[l]) / prob.u[l]
+        bp = prob.block_ptr[l]
+        for b in range(len(bp) - 1):
+            s = slice(bp[b], bp[b + 1])
+            assert np.linalg.norm(q[s] - prob.y[l][s]) <= prob.eps[l][b] * (1 + 1e-10)
+
+
+def test_zero_is_the_solution_when_data_inside_balls():
+    # ||y_b|| <= eps_b for every block: X = 0 is feasible and minimises the
+    # (non-negative) objective uniquely, so the iteration must go to 0.
+    prob, X0 = _tiny_problem(2, y_zero=True)
+    prm = pd.Params(mu=0.05)
+    nrm, _, _ = pd.op_norm_phi(prob, np.random.default_rng(0).standard_normal((2, 16, 16)), tol=1e-10)
+    kap = pd.step_sizes(prob, prm, nrm)
+    st = pd.zero_state(prob)
+    st.X = X0.copy()
+    st.Xt = X0.copy()
+    for _ in range(300):
+        st = pd.pd_iteration(st, prob, prm, kap)
+    assert np.linalg.norm(st.X) < 1e-6 * np.linalg.norm(X0)
+
+
+@pytest.mark.slow
+def test_constraints_approached_at_convergence():
+    # Well-conditioned tiny problem (M > N, uniform uv, U = I): the primal-dual
+    # iterates approach feasibility and the objective settles.  PD converges
+    # sublinearly, so the bound is checked to 3 % after 1200 iterations and the
+    # residual must keep shrinking towards the ball.
+    rng = np.random.default_rng(3)
+    nx = ny = 16; L = 2; m = 600
+    uv = [rng.uniform(-0.5, 0.5, (m, 2)).astype(np.float32).astype(np.float64) for _ in range(L)]
+    th = [np.ones(m)] * L
+    X0 = np.zeros((L, ny, nx)); X0[:, 8, 8] = [1.0, 0.7]; X0[:, 5, 9] = 0.4
+    bp = [np.array([0, 300, 600])] * L
+    y = [nufft.phi(X0[l], uv[l], th[l]) + 0.05 * (rng.standard_normal(m) + 1j * rng.standard_normal(m)) for l in range(L)]
+    eps = [np.sqrt(np.diff(bp[l]) * 0.05 ** 2 * 2 * 1.3) for l in range(L)]
+    prob = pd.Problem(nx=nx, ny=ny, uv=uv, y=y, theta=th, u=[np.ones(m)] * L, eps=eps, block_ptr=bp)
+    prm = pd.Params(mu=0.02)
+    nrm, _, _ = pd.op_norm_phi(prob, rng.standard_normal((2, 16, 16)), tol=1e-10)
+    kap = pd.step_sizes(prob, prm, nrm)
+    st = pd.zero_state(prob)
+    ratio, objs = {}, []
+    for it in range(1, 1201):
+        st = pd.pd_iteration(st, prob, prm, kap)
+        if it in (600, 1200):
+            _, _, res = pd.objective_parts(st.X, prob, prm)
+            ratio[it] = max(float(np.max(r / e)) for r, e in zip(res, prob.eps))
+        if it >= 1000 and it % 100 == 0:
+            nuc, l21, _ = pd.objective_parts(st.X, prob, prm)
+            objs.append(nuc + prm.mu * l21)
+    assert ratio[1200] <= 1.03 and ratio[1200] < ratio[600]
+    assert abs(objs[-1] - objs[0]) <= 2e-3 * objs[-1]
+    assert st.beta < 1e-4
+    assert np.all(st.X >= 0)
+
+
+def test_adaptive_eps_update_rule():
+    # Steps 13-19 with constants from Appendix A: force the update conditions
+    prob, X0 = _tiny_problem(4)
+    prm = pd.Params(mu=0.05, adaptive_eps=True, vartheta_bar=0)
+    st = pd.zero_state(prob)
+    st.X = X0.copy(); st.Xt = X0.copy(); st.beta = 0.0; st.t = 5
+    out = pd.pd_iteration(st, prob, prm, (1.0, 1 / 9, 1e-3))
+    for l in range(prob.L):
+        for b in range(len(prob.eps[l])):
+            rho = out.extra["rho"][l][b]
+            e0 = prob.eps[l][b]
+            if abs(rho - e0) / e0 > prm.lam2:
+                assert out.eps[l][b] == pytest.approx(0.618 * rho + 0.382 * e0)
+                assert out.vartheta[l][b] == 6
+            else:
+                assert out.eps[l][b] == e0
+
+
+def test_reweighting_formulas():
+    prob, X0 = _tiny_problem(5)
+    wbar, w = pd.reweight(X0, prob, gamma=0.5, gamma_bar=0.25)
+    C = wavelets.psi_adj(X0)
+    rn = np.sqrt((C ** 2).sum(axis=1))
+    assert np.allclose(wbar, 0.25 / (0.25 + rn))
+    s = np.linalg.svd(X0.reshape(2, -1).T, compute_uv=False)
+    assert np.allclose(w, 0.5 / (0.5 + s))
+    assert np.all(np.diff(w) >= 0)          # non-decreasing: S*_w is then the exact prox
+
+
+def test_mu_hat_definition():
+    prob, X0 = _tiny_problem(6)
+    Xd = pd.dirty_cube(prob)
+    # PSF peak normalisation: Phi^dag Phi delta scaled to peak 1
+    delta = np.zeros((16, 16)); delta[8, 8] = 1
+    psf = nufft.phi_adj(nufft.phi(delta, prob.uv[0], prob.theta[0]), prob.uv[0], prob.theta[0], 16, 16)
+    assert np.allclose(Xd[0], nufft.phi_adj(prob.y[0], prob.uv[0], prob.theta[0], 16, 16) / psf.max())
+    mu = pd.mu_hat(prob)
+    nuc = np.linalg.svd(Xd.reshape(2, -1).T, compute_uv=False).sum()
+    l21 = np.sqrt((wavelets.psi_adj(Xd) ** 2).sum(axis=1)).sum()
+    assert mu == pytest.approx(nuc / l21)
+
+
+def test_workload_measurements_and_bounds():
+    cfg = W.CONFIGS["t2"]
+    inp = W.make_problem_inputs(cfg)
+    prob, y_raw = pd.build_problem(cfg, inp)
+    for l in range(cfg.L):
+        m = len(prob.uv[l])
+        bp = inp["block_ptr"][l]
+        assert bp[0] == 0 and bp[-1] == m and np.all(np.diff(bp) >= 0)
+        mb = np.diff(bp)
+        assert np.allclose(prob.eps[l], np.sqrt(mb + 2 * np.sqrt(mb)))
+        # whitened noise of each block is inside its bound with high probability
+        y0 = nufft.phi(inp["X0"][l], prob.uv[l], np.ones(m))
+        wn = prob.theta[l] * (y_raw[l] - y0)
+        assert np.linalg.norm(wn) ** 2 == pytest.approx(m, rel=0.2)
