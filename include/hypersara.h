@@ -1,0 +1,273 @@
+/*
+ * hypersara.h -- C ABI of the MI355X (gfx950) HyperSARA primal-dual hot path.
+ *
+ * Method: Abdulaziz, Dabbech & Wiaux, "Wideband super-resolution imaging in
+ * radio interferometry via low rankness and joint average sparsity models
+ * (HyperSARA)", MNRAS, arXiv:1806.04596.  Sections, equation labels and
+ * algorithm steps of that paper are cited per entry point.
+ *
+ * Conventions (all entry points):
+ *  - Every call returns hs_status (0 = HS_OK, negative = error); no C++
+ *    exception crosses this boundary.  hs_last_error(ctx) gives a message.
+ *  - A context fixes the problem shape and the working precision (HS_F32 or
+ *    HS_F64).  "real" below is float or double accordingly, "complex" is two
+ *    interleaved reals (re, im).
+ *  - Image cubes are [L][ny][nx] row-major (row j = y, column i = x), pixel
+ *    (i, j) sits at (i - nx/2, j - ny/2) from the phase centre.
+ *  - uv coordinates are in cycles per pixel at the channel's own frequency.
+ *  - Device pointers must be device memory of the context's device, sized as
+ *    stated; they are borrowed for the call only.  Device work is enqueued on
+ *    the stream given in hs_problem_desc and is asynchronous unless a call is
+ *    documented as synchronising.  Asynchronous device faults surface as
+ *    HS_ERR_HIP at the next synchronising call.
+ *  - Host pointers are read during the call only (the library copies them).
+ *  - The library never allocates device memory: hs_plan reports the
+ *    workspace size and the caller binds a buffer with hs_bind_workspace.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef HYPERSARA_H
+#define HYPERSARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hs_status;
+enum {
+    HS_OK = 0,
+    HS_ERR_INVALID_ARG = -1,
+    HS_ERR_SHAPE = -2,
+    HS_ERR_DTYPE = -3,
+    HS_ERR_NOT_PLANNED = -4,
+    HS_ERR_NO_WORKSPACE = -5,
+    HS_ERR_NONFINITE = -6,
+    HS_ERR_HIP = -7,
+    HS_ERR_NOT_CONVERGED = -8
+};
+
+enum { HS_F32 = 0, HS_F64 = 1 };
+enum { HS_NORM_PHI_PRECOND = 0, HS_NORM_PSI = 1 };
+
+typedef struct hs_ctx hs_ctx;
+
+/* Problem description (Sec. 2.1 data model, Sec. 2.3 dictionary).
+ * nx, ny: image size; powers of two in 16..16384 (and >= 2^levels).
+ * L: number of channels (1..64).
+ * oversamp: grid oversampling per dimension; must be 2.
+ * J: Kaiser-Bessel support per dimension; must be 8.
+ * levels: wavelet depth (1..6), n_db: number of Daubechies bases (0..8),
+ *   the dictionary is Dirac + db1..db{n_db} (D = 1 + n_db bases).
+ * dtype: HS_F32 or HS_F64.  tile: gridding tile edge (0 = automatic; else a
+ *   power of two in 8..64 with 2*nx/tile >= 3 and 2*ny/tile >= 3).
+ * device: HIP device ordinal; stream: hipStream_t (NULL = default stream). */
+typedef struct {
+    int32_t nx, ny, L;
+    int32_t oversamp;
+    int32_t J;
+    int32_t levels;
+    int32_t n_db;
+    int32_t dtype;
+    int32_t tile;
+    int32_t device;
+    void* stream;
+} hs_problem_desc;
+
+/* Sizes after hs_plan. */
+typedef struct {
+    int64_t n_vis;          /* sum of M_l */
+    int64_t n_blocks;       /* sum of B_l */
+    int64_t n_bins;         /* (block, preconditioner value) classes */
+    int64_t n_runs;         /* segmented-reduction runs */
+    int64_t n_degrid_units; /* degridding work units */
+    int64_t n_grid_units;   /* gridding work units */
+    int32_t tile;           /* tile edge used */
+    int32_t kb_terms;       /* terms of the kernel's power series */
+    size_t workspace_bytes;
+} hs_info;
+
+/* Parameters of one adaptive PPD iteration (Algorithm 2, Sec. 3.4).
+ * kappa1 <= 0 -> 1; kappa2 <= 0 -> 1/D (= 1/||Psi^dagger||_S^2);
+ * kappa3 must be > 0 (1/||U^{1/2} Phi||_S^2, see hs_op_norm).
+ * tau: primal step, convergence needs tau(k1 + k2 D + k3 ||U^1/2 Phi||^2) < 1.
+ * wbar: device real [D][ny][nx] l2,1 weights (NULL = ones), copied.
+ * w: host double [L] nuclear weights paired with singular values in
+ *    decreasing order (NULL = ones), copied.
+ * adaptive_eps: nonzero enables Steps 13-19 with lam1..lam3, vartheta_bar
+ *    (Appendix A: 5e-4, 0.01, 0.618, 100). */
+typedef struct {
+    double mu, tau, kappa1, kappa2, kappa3;
+    const void* wbar;
+    const double* w;
+    int32_t adaptive_eps;
+    double lam1, lam2, lam3;
+    int32_t vartheta_bar;
+} hs_pd_params;
+
+/* Device pointers to a primal-dual state, ctx dtype.  X, Xt, P: [L][ny][nx];
+ * A: [D][L][ny][nx]; v: [sum M_l] complex in the caller's visibility order
+ * (channel by channel, each in the order given to hs_set_channel).
+ * Any member may be NULL (skipped). */
+typedef struct {
+    void* X;
+    void* Xt;
+    void* P;
+    void* A;
+    void* v;
+} hs_state_ptrs;
+
+/* Outer loop (Algorithm 1).  Each reweight runs iters_per_reweight PD
+ * iterations (or stops early when beta < beta_tol, checked every
+ * check_every iterations), then updates wbar by eq:weights-l21 and w by
+ * eq:weights-n with gamma, gamma_bar starting at 1 and multiplied by
+ * gamma_factor after each update.  Warm starts every variable. */
+typedef struct {
+    int32_t n_reweights;
+    int32_t iters_per_reweight;
+    double gamma_factor;
+    double beta_tol;
+    int32_t check_every;
+} hs_solve_params;
+
+typedef struct {
+    int64_t iterations;
+    int32_t reweights;
+    double final_beta;
+} hs_report;
+
+/* ---------------------------------------------------------- diagnostics */
+const char* hs_status_string(hs_status s);
+/* Message of the last error on ctx (or of the last failed hs_create when ctx is NULL). */
+const char* hs_last_error(const hs_ctx* ctx);
+
+/* -------------------------------------------------------------- lifecycle */
+/* Creates a context; *out is set on success.  Validates the description
+ * (HS_ERR_INVALID_ARG / HS_ERR_SHAPE / HS_ERR_DTYPE).  No device memory is
+ * allocated. */
+hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out);
+hs_status hs_destroy(hs_ctx* ctx);
+
+/* Channel data for the measurement model y_l = Phi_l x_l + w_l with
+ * Phi_l = Theta_l G_l F Z (eq:inverse) split in blocks (Sec. 2.3).
+ * l: channel 0..L-1; M: number of visibilities (>= 0);
+ * nblocks, block_ptr[nblocks+1]: contiguous blocks, block_ptr[0] = 0,
+ *   non-decreasing, block_ptr[nblocks] = M (nblocks >= 1 when M > 0);
+ * uv[M][2]: (u, v) in cycles per pixel; y_raw[M][2]: complex data before
+ *   natural weighting; theta[M]: natural weights 1/sigma (> 0);
+ * precond[M]: diagonal of U (> 0), or NULL for U = I (Sec. 3.3, the
+ *   density preconditioner is available from hs_density_precond);
+ * eps[nblocks]: l2 bounds (>= 0).
+ * All pointers are host and copied.  Non-finite values -> HS_ERR_NONFINITE.
+ * Must be called for every channel before hs_plan. */
+hs_status hs_set_channel(hs_ctx* ctx, int32_t l, int64_t M, int32_t nblocks, const int64_t* block_ptr,
+                         const double* uv, const double* y_raw, const double* theta,
+                         const double* precond, const double* eps);
+
+/* Replaces y_raw, theta and eps of channel l after hs_plan/hs_bind_workspace
+ * (same M and blocks).  Host pointers, copied; enqueues uploads on the stream. */
+hs_status hs_set_data(hs_ctx* ctx, int32_t l, const double* y_raw, const double* theta, const double* eps);
+
+/* Sorts and bins the visibilities (bit-exact integer keys, see
+ * hs_visibility_order), builds the work lists, kernel and FFT tables, and
+ * returns the device workspace size in bytes. */
+hs_status hs_plan(hs_ctx* ctx, size_t* workspace_bytes);
+
+/* Binds caller-allocated device memory (>= workspace_bytes, 256-byte aligned)
+ * and uploads the plan.  The primal-dual state lives in this workspace and
+ * starts at zero (Algorithm 2 initialisation). */
+hs_status hs_bind_workspace(hs_ctx* ctx, void* dev, size_t bytes);
+
+hs_status hs_get_info(const hs_ctx* ctx, hs_info* info);
+
+/* ------------------------------------------------ host utilities (no GPU) */
+/* Density preconditioner (Sec. 3.3): out[m] = 1/n_m with n_m the number of
+ * visibilities in the same cell (floor(u nx) mod nx, floor(v ny) mod ny). */
+hs_status hs_density_precond(int64_t M, const double* uv, int32_t nx, int32_t ny, double* out);
+
+/* The library's visibility order for one channel: perm[k] = input index of the
+ * k-th visibility in tile-major order, sorted by (tile, region, bin) with ties
+ * in input order; region_ptr[t*9 + r] = first position of region r of tile t,
+ * region_ptr has (2nx/tile)(2ny/tile)*9 + 1 entries.  precond may be NULL. */
+hs_status hs_visibility_order(int64_t M, const double* uv, const double* precond, int32_t nblocks,
+                              const int64_t* block_ptr, int32_t nx, int32_t ny, int32_t tile,
+                              int64_t* perm, int64_t* region_ptr);
+
+/* Low-pass filter of db-K (2K taps) by the library's own spectral factorisation. */
+hs_status hs_daubechies_filter(int32_t K, double* h);
+
+/* --------------------------------------------------------------- operators */
+/* Phi (eq:inverse, all channels): Y = [Theta_l G_l F Z x_l]_l.
+ * X: real [L][ny][nx]; Y: complex [sum M_l] in the caller's order. */
+hs_status hs_phi(hs_ctx* ctx, const void* X, void* Y);
+
+/* Re Phi^dagger (adjoint in the dual problem, Sec. 3.2): X_l = Re Z^T F^H G_l^T Theta_l y_l. */
+hs_status hs_phi_adj(hs_ctx* ctx, const void* Y, void* X);
+
+/* Psi^dagger (Sec. 2.3): C[d] = Psi_d^dagger X, d = 0 Dirac, d = K for db-K.
+ * X: real [L][ny][nx]; C: real [D][L][ny][nx]. */
+hs_status hs_psi_adj(hs_ctx* ctx, const void* X, void* C);
+
+/* Psi: X = sum_d Psi_d C[d]. */
+hs_status hs_psi(hs_ctx* ctx, const void* C, void* X);
+
+/* --------------------------------------------------- proxes / dual updates */
+/* eq:prox-L21 in place: rows of length L at fixed (d, y, x) of A [D][L][ny][nx]
+ * are shrunk by max(||a|| - t*wbar, 0)/||a||.  wbar: real [D][ny][nx] or NULL (ones). */
+hs_status hs_prox_l21(hs_ctx* ctx, void* A, const void* wbar, double t);
+
+/* Algorithm 2 Steps 7-8: A_d <- (I - S^{l21}_{wbar mu D})(A_d + Psi_d^dagger Xt) in place,
+ * and, when At_sum is not NULL, At_sum = sum_d Psi_d A_d (real [L][ny][nx]). */
+hs_status hs_dual_l21(hs_ctx* ctx, void* A, const void* Xt, const void* wbar, double mu, void* At_sum);
+
+/* eq:prox-L* in place on the N x L matrix X (column l = channel l):
+ * singular values soft-thresholded by w (host [L], paired with decreasing
+ * singular values; NULL = ones).  sigma_out (host [L], may be NULL) receives
+ * the singular values of the input in decreasing order.  Synchronising. */
+hs_status hs_prox_nuclear(hs_ctx* ctx, void* X, const double* w, double* sigma_out);
+
+/* Algorithm 2 Step 5: P <- (I - S*_w)(P + Xt) in place. */
+hs_status hs_dual_nuclear(hs_ctx* ctx, void* P, const void* Xt, const double* w);
+
+/* Algorithm 2 Steps 4, 10, 11 for every block (l, b): v_l^b <- the
+ * preconditioned data-fidelity dual update from Xt (eq:md with the ellipsoid
+ * projection solved exactly).  v: complex [sum M_l] caller order, in place.
+ * When adj_out is not NULL it receives Re Phi^dagger v_new (Steps 12, 20; real [L][ny][nx]). */
+hs_status hs_dual_data(hs_ctx* ctx, void* v, const void* Xt, void* adj_out);
+
+/* Prox of the indicator of B(y_l^b, eps_l^b) in the metric U_l^b (eq:prox,
+ * Sec. 3.3): z <- argmin_{||q - y|| <= eps} (q - z)^H U (q - z).  z: device
+ * complex [M_b], block b of channel l in the caller's order.  Synchronising. */
+hs_status hs_proj_ellipsoid(hs_ctx* ctx, int32_t l, int32_t b, void* z);
+
+/* Spectral norms for the step sizes (Sec. 3.4), FP64 power iteration.
+ * which = HS_NORM_PHI_PRECOND: max_l of the largest eigenvalue of
+ *   x -> Re Phi_l^dagger U_l Phi_l x over real images, started from x0
+ *   (device real [L][ny][nx], caller-drawn), stopping at relative change
+ *   < tol or max_it iterations; per-channel values in per_channel (host [L], may be NULL).
+ * which = HS_NORM_PSI: ||Psi^dagger||_S^2 = D (orthonormal bases), exact.
+ * *iters receives the iterations used (may be NULL).  Synchronising. */
+hs_status hs_op_norm(hs_ctx* ctx, int32_t which, int32_t max_it, double tol, const void* x0,
+                     double* out, double* per_channel, int32_t* iters);
+
+/* -------------------------------------------------------------- PD solver */
+/* Sets parameters of Algorithm 2 (does not reset the state). */
+hs_status hs_pd_init(hs_ctx* ctx, const hs_pd_params* params);
+/* Copy a state into / out of the context (device-to-device, on the stream). */
+hs_status hs_pd_set_state(hs_ctx* ctx, const hs_state_ptrs* st);
+hs_status hs_pd_get_state(hs_ctx* ctx, const hs_state_ptrs* st);
+/* n iterations of Algorithm 2 (Steps 3-23).  The first call captures one
+ * iteration into a HIP graph that later calls replay. */
+hs_status hs_pd_iterate(hs_ctx* ctx, int32_t n);
+/* beta of the last iteration (Step 23), and per-block residual norms rho
+ * (Step 13, host [n_blocks], may be NULL) and bounds eps (host [n_blocks],
+ * may be NULL).  Synchronising. */
+hs_status hs_pd_stats(hs_ctx* ctx, double* beta, double* rho, double* eps);
+/* Algorithm 1 on the current state; X_out (device real [L][ny][nx], may be NULL). */
+hs_status hs_solve(hs_ctx* ctx, const hs_solve_params* params, void* X_out, hs_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYPERSARA_H */

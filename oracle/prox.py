@@ -136,6 +136,8 @@ def proj_ball_precond(c: np.ndarray, y: np.ndarray, u: np.ndarray, eps: float):
     r = c - y
     if np.linalg.norm(r) <= eps:
         return c.copy(), 0.0
+    if eps == 0.0:          # the ball is the single point y
+        return y.copy(), np.inf
     a = (u * u) * (r.real ** 2 + r.imag ** 2)
     lam = secular_root(a, u, eps)
     return y + (u / (u + lam)) * r, lam

@@ -1,0 +1,817 @@
+// C ABI entry points: lifecycle, workspace, operators, proxes and the PD solver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+static std::string g_create_err;
+
+hs_status fail(hs_ctx* c, hs_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return s;
+}
+
+hs_status hip_check(hs_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return HS_OK;
+    return fail(c, HS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hs_status build_plan(hs_ctx* c);
+
+// ------------------------------------------------------------ workspace layout
+struct Carver {
+    size_t off = 0;
+    template <typename P>
+    void take(P*& p, size_t bytes, char* base) {
+        off = (off + 255) & ~(size_t)255;
+        p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += std::max<size_t>(bytes, 1);
+    }
+};
+
+static size_t carve(hs_ctx* c, char* base) {
+    Carver k;
+    Dev& d = c->d;
+    const size_t r = c->rsz, cx = 2 * c->rsz;
+    const size_t M = (size_t)c->Mtot, LN = (size_t)c->L * c->N;
+    k.take(d.vis_cell, M * 4, base);
+    k.take(d.vis_frac, M * cx, base);
+    k.take(d.vis_y, M * cx, base);
+    k.take(d.vis_theta, M * r, base);
+    k.take(d.vis_u, M * r, base);
+    k.take(d.vis_bin, M * 4, base);
+    k.take(d.vis_perm, M * 4, base);
+    k.take(d.vis_pos, M * 4, base);
+    k.take(d.v, M * cx, base);
+    k.take(d.vwork, M * cx, base);
+    k.take(d.dunits, c->dunits.size() * sizeof(DegridUnit), base);
+    k.take(d.gunits, c->gunits.size() * sizeof(GridUnit), base);
+    k.take(d.splits, c->splits.size() * sizeof(SplitTile), base);
+    k.take(d.granges, c->h_granges.size() * 4, base);
+    k.take(d.gpartial, (size_t)c->npartial * c->T * c->T * cx, base);
+    k.take(d.bin_u, (size_t)c->nbins * 8, base);
+    k.take(d.bin_block, (size_t)c->nbins * 4, base);
+    k.take(d.blk_bin_ptr, (size_t)(c->nblk + 1) * 4, base);
+    k.take(d.blk_eps, (size_t)c->nblk * 8, base);
+    k.take(d.blk_lambda, (size_t)c->nblk * 8, base);
+    k.take(d.blk_rho2, (size_t)c->nblk * 8, base);
+    k.take(d.blk_vartheta, (size_t)c->nblk * 4, base);
+    k.take(d.run_sum, (size_t)c->nruns * 16, base);
+    k.take(d.bin_run_ptr, (size_t)(c->nbins + 1) * 4, base);
+    k.take(d.bin_runs, (size_t)c->nruns * 4, base);
+    k.take(d.bin_S, (size_t)c->nbins * 16, base);
+    k.take(d.grid, (size_t)c->L * c->Kx * c->Ky * cx, base);
+    k.take(d.H, (size_t)c->L * c->ny * c->Kx * cx, base);
+    k.take(d.tw_x, (size_t)c->Kx * cx, base);
+    k.take(d.tw_y, (size_t)c->Ky * cx, base);
+    k.take(d.sx, (size_t)c->nx * r, base);
+    k.take(d.sy, (size_t)c->ny * r, base);
+    k.take(d.X, LN * r, base);
+    k.take(d.Xt, LN * r, base);
+    k.take(d.P, LN * r, base);
+    k.take(d.img0, LN * r, base);
+    k.take(d.img1, LN * r, base);
+    k.take(d.A, (size_t)c->D * LN * r, base);
+    k.take(d.coef, (size_t)std::max(c->n_db, 1) * LN * r, base);
+    k.take(d.wtmp, (size_t)std::max(c->n_db, 1) * LN * r, base);
+    k.take(d.wbar, (size_t)c->D * c->N * r, base);
+    k.take(d.filt, (size_t)MAX_DB * 32 * r, base);
+    k.take(d.gram_part, (size_t)NGRAM * MAX_L * MAX_L * 8, base);
+    k.take(d.gram, (size_t)MAX_L * MAX_L * 8, base);
+    k.take(d.eigV, (size_t)MAX_L * MAX_L * 8, base);
+    k.take(d.eig_sig, (size_t)MAX_L * 8, base);
+    k.take(d.w_nuc, (size_t)MAX_L * 8, base);
+    k.take(d.Wmat, (size_t)MAX_L * MAX_L * r, base);
+    k.take(d.red_part, (size_t)std::max<int64_t>(NRED * 4, 64 * MAX_L) * 8, base);
+    k.take(d.scal, 64 * 8, base);
+    k.take(d.chan_nrm, (size_t)MAX_L * 8, base);
+    return (k.off + 255) & ~(size_t)255;
+}
+
+template <typename T>
+static void upload_real(hs_ctx* c, void* dst, const std::vector<double>& src) {
+    std::vector<T> tmp(src.begin(), src.end());
+    if (!tmp.empty()) (void)hipMemcpy(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename V>
+static void upload(void* dst, const std::vector<V>& src) {
+    if (!src.empty()) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+static hs_status bind_impl(hs_ctx* c) {
+    Dev& d = c->d;
+    upload(d.vis_cell, c->h_cell);
+    upload_real<T>(c, d.vis_frac, c->h_frac);
+    upload_real<T>(c, d.vis_y, c->h_y);
+    upload_real<T>(c, d.vis_theta, c->h_theta);
+    upload_real<T>(c, d.vis_u, c->h_u);
+    upload(d.vis_bin, c->h_bin);
+    upload(d.vis_perm, c->h_perm);
+    {
+        std::vector<int32_t> pos(c->h_pos_of.begin(), c->h_pos_of.end());
+        upload(d.vis_pos, pos);
+    }
+    upload(d.dunits, c->dunits);
+    upload(d.gunits, c->gunits);
+    upload(d.splits, c->splits);
+    upload(d.granges, c->h_granges);
+    upload(d.bin_u, c->h_bin_u);
+    upload(d.bin_block, c->h_bin_block);
+    upload(d.blk_bin_ptr, c->h_blk_bin_ptr);
+    upload(d.blk_eps, c->h_blk_eps);
+    upload(d.bin_run_ptr, c->h_bin_run_ptr);
+    upload(d.bin_runs, c->h_bin_runs);
+    // FFT twiddles exp(-2 pi i k / K) and deapodisation 1/phihat(p/K)
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int dim = 0; dim < 2; ++dim) {
+        const int K = dim == 0 ? c->Kx : c->Ky;
+        std::vector<double> tw(2 * (size_t)K);
+        for (int k = 0; k < K; ++k) {
+            const long double a = 2.0L * pi * (long double)k / (long double)K;
+            tw[2 * k] = (double)std::cos(a);
+            tw[2 * k + 1] = (double)(-std::sin(a));
+        }
+        upload_real<T>(c, dim == 0 ? d.tw_x : d.tw_y, tw);
+        const int n = dim == 0 ? c->nx : c->ny;
+        std::vector<double> s(n);
+        for (int i = 0; i < n; ++i) s[i] = 1.0 / kb_ft((double)(i - n / 2) / (double)K);
+        upload_real<T>(c, dim == 0 ? d.sx : d.sy, s);
+    }
+    {
+        std::vector<double> f((size_t)MAX_DB * 32, 0.0);
+        for (int b = 0; b < c->n_db; ++b) {
+            const int K = b + 1;
+            double h[2 * MAX_DB];
+            daubechies_host(K, h);
+            for (int j = 0; j < 2 * K; ++j) {
+                f[b * 32 + j] = h[j];
+                f[b * 32 + 16 + j] = ((j & 1) ? -1.0 : 1.0) * h[2 * K - 1 - j];
+            }
+        }
+        upload_real<T>(c, d.filt, f);
+    }
+    {
+        std::vector<double> I((size_t)MAX_L * MAX_L, 0.0);
+        for (int i = 0; i < MAX_L; ++i) I[i * MAX_L + i] = 1.0;
+        upload(d.eigV, I);
+        std::vector<double> ones(MAX_L, 1.0);
+        upload(d.w_nuc, ones);
+    }
+    const int64_t LN = (int64_t)c->L * c->N;
+    launch_fill<T>(c->stream, (T*)d.X, T(0), LN);
+    launch_fill<T>(c->stream, (T*)d.Xt, T(0), LN);
+    launch_fill<T>(c->stream, (T*)d.P, T(0), LN);
+    launch_fill<T>(c->stream, (T*)d.A, T(0), (int64_t)c->D * LN);
+    launch_fill<T>(c->stream, (T*)d.v, T(0), 2 * c->Mtot);
+    launch_fill<T>(c->stream, (T*)d.wbar, T(1), (int64_t)c->D * c->N);
+    launch_fill<double>(c->stream, d.scal, 0.0, 64);
+    launch_fill<int32_t>(c->stream, d.blk_vartheta, 0, c->nblk);
+    launch_fill<double>(c->stream, d.blk_lambda, 0.0, c->nblk);
+    launch_fill<double>(c->stream, d.blk_rho2, 0.0, c->nblk);
+    return hip_check(c, hipStreamSynchronize(c->stream), "hs_bind_workspace");
+}
+
+// ------------------------------------------------------------- operator bodies
+template <typename T>
+static void phi_impl(hs_ctx* c, const T* X, cplx<T>* Y) {
+    launch_fft_rows_fwd<T>(c, X, c->L);
+    launch_fft_cols_fwd<T>(c, c->L);
+    launch_degrid_plain<T>(c, Y);
+}
+
+// grid-order visibility values (already weighted) -> Re Z^T F^H G^T vals
+template <typename T>
+static void adj_from_grid_order(hs_ctx* c, const cplx<T>* vals, const T* weight, T* X) {
+    launch_grid_pull<T>(c, vals, weight);
+    launch_fft_cols_adj<T>(c, c->L);
+    launch_fft_rows_adj<T>(c, X, c->L);
+}
+
+template <typename T>
+static void phi_adj_impl(hs_ctx* c, const cplx<T>* Y, T* X) {
+    launch_gather_user<T>(c, Y, (cplx<T>*)c->d.vwork, true);
+    adj_from_grid_order<T>(c, (const cplx<T>*)c->d.vwork, nullptr, X);
+}
+
+// Steps 4, 10, 11 on dual v (grid order, in place); Step 12 + F^H Z^T into adj if given.
+template <typename T>
+static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj) {
+    launch_fft_rows_fwd<T>(c, Xt, c->L);
+    launch_fft_cols_fwd<T>(c, c->L);
+    launch_degrid_dual_v<T>(c, v);
+    launch_bins_and_roots<T>(c);
+    launch_dual_apply_v<T>(c, v);
+    if (adj) adj_from_grid_order<T>(c, v, (const T*)c->d.vis_theta, adj);
+}
+
+template <typename T>
+static void dual_nuclear_impl(hs_ctx* c, T* P, const T* Xt) {
+    launch_gram<T>(c, P, Xt);
+    launch_eig(c, 0);
+    launch_backproject<T>(c, P, P, Xt);
+}
+
+template <typename T>
+static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu, T* At_sum) {
+    launch_psi_adj<T>(c, Xt, nullptr);
+    launch_l21_dual<T>(c, A, Xt, (const T*)c->d.coef, wbar, mu * (double)c->D, 0);
+    if (At_sum) launch_psi_sum<T>(c, A + (size_t)c->L * c->N, A, At_sum);
+}
+
+// One iteration of Algorithm 2 on the context state.
+template <typename T>
+static void pd_iter_impl(hs_ctx* c) {
+    Dev& d = c->d;
+    T* Xt = (T*)d.Xt;
+    // data fidelity (Steps 3-4, 9-12) -> img0 = Re Phi^dag v
+    dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0);
+    // low rankness (Step 5)
+    dual_nuclear_impl<T>(c, (T*)d.P, Xt);
+    // joint average sparsity (Steps 6-8) -> img1 = sum_d Psi_d A_d
+    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
+    // primal (Steps 20-23)
+    launch_primal<T>(c, (const T*)d.img1, (const T*)d.img0);
+}
+
+template <typename T>
+static hs_status op_norm_impl(hs_ctx* c, int max_it, double tol, const T* x0, double* out, double* per, int* iters) {
+    Dev& d = c->d;
+    const int64_t LN = (int64_t)c->L * c->N;
+    T* x = (T*)d.img1;
+    hipMemcpyAsync(x, x0, LN * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+    launch_chan_norms<T>(c, x, d.chan_nrm);
+    launch_chan_scale<T>(c, x, d.chan_nrm);
+    std::vector<double> lam(c->L, 0.0), prev(c->L, 0.0);
+    int it = 0;
+    for (it = 1; it <= max_it; ++it) {
+        launch_fft_rows_fwd<T>(c, x, c->L);
+        launch_fft_cols_fwd<T>(c, c->L);
+        launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)d.vis_u);
+        adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, x);
+        launch_chan_norms<T>(c, x, d.chan_nrm);
+        hs_status s = hip_check(c, hipMemcpyAsync(lam.data(), d.chan_nrm, c->L * 8, hipMemcpyDeviceToHost, c->stream),
+                                "hs_op_norm");
+        if (s) return s;
+        s = hip_check(c, hipStreamSynchronize(c->stream), "hs_op_norm");
+        if (s) return s;
+        launch_chan_scale<T>(c, x, d.chan_nrm);
+        bool done = true;
+        for (int l = 0; l < c->L; ++l)
+            if (!(lam[l] == 0.0 || std::fabs(lam[l] - prev[l]) <= tol * lam[l])) done = false;
+        prev = lam;
+        if (done) break;
+    }
+    if (it > max_it) it = max_it;
+    double mx = 0.0;
+    for (int l = 0; l < c->L; ++l) mx = std::max(mx, lam[l]);
+    *out = mx;
+    if (per) std::copy(lam.begin(), lam.end(), per);
+    if (iters) *iters = it;
+    return HS_OK;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+#define HS_TRY_BEGIN try {
+#define HS_TRY_END(c)                                                           \
+    }                                                                           \
+    catch (const std::exception& ex) {                                          \
+        return fail(c, HS_ERR_INVALID_ARG, std::string("exception: ") + ex.what()); \
+    }                                                                           \
+    catch (...) {                                                               \
+        return fail(c, HS_ERR_INVALID_ARG, "unknown exception");                \
+    }
+
+#define HS_DISPATCH(c, CALL)                          \
+    do {                                              \
+        if ((c)->dtype == HS_F32) { typedef float T; CALL; } \
+        else { typedef double T; CALL; }              \
+    } while (0)
+
+static hs_status ready(hs_ctx* c) {
+    if (!c) return HS_ERR_INVALID_ARG;
+    if (!c->planned) return fail(c, HS_ERR_NOT_PLANNED, "call hs_plan first");
+    if (!c->bound) return fail(c, HS_ERR_NO_WORKSPACE, "call hs_bind_workspace first");
+    hipSetDevice(c->device);
+    return HS_OK;
+}
+
+static hs_status launched(hs_ctx* c, const char* what) {
+    return hip_check(c, hipGetLastError(), what);
+}
+
+extern "C" {
+
+const char* hs_status_string(hs_status s) {
+    switch (s) {
+        case HS_OK: return "ok";
+        case HS_ERR_INVALID_ARG: return "invalid argument";
+        case HS_ERR_SHAPE: return "unsupported shape";
+        case HS_ERR_DTYPE: return "unsupported dtype";
+        case HS_ERR_NOT_PLANNED: return "not planned";
+        case HS_ERR_NO_WORKSPACE: return "no workspace bound";
+        case HS_ERR_NONFINITE: return "non-finite input";
+        case HS_ERR_HIP: return "HIP runtime error";
+        case HS_ERR_NOT_CONVERGED: return "not converged";
+        default: return "unknown status";
+    }
+}
+
+const char* hs_last_error(const hs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
+    HS_TRY_BEGIN
+    if (!desc || !out) return fail(nullptr, HS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const hs_problem_desc& d = *desc;
+    if (d.dtype != HS_F32 && d.dtype != HS_F64) return fail(nullptr, HS_ERR_DTYPE, "dtype must be HS_F32 or HS_F64");
+    if (d.oversamp != 2) return fail(nullptr, HS_ERR_INVALID_ARG, "oversamp must be 2");
+    if (d.J != KB_J) return fail(nullptr, HS_ERR_INVALID_ARG, "J must be 8");
+    if (d.L < 1 || d.L > MAX_L) return fail(nullptr, HS_ERR_SHAPE, "L must be in 1..64");
+    if (d.levels < 1 || d.levels > 6 || d.n_db < 0 || d.n_db > MAX_DB)
+        return fail(nullptr, HS_ERR_INVALID_ARG, "levels in 1..6 and n_db in 0..8");
+    const int q = 1 << d.levels;
+    if (d.nx < 16 || d.ny < 16 || d.nx % q || d.ny % q || d.nx > 16384 || d.ny > 16384 || (d.nx & (d.nx - 1)) ||
+        (d.ny & (d.ny - 1)))
+        return fail(nullptr, HS_ERR_SHAPE, "nx, ny must be powers of two in 16..16384 and multiples of 2^levels");
+    if (2 * d.nx > 4096 * 8 || 2 * d.ny > 4096 * 8) return fail(nullptr, HS_ERR_SHAPE, "grid too large");
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || d.device < 0 || d.device >= dev_count)
+        return fail(nullptr, HS_ERR_HIP, "no such HIP device");
+    hs_ctx* c = new hs_ctx();
+    c->desc = d;
+    c->nx = d.nx;
+    c->ny = d.ny;
+    c->L = d.L;
+    c->Kx = 2 * d.nx;
+    c->Ky = 2 * d.ny;
+    c->N = (int64_t)d.nx * d.ny;
+    c->n_db = d.n_db;
+    c->D = 1 + d.n_db;
+    c->levels = d.levels;
+    c->dtype = d.dtype;
+    c->rsz = d.dtype == HS_F32 ? 4 : 8;
+    c->stream = (hipStream_t)d.stream;
+    c->device = d.device;
+    c->ch.resize(d.L);
+    c->w_host.assign(MAX_L, 1.0);
+    c->k2 = 1.0 / c->D;
+    *out = c;
+    return HS_OK;
+    HS_TRY_END(nullptr)
+}
+
+hs_status hs_destroy(hs_ctx* c) {
+    if (!c) return HS_ERR_INVALID_ARG;
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    delete c;
+    return HS_OK;
+}
+
+hs_status hs_set_channel(hs_ctx* c, int32_t l, int64_t M, int32_t nblocks, const int64_t* bp, const double* uv,
+                         const double* y_raw, const double* theta, const double* precond, const double* eps) {
+    HS_TRY_BEGIN
+    if (!c) return HS_ERR_INVALID_ARG;
+    if (c->planned) return fail(c, HS_ERR_INVALID_ARG, "hs_set_channel after hs_plan (use hs_set_data)");
+    if (l < 0 || l >= c->L) return fail(c, HS_ERR_INVALID_ARG, "channel index out of range");
+    if (M < 0 || nblocks < 0 || (M > 0 && nblocks < 1) || !bp) return fail(c, HS_ERR_INVALID_ARG, "bad M / blocks");
+    if (M > 0 && (!uv || !y_raw || !theta)) return fail(c, HS_ERR_INVALID_ARG, "null data pointer");
+    if (nblocks > 0 && !eps) return fail(c, HS_ERR_INVALID_ARG, "null eps");
+    if (nblocks > 0 && (bp[0] != 0 || bp[nblocks] != M)) return fail(c, HS_ERR_INVALID_ARG, "block_ptr must span 0..M");
+    for (int b = 0; b < nblocks; ++b)
+        if (bp[b + 1] < bp[b]) return fail(c, HS_ERR_INVALID_ARG, "block_ptr not monotone");
+    for (int64_t m = 0; m < 2 * M; ++m)
+        if (!std::isfinite(uv[m]) || !std::isfinite(y_raw[m])) return fail(c, HS_ERR_NONFINITE, "non-finite uv or y");
+    for (int64_t m = 0; m < M; ++m) {
+        if (!std::isfinite(theta[m]) || !(theta[m] > 0)) return fail(c, HS_ERR_NONFINITE, "theta must be finite and > 0");
+        if (precond && (!std::isfinite(precond[m]) || !(precond[m] > 0)))
+            return fail(c, HS_ERR_NONFINITE, "preconditioner must be finite and > 0");
+        const double tx = std::fabs(uv[2 * m]) * c->Kx, ty = std::fabs(uv[2 * m + 1]) * c->Ky;
+        if (tx > 1e9 || ty > 1e9) return fail(c, HS_ERR_INVALID_ARG, "|u| too large");
+    }
+    for (int b = 0; b < nblocks; ++b)
+        if (!std::isfinite(eps[b]) || eps[b] < 0) return fail(c, HS_ERR_NONFINITE, "eps must be finite and >= 0");
+    Channel& ch = c->ch[l];
+    ch.M = M;
+    ch.nb = nblocks;
+    ch.bp.assign(bp, bp + nblocks + 1);
+    ch.uv.assign(uv, uv + 2 * M);
+    ch.y.assign(y_raw, y_raw + 2 * M);
+    ch.theta.assign(theta, theta + M);
+    ch.has_u = precond != nullptr;
+    if (precond) ch.u.assign(precond, precond + M);
+    else ch.u.clear();
+    ch.eps.assign(eps, eps + nblocks);
+    ch.set = true;
+    return HS_OK;
+    HS_TRY_END(c)
+}
+
+hs_status hs_set_data(hs_ctx* c, int32_t l, const double* y_raw, const double* theta, const double* eps) {
+    HS_TRY_BEGIN
+    hs_status s = ready(c);
+    if (s) return s;
+    if (l < 0 || l >= c->L) return fail(c, HS_ERR_INVALID_ARG, "channel index out of range");
+    Channel& ch = c->ch[l];
+    for (int64_t m = 0; m < ch.M; ++m) {
+        if (!std::isfinite(y_raw[2 * m]) || !std::isfinite(y_raw[2 * m + 1])) return fail(c, HS_ERR_NONFINITE, "y");
+        if (!std::isfinite(theta[m]) || !(theta[m] > 0)) return fail(c, HS_ERR_NONFINITE, "theta");
+    }
+    for (int b = 0; b < ch.nb; ++b)
+        if (!std::isfinite(eps[b]) || eps[b] < 0) return fail(c, HS_ERR_NONFINITE, "eps");
+    ch.y.assign(y_raw, y_raw + 2 * ch.M);
+    ch.theta.assign(theta, theta + ch.M);
+    ch.eps.assign(eps, eps + ch.nb);
+    const int64_t base = c->chan_off[l];
+    for (int64_t k = 0; k < ch.M; ++k) {
+        const int64_t g = base + k;
+        const int64_t m = c->h_perm[g] - base;
+        c->h_theta[g] = ch.theta[m];
+        c->h_y[2 * g] = ch.theta[m] * ch.y[2 * m];
+        c->h_y[2 * g + 1] = ch.theta[m] * ch.y[2 * m + 1];
+    }
+    for (int b = 0; b < ch.nb; ++b) c->h_blk_eps[c->blk_off[l] + b] = ch.eps[b];
+    hipStreamSynchronize(c->stream);
+    const size_t n = (size_t)ch.M;
+    if (c->dtype == HS_F32) {
+        std::vector<float> th(c->h_theta.begin() + base, c->h_theta.begin() + base + n);
+        std::vector<float> yy(c->h_y.begin() + 2 * base, c->h_y.begin() + 2 * (base + n));
+        hipMemcpy((float*)c->d.vis_theta + base, th.data(), n * 4, hipMemcpyHostToDevice);
+        hipMemcpy((float*)c->d.vis_y + 2 * base, yy.data(), 2 * n * 4, hipMemcpyHostToDevice);
+    } else {
+        hipMemcpy((double*)c->d.vis_theta + base, c->h_theta.data() + base, n * 8, hipMemcpyHostToDevice);
+        hipMemcpy((double*)c->d.vis_y + 2 * base, c->h_y.data() + 2 * base, 2 * n * 8, hipMemcpyHostToDevice);
+    }
+    hipMemcpy(c->d.blk_eps + c->blk_off[l], ch.eps.data(), ch.nb * 8, hipMemcpyHostToDevice);
+    return launched(c, "hs_set_data");
+    HS_TRY_END(c)
+}
+
+hs_status hs_plan(hs_ctx* c, size_t* ws) {
+    HS_TRY_BEGIN
+    if (!c || !ws) return HS_ERR_INVALID_ARG;
+    if (c->planned) {
+        *ws = c->ws_bytes;
+        return HS_OK;
+    }
+    hs_status s = build_plan(c);
+    if (s) return s;
+    c->ws_bytes = carve(c, nullptr);
+    c->planned = true;
+    *ws = c->ws_bytes;
+    return HS_OK;
+    HS_TRY_END(c)
+}
+
+hs_status hs_bind_workspace(hs_ctx* c, void* dev, size_t bytes) {
+    HS_TRY_BEGIN
+    if (!c || !dev) return HS_ERR_INVALID_ARG;
+    if (!c->planned) return fail(c, HS_ERR_NOT_PLANNED, "call hs_plan first");
+    if (bytes < c->ws_bytes) return fail(c, HS_ERR_NO_WORKSPACE, "workspace too small");
+    if (((uintptr_t)dev) & 255) return fail(c, HS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    hs_status s = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    if (s) return s;
+    fft_init_attrs();
+    c->ws = dev;
+    carve(c, (char*)dev);
+    if (c->dtype == HS_F32) s = bind_impl<float>(c);
+    else s = bind_impl<double>(c);
+    if (s) return s;
+    c->bound = true;
+    c->graph_valid = false;
+    return HS_OK;
+    HS_TRY_END(c)
+}
+
+hs_status hs_get_info(const hs_ctx* c, hs_info* info) {
+    if (!c || !info) return HS_ERR_INVALID_ARG;
+    info->n_vis = c->Mtot;
+    info->n_blocks = c->nblk;
+    info->n_bins = c->nbins;
+    info->n_runs = c->nruns;
+    info->n_degrid_units = (int64_t)c->dunits.size();
+    info->n_grid_units = (int64_t)c->gunits.size();
+    info->tile = c->T;
+    info->kb_terms = c->kb_terms;
+    info->workspace_bytes = c->ws_bytes;
+    return HS_OK;
+}
+
+hs_status hs_phi(hs_ctx* c, const void* X, void* Y) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!X || !Y) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    HS_DISPATCH(c, phi_impl<T>(c, (const T*)X, (cplx<T>*)Y));
+    return launched(c, "hs_phi");
+}
+
+hs_status hs_phi_adj(hs_ctx* c, const void* Y, void* X) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!X || !Y) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    HS_DISPATCH(c, phi_adj_impl<T>(c, (const cplx<T>*)Y, (T*)X));
+    return launched(c, "hs_phi_adj");
+}
+
+hs_status hs_psi_adj(hs_ctx* c, const void* X, void* C) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!X || !C) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    const size_t LN = (size_t)c->L * c->N;
+    hipMemcpyAsync(C, X, LN * c->rsz, hipMemcpyDeviceToDevice, c->stream);
+    HS_DISPATCH(c, launch_psi_adj<T>(c, (const T*)X, (T*)C + LN));
+    return launched(c, "hs_psi_adj");
+}
+
+hs_status hs_psi(hs_ctx* c, const void* C, void* X) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!X || !C) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    const size_t LN = (size_t)c->L * c->N;
+    HS_DISPATCH(c, launch_psi_sum<T>(c, (const T*)C + LN, (const T*)C, (T*)X));
+    return launched(c, "hs_psi");
+}
+
+hs_status hs_prox_l21(hs_ctx* c, void* A, const void* wbar, double t) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!A || !(t >= 0)) return fail(c, HS_ERR_INVALID_ARG, "bad argument");
+    HS_DISPATCH(c, launch_l21_dual<T>(c, (T*)A, nullptr, nullptr, (const T*)wbar, t, 1));
+    return launched(c, "hs_prox_l21");
+}
+
+hs_status hs_dual_l21(hs_ctx* c, void* A, const void* Xt, const void* wbar, double mu, void* At_sum) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!A || !Xt || !(mu >= 0)) return fail(c, HS_ERR_INVALID_ARG, "bad argument");
+    HS_DISPATCH(c, dual_l21_impl<T>(c, (T*)A, (const T*)Xt, (const T*)wbar, mu, (T*)At_sum));
+    return launched(c, "hs_dual_l21");
+}
+
+static hs_status upload_w(hs_ctx* c, const double* w) {
+    std::vector<double> wv(MAX_L, 1.0);
+    if (w)
+        for (int l = 0; l < c->L; ++l) {
+            if (!std::isfinite(w[l]) || w[l] < 0) return fail(c, HS_ERR_NONFINITE, "nuclear weights must be >= 0");
+            wv[l] = w[l];
+        }
+    c->w_host = wv;
+    hs_status s = hip_check(c, hipStreamSynchronize(c->stream), "upload w");
+    if (s) return s;
+    return hip_check(c, hipMemcpy(c->d.w_nuc, c->w_host.data(), MAX_L * 8, hipMemcpyHostToDevice), "upload w");
+}
+
+hs_status hs_prox_nuclear(hs_ctx* c, void* X, const double* w, double* sigma_out) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!X) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    std::vector<double> saved = c->w_host;
+    s = upload_w(c, w);
+    if (s) return s;
+    HS_DISPATCH(c, { launch_gram<T>(c, (const T*)X, nullptr); launch_eig(c, 1);
+                     launch_backproject<T>(c, (T*)X, (const T*)X, nullptr); });
+    s = launched(c, "hs_prox_nuclear");
+    if (s) return s;
+    std::vector<double> sg(MAX_L);
+    s = hip_check(c, hipMemcpyAsync(sg.data(), c->d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream), "sigma");
+    if (s) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_prox_nuclear");
+    if (s) return s;
+    if (sigma_out) std::copy(sg.begin(), sg.begin() + c->L, sigma_out);
+    return upload_w(c, saved.data());
+}
+
+hs_status hs_dual_nuclear(hs_ctx* c, void* P, const void* Xt, const double* w) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!P || !Xt) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    std::vector<double> saved = c->w_host;
+    s = upload_w(c, w);
+    if (s) return s;
+    HS_DISPATCH(c, dual_nuclear_impl<T>(c, (T*)P, (const T*)Xt));
+    s = launched(c, "hs_dual_nuclear");
+    if (s) return s;
+    return upload_w(c, saved.data());
+}
+
+hs_status hs_dual_data(hs_ctx* c, void* v, const void* Xt, void* adj_out) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!v || !Xt) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    HS_DISPATCH(c, {
+        cplx<T>* vw = (cplx<T>*)c->d.vwork;
+        launch_gather_user<T>(c, (const cplx<T>*)v, vw, false);
+        dual_data_impl<T>(c, vw, (const T*)Xt, (T*)adj_out);
+        launch_scatter_user<T>(c, vw, (cplx<T>*)v);
+    });
+    return launched(c, "hs_dual_data");
+}
+
+hs_status hs_proj_ellipsoid(hs_ctx* c, int32_t l, int32_t b, void* z) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!z || l < 0 || l >= c->L || b < 0 || b >= c->ch[l].nb) return fail(c, HS_ERR_INVALID_ARG, "bad block");
+    const int64_t pos0 = c->chan_off[l] + c->ch[l].bp[b];
+    const int64_t Mb = c->ch[l].bp[b + 1] - c->ch[l].bp[b];
+    if (Mb == 0) return HS_OK;
+    HS_DISPATCH(c, launch_proj_block<T>(c, pos0, Mb, c->blk_off[l] + b, (cplx<T>*)z));
+    s = launched(c, "hs_proj_ellipsoid");
+    if (s) return s;
+    return hip_check(c, hipStreamSynchronize(c->stream), "hs_proj_ellipsoid");
+}
+
+hs_status hs_op_norm(hs_ctx* c, int32_t which, int32_t max_it, double tol, const void* x0, double* out,
+                     double* per_channel, int32_t* iters) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!out) return fail(c, HS_ERR_INVALID_ARG, "null out");
+    if (which == HS_NORM_PSI) {
+        *out = (double)c->D;
+        if (iters) *iters = 0;
+        return HS_OK;
+    }
+    if (which != HS_NORM_PHI_PRECOND || !x0 || max_it < 1 || !(tol >= 0))
+        return fail(c, HS_ERR_INVALID_ARG, "bad op_norm arguments");
+    c->graph_valid = false;  // scratch buffers are reused
+    if (c->dtype == HS_F32) s = op_norm_impl<float>(c, max_it, tol, (const float*)x0, out, per_channel, iters);
+    else s = op_norm_impl<double>(c, max_it, tol, (const double*)x0, out, per_channel, iters);
+    if (s) return s;
+    return launched(c, "hs_op_norm");
+}
+
+hs_status hs_pd_init(hs_ctx* c, const hs_pd_params* p) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!p) return fail(c, HS_ERR_INVALID_ARG, "null params");
+    if (!(p->mu >= 0) || !(p->tau > 0) || !(p->kappa3 > 0))
+        return fail(c, HS_ERR_INVALID_ARG, "need mu >= 0, tau > 0, kappa3 > 0");
+    c->mu = p->mu;
+    c->tau = p->tau;
+    c->k1 = p->kappa1 > 0 ? p->kappa1 : 1.0;
+    c->k2 = p->kappa2 > 0 ? p->kappa2 : 1.0 / c->D;
+    c->k3 = p->kappa3;
+    c->adaptive = p->adaptive_eps != 0;
+    c->lam1 = p->lam1 > 0 ? p->lam1 : 5e-4;
+    c->lam2 = p->lam2 > 0 ? p->lam2 : 0.01;
+    c->lam3 = p->lam3 > 0 ? p->lam3 : 0.618;
+    c->vartheta_bar = p->vartheta_bar > 0 ? p->vartheta_bar : 100;
+    s = upload_w(c, p->w);
+    if (s) return s;
+    if (p->wbar) hipMemcpyAsync(c->d.wbar, p->wbar, (size_t)c->D * c->N * c->rsz, hipMemcpyDeviceToDevice, c->stream);
+    else HS_DISPATCH(c, launch_fill<T>(c->stream, (T*)c->d.wbar, T(1), (int64_t)c->D * c->N));
+    c->pd_ready = true;
+    c->graph_valid = false;
+    return launched(c, "hs_pd_init");
+}
+
+hs_status hs_pd_set_state(hs_ctx* c, const hs_state_ptrs* st) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!st) return fail(c, HS_ERR_INVALID_ARG, "null state");
+    const size_t LN = (size_t)c->L * c->N * c->rsz;
+    if (st->X) hipMemcpyAsync(c->d.X, st->X, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->Xt) hipMemcpyAsync(c->d.Xt, st->Xt, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->P) hipMemcpyAsync(c->d.P, st->P, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->A) hipMemcpyAsync(c->d.A, st->A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
+    if (st->v) HS_DISPATCH(c, launch_gather_user<T>(c, (const cplx<T>*)st->v, (cplx<T>*)c->d.v, false));
+    return launched(c, "hs_pd_set_state");
+}
+
+hs_status hs_pd_get_state(hs_ctx* c, const hs_state_ptrs* st) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!st) return fail(c, HS_ERR_INVALID_ARG, "null state");
+    const size_t LN = (size_t)c->L * c->N * c->rsz;
+    if (st->X) hipMemcpyAsync(st->X, c->d.X, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->Xt) hipMemcpyAsync(st->Xt, c->d.Xt, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->P) hipMemcpyAsync(st->P, c->d.P, LN, hipMemcpyDeviceToDevice, c->stream);
+    if (st->A) hipMemcpyAsync(st->A, c->d.A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
+    if (st->v) HS_DISPATCH(c, launch_scatter_user<T>(c, (const cplx<T>*)c->d.v, (cplx<T>*)st->v));
+    return launched(c, "hs_pd_get_state");
+}
+
+static hs_status pd_capture(hs_ctx* c) {
+    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+    hs_status s = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
+    if (s) return s;
+    HS_DISPATCH(c, pd_iter_impl<T>(c));
+    hipError_t le = hipGetLastError();
+    s = hip_check(c, hipStreamEndCapture(c->stream, &c->graph), "end capture");
+    if (s) return s;
+    if (le != hipSuccess) return hip_check(c, le, "launch during capture");
+    s = hip_check(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate");
+    if (s) return s;
+    c->graph_valid = true;
+    return HS_OK;
+}
+
+hs_status hs_pd_iterate(hs_ctx* c, int32_t n) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
+    if (n < 0) return fail(c, HS_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return HS_OK;
+    if (c->stream == nullptr) {
+        // the legacy default stream cannot be captured: run eagerly
+        for (int i = 0; i < n; ++i) HS_DISPATCH(c, pd_iter_impl<T>(c));
+        c->t_iter += n;
+        return launched(c, "hs_pd_iterate");
+    }
+    if (!c->graph_valid) {
+        s = pd_capture(c);
+        if (s) return s;
+    }
+    for (int i = 0; i < n; ++i) {
+        s = hip_check(c, hipGraphLaunch(c->gexec, c->stream), "hipGraphLaunch");
+        if (s) return s;
+    }
+    c->t_iter += n;
+    return HS_OK;
+}
+
+hs_status hs_pd_stats(hs_ctx* c, double* beta, double* rho, double* eps) {
+    hs_status s = ready(c);
+    if (s) return s;
+    double sc[4];
+    s = hip_check(c, hipMemcpyAsync(sc, c->d.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream), "stats");
+    if (s) return s;
+    std::vector<double> r2(c->nblk), ep(c->nblk);
+    if (c->nblk) {
+        hipMemcpyAsync(r2.data(), c->d.blk_rho2, c->nblk * 8, hipMemcpyDeviceToHost, c->stream);
+        hipMemcpyAsync(ep.data(), c->d.blk_eps, c->nblk * 8, hipMemcpyDeviceToHost, c->stream);
+    }
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_pd_stats");
+    if (s) return s;
+    if (beta) *beta = sc[0];
+    if (rho)
+        for (int64_t b = 0; b < c->nblk; ++b) rho[b] = std::sqrt(r2[b]);
+    if (eps) std::copy(ep.begin(), ep.end(), eps);
+    return HS_OK;
+}
+
+hs_status hs_solve(hs_ctx* c, const hs_solve_params* p, void* X_out, hs_report* rep) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!p || p->iters_per_reweight < 1 || p->n_reweights < 0 || !(p->gamma_factor > 0))
+        return fail(c, HS_ERR_INVALID_ARG, "bad solve parameters");
+    if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
+    double gamma = 1.0, gamma_bar = 1.0, beta = 0.0;
+    int64_t total = 0;
+    const int check = p->check_every > 0 ? p->check_every : p->iters_per_reweight;
+    int k = 0;
+    for (k = 0; k <= p->n_reweights; ++k) {
+        int done = 0;
+        while (done < p->iters_per_reweight) {
+            const int n = std::min(check, p->iters_per_reweight - done);
+            s = hs_pd_iterate(c, n);
+            if (s) return s;
+            done += n;
+            total += n;
+            s = hs_pd_stats(c, &beta, nullptr, nullptr);
+            if (s) return s;
+            if (p->beta_tol > 0 && beta < p->beta_tol) break;
+        }
+        if (k == p->n_reweights) break;
+        // eq:weights-l21 and eq:weights-n from the current estimate
+        HS_DISPATCH(c, {
+            launch_psi_adj<T>(c, (const T*)c->d.X, nullptr);
+            launch_reweight_l21<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
+            launch_gram<T>(c, (const T*)c->d.X, nullptr);
+            launch_eig(c, 0);
+        });
+        s = launched(c, "hs_solve reweight");
+        if (s) return s;
+        std::vector<double> sg(MAX_L);
+        hipMemcpyAsync(sg.data(), c->d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
+        s = hip_check(c, hipStreamSynchronize(c->stream), "hs_solve");
+        if (s) return s;
+        std::vector<double> w(c->L);
+        for (int l = 0; l < c->L; ++l) w[l] = gamma / (gamma + sg[l]);
+        s = upload_w(c, w.data());
+        if (s) return s;
+        gamma *= p->gamma_factor;
+        gamma_bar *= p->gamma_factor;
+    }
+    if (X_out) hipMemcpyAsync(X_out, c->d.X, (size_t)c->L * c->N * c->rsz, hipMemcpyDeviceToDevice, c->stream);
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_solve");
+    if (s) return s;
+    if (rep) {
+        rep->iterations = total;
+        rep->reweights = std::min(k, p->n_reweights);
+        rep->final_beta = beta;
+    }
+    return HS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Internal declarations of the HyperSARA gfx950 library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hypersara.h"
+
+namespace hs {
+
+constexpr int KB_J = 8;             // kernel support per dimension (taps)
+constexpr int KB_MAX_TERMS = 40;    // power-series terms of the kernel (upper bound)
+constexpr int MAX_L = 64;           // channels (Gram matrix edge)
+constexpr int DEG_THREADS = 256;    // degridding workgroup = one batch of visibilities
+constexpr int DEG_BATCHES = 4;      // batches per degridding work unit
+constexpr int GRID_SPLIT = 2048;    // pull elements per gridding work unit
+constexpr int N_GRANGES = 13;       // visibility ranges feeding one tile core
+constexpr int MAX_DB = 8;
+constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
+
+// One degridding work unit: `count` (<= DEG_THREADS*DEG_BATCHES) visibilities of
+// one tile of channel l starting at global position `start`.  Its segmented
+// reduction runs are numbered from run_base.
+struct DegridUnit {
+    int32_t l, tile, start, count;
+    int32_t run_base, pad0, pad1, pad2;
+};
+
+// One gridding work unit: part `split` of `nsplit` of the visibilities that
+// reach the core of `tile` of channel l.  nsplit > 1 writes a partial tile to
+// slot partial + split; nsplit == 1 writes the grid directly.
+struct GridUnit {
+    int32_t l, tile, split, nsplit;
+    int32_t partial, pad0, pad1, pad2;
+};
+
+// A tile whose gridding was split: the partials are summed in order.
+struct SplitTile {
+    int32_t l, tile, partial, nsplit;
+};
+
+template <typename T>
+struct KBPoly {                 // phi(d) = sum_k c[k] w^k, w = 1 - (2d/J)^2
+    T c[KB_MAX_TERMS];
+    int n;
+};
+
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+// Device pointers carved from the caller's workspace.
+struct Dev {
+    // per visibility, tile-major order
+    int32_t* vis_cell = nullptr;   // (cy << 16) | cx
+    void* vis_frac = nullptr;      // [M][2] real, t - floor(t)
+    void* vis_y = nullptr;         // [M] complex, theta * y_raw
+    void* vis_theta = nullptr;     // [M] real
+    void* vis_u = nullptr;         // [M] real, preconditioner
+    int32_t* vis_bin = nullptr;    // [M] global bin
+    int32_t* vis_perm = nullptr;   // [M] caller's global index
+    int32_t* vis_pos = nullptr;    // [M] caller's global index -> position
+    void* v = nullptr;             // [M] complex, PD dual
+    void* vwork = nullptr;         // [M] complex scratch
+    // work lists
+    DegridUnit* dunits = nullptr;
+    GridUnit* gunits = nullptr;
+    SplitTile* splits = nullptr;
+    int32_t* granges = nullptr;    // [L*ntiles][13][2]
+    void* gpartial = nullptr;      // [npartial][T*T] complex
+    // bins / blocks
+    double* bin_u = nullptr;       // [nbins]
+    int32_t* bin_block = nullptr;  // [nbins]
+    int32_t* blk_bin_ptr = nullptr;// [nblk+1]
+    double* blk_eps = nullptr;     // [nblk]
+    double* blk_lambda = nullptr;  // [nblk]
+    double* blk_rho2 = nullptr;    // [nblk] ||y - Phi Xt||^2 (Step 13)
+    int32_t* blk_vartheta = nullptr; // [nblk]
+    double* run_sum = nullptr;     // [nruns][2] (|d|^2, |y - Phi Xt|^2)
+    int32_t* bin_run_ptr = nullptr;// [nbins+1]
+    int32_t* bin_runs = nullptr;   // [nruns]
+    double* bin_S = nullptr;       // [nbins][2]
+    // FFT
+    void* grid = nullptr;          // [L][Ky][Kx] complex
+    void* H = nullptr;             // [L][ny][Kx] complex
+    void* tw_x = nullptr;          // [Kx] complex exp(-2 pi i k/Kx)
+    void* tw_y = nullptr;          // [Ky]
+    void* sx = nullptr;            // [nx] real
+    void* sy = nullptr;            // [ny] real
+    // images
+    void* X = nullptr;
+    void* Xt = nullptr;
+    void* P = nullptr;
+    void* img0 = nullptr;
+    void* img1 = nullptr;
+    void* A = nullptr;             // [D][L][N]
+    void* coef = nullptr;          // [n_db][L][N]
+    void* wtmp = nullptr;          // [n_db][L][N]
+    void* wbar = nullptr;          // [D][N]
+    void* filt = nullptr;          // [n_db][2][16] real (h, g)
+    // nuclear norm
+    double* gram_part = nullptr;   // [ngram][64][64]
+    double* gram = nullptr;        // [64][64]
+    double* eigV = nullptr;        // [64][64]
+    double* eig_sig = nullptr;     // [64]
+    double* w_nuc = nullptr;       // [64]
+    void* Wmat = nullptr;          // [64][64] real
+    // reductions
+    double* red_part = nullptr;    // [nred][4]
+    double* scal = nullptr;        // [64]: beta, iteration, ||dX||^2, ||X||^2
+    double* chan_nrm = nullptr;    // [64] per-channel norms
+};
+
+struct Channel {
+    bool set = false;
+    int64_t M = 0;
+    int32_t nb = 0;
+    std::vector<int64_t> bp;
+    std::vector<double> uv, y, theta, u, eps;
+    bool has_u = false;
+};
+
+enum { NRED = 512, NGRAM = 512 };
+
+}  // namespace hs
+
+struct hs_ctx {
+    hs_problem_desc desc{};
+    int nx = 0, ny = 0, L = 0, Kx = 0, Ky = 0, D = 0, n_db = 0, levels = 0;
+    int64_t N = 0;
+    int dtype = HS_F32;
+    size_t rsz = 4;  // sizeof(real)
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    std::vector<hs::Channel> ch;
+    // plan
+    bool planned = false, bound = false;
+    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0;
+    int64_t Mtot = 0;
+    std::vector<int64_t> chan_off;     // [L+1]
+    std::vector<int32_t> blk_off;      // [L+1]
+    int64_t nblk = 0, nbins = 0, nruns = 0, npartial = 0;
+    std::vector<hs::DegridUnit> dunits;
+    std::vector<hs::GridUnit> gunits;
+    std::vector<hs::SplitTile> splits;
+    int kb_terms = 0;
+    std::vector<double> kb_c;          // power-series coefficients
+    // host staging of the plan (uploaded at bind)
+    std::vector<int32_t> h_cell, h_bin, h_perm, h_granges, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_bin_runs;
+    std::vector<double> h_frac, h_y, h_theta, h_u, h_bin_u, h_blk_eps;
+    std::vector<int64_t> h_pos_of;     // caller global index -> grid position
+    size_t ws_bytes = 0;
+    void* ws = nullptr;
+    hs::Dev d;
+    // PD
+    bool pd_ready = false;
+    double mu = 0, tau = 0.33, k1 = 1, k2 = 0, k3 = 0;
+    bool adaptive = false;
+    double lam1 = 5e-4, lam2 = 0.01, lam3 = 0.618;
+    int vartheta_bar = 100;
+    int64_t t_iter = 0;
+    std::vector<double> w_host;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+};
+
+namespace hs {
+
+// ------------------------------------------------------------ host helpers
+hs_status fail(hs_ctx* c, hs_status s, const std::string& msg);
+hs_status hip_check(hs_ctx* c, hipError_t e, const char* what);
+void kb_series(int terms_for_bits, std::vector<double>& coef, double& beta);
+int kb_terms_needed(int mantissa_bits);
+double kb_ft(double xi);
+void daubechies_host(int K, double* h);
+
+// ------------------------------------------------------------ kernel launchers
+template <typename T> void launch_fill(hipStream_t s, T* p, T v, int64_t n);
+template <typename T> void launch_axpby(hipStream_t s, T* y, const T* x, T a, T b, int64_t n);   // y = a*x + b*y
+
+// NUFFT (k_nufft.hip)
+void fft_init_attrs();
+template <typename T> void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L);
+template <typename T> void launch_fft_cols_fwd(hs_ctx* c, int L);
+template <typename T> void launch_fft_cols_adj(hs_ctx* c, int L);
+template <typename T> void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L);
+template <typename T> void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user);
+template <typename T> void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult);
+template <typename T> void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v);
+template <typename T> void launch_bins_and_roots(hs_ctx* c);
+template <typename T> void launch_dual_apply_v(hs_ctx* c, cplx<T>* v);
+template <typename T> void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight);
+template <typename T> void launch_gather_user(hs_ctx* c, const cplx<T>* in_user, cplx<T>* out_grid, bool times_theta);
+template <typename T> void launch_scatter_user(hs_ctx* c, const cplx<T>* in_grid, cplx<T>* out_user);
+template <typename T> void launch_proj_block(hs_ctx* c, int64_t pos0_user, int64_t Mb, int blk, cplx<T>* z);
+
+// wavelets (k_wavelet.hip)
+template <typename T> void launch_psi_adj(hs_ctx* c, const T* X, T* Cout /*[n_db][L][N]; null -> coef*/);
+template <typename T> void launch_psi_sum(hs_ctx* c, const T* Cdb /*[n_db][L][N]*/, const T* C0, T* Xout);
+template <typename T> void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T* coef, const T* wbar, double thr, int mode);
+
+// nuclear (k_nuclear.hip)
+template <typename T> void launch_gram(hs_ctx* c, const T* P, const T* Xt);
+void launch_eig(hs_ctx* c, int mode);
+template <typename T> void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2);
+
+// primal and helpers (k_misc.hip)
+template <typename T> void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg);
+template <typename T> void launch_chan_norms(hs_ctx* c, const T* X, double* out);
+template <typename T> void launch_chan_scale(hs_ctx* c, T* X, const double* nrm);
+template <typename T> void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);
+
+}  // namespace hs

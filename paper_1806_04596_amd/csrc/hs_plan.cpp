@@ -1,0 +1,437 @@
+// Host-side plan: visibility order and bins, work lists, kernel/FFT/wavelet tables.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+// ------------------------------------------------------------------- kernel
+// Kaiser-Bessel kernel of width J = 8 on a 2x oversampled grid, shape
+// parameter from Beatty et al. (2005): beta = pi sqrt((J/s)^2 (s-1/2)^2 - 0.8).
+static long double kb_beta_ld() {
+    const long double J = KB_J, s = 2.0L;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    return pi * std::sqrt((J / s) * (J / s) * (s - 0.5L) * (s - 0.5L) - 0.8L);
+}
+
+// Taylor terms of I0(beta sqrt(w)) = sum_k (beta^2 w / 4)^k / (k!)^2.
+static void i0_terms(long double beta, std::vector<long double>& t, int n) {
+    t.resize(n);
+    const long double q = beta * beta / 4.0L;
+    t[0] = 1.0L;
+    for (int k = 1; k < n; ++k) t[k] = t[k - 1] * q / ((long double)k * (long double)k);
+}
+
+static long double i0_of_beta() {
+    std::vector<long double> t;
+    i0_terms(kb_beta_ld(), t, 200);
+    long double s = 0.0L;
+    for (int k = 199; k >= 0; --k) s += t[k];
+    return s;
+}
+
+int kb_terms_needed(int mantissa_bits) {
+    std::vector<long double> t;
+    i0_terms(kb_beta_ld(), t, 200);
+    const long double I0 = i0_of_beta();
+    const long double tol = std::ldexp(1.0L, -(mantissa_bits + 2));
+    for (int n = 1; n < KB_MAX_TERMS; ++n) {
+        long double tail = 0.0L;
+        for (int k = n; k < 200; ++k) tail += t[k];
+        if (tail / I0 <= tol) return n;
+    }
+    return KB_MAX_TERMS;
+}
+
+void kb_series(int terms, std::vector<double>& coef, double& beta) {
+    std::vector<long double> t;
+    const long double b = kb_beta_ld();
+    i0_terms(b, t, terms);
+    const long double I0 = i0_of_beta();
+    coef.resize(terms);
+    for (int k = 0; k < terms; ++k) coef[k] = (double)(t[k] / I0);
+    beta = (double)b;
+}
+
+// Continuous Fourier transform of the normalised kernel (closed form).
+double kb_ft(double xi) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double b = kb_beta_ld();
+    const long double z = b * b - (pi * KB_J * (long double)xi) * (pi * KB_J * (long double)xi);
+    long double v;
+    if (z > 0) {
+        const long double r = std::sqrt(z);
+        v = KB_J * std::sinh(r) / r;
+    } else if (z < 0) {
+        const long double r = std::sqrt(-z);
+        v = KB_J * std::sin(r) / r;
+    } else {
+        v = KB_J;
+    }
+    return (double)(v / i0_of_beta());
+}
+
+// ----------------------------------------------------------------- Daubechies
+// db-K low-pass by spectral factorisation: roots of P_K(y) = sum_{k<K} C(K-1+k,k) y^k
+// (Durand-Kerner in long double), z-roots inside the unit circle, then
+// sqrt(2) ((1+z^-1)/2)^K prod (1 - r z^-1)/(1 - r).
+void daubechies_host(int K, double* h) {
+    typedef std::complex<long double> cld;
+    std::vector<long double> a(K);  // coefficients, a[k] for y^k
+    for (int k = 0; k < K; ++k) {
+        long double c = 1.0L;
+        for (int i = 1; i <= k; ++i) c = c * (long double)(K - 1 + i) / (long double)i;
+        a[k] = c;
+    }
+    const int deg = K - 1;
+    std::vector<cld> roots(deg);
+    if (deg > 0) {
+        std::vector<cld> m(deg + 1);
+        for (int k = 0; k <= deg; ++k) m[k] = a[k] / a[deg];  // monic
+        for (int i = 0; i < deg; ++i) roots[i] = std::pow(cld(0.4L, 0.9L), (long double)i);
+        auto peval = [&](cld x) {
+            cld s = m[deg];
+            for (int k = deg - 1; k >= 0; --k) s = s * x + m[k];
+            return s;
+        };
+        for (int it = 0; it < 5000; ++it) {
+            long double delta = 0.0L;
+            for (int i = 0; i < deg; ++i) {
+                cld den = 1.0L;
+                for (int j = 0; j < deg; ++j)
+                    if (j != i) den *= (roots[i] - roots[j]);
+                const cld step = peval(roots[i]) / den;
+                roots[i] -= step;
+                delta = std::max(delta, std::abs(step));
+            }
+            if (delta < 1e-30L) break;
+        }
+    }
+    std::vector<cld> poly(1, cld(1.0L, 0.0L));
+    auto conv = [&](cld c0, cld c1) {
+        std::vector<cld> out(poly.size() + 1, cld(0, 0));
+        for (size_t i = 0; i < poly.size(); ++i) {
+            out[i] += poly[i] * c0;
+            out[i + 1] += poly[i] * c1;
+        }
+        poly.swap(out);
+    };
+    for (int k = 0; k < K; ++k) conv(cld(0.5L, 0), cld(0.5L, 0));
+    for (int i = 0; i < deg; ++i) {
+        const cld y = roots[i];
+        const cld b = 1.0L - 2.0L * y;
+        const cld s = std::sqrt(b * b - 1.0L);
+        cld z = b + s;
+        if (std::abs(z) >= 1.0L) z = b - s;
+        conv(cld(1.0L, 0) / (1.0L - z), -z / (1.0L - z));
+    }
+    const long double r2 = std::sqrt(2.0L);
+    for (int k = 0; k < 2 * K; ++k) h[k] = (double)(r2 * poly[k].real());
+}
+
+// ------------------------------------------------------------------- binning
+static inline int region_class(int o, int T) {
+    if (o < KB_J / 2 - 1) return 0;
+    if (o >= T - KB_J / 2) return 2;
+    return 1;
+}
+
+struct ChanOrder {
+    std::vector<int64_t> perm;        // position -> input index
+    std::vector<int64_t> region_ptr;  // [ntiles*9 + 1]
+    std::vector<int32_t> bin_local;   // per input index
+    std::vector<int32_t> cx, cy;      // per input index
+    std::vector<double> fx, fy;       // per input index
+    std::vector<double> class_val;    // distinct preconditioner values (ascending)
+    int C = 1;
+};
+
+static void order_channel(int64_t M, const double* uv, const double* u, int nb, const int64_t* bp, int nx, int ny,
+                          int T, ChanOrder& o) {
+    const int Kx = 2 * nx, Ky = 2 * ny;
+    const int tx = Kx / T, ty = Ky / T;
+    const int64_t ntr = (int64_t)tx * ty * 9;
+    o.cx.resize(M);
+    o.cy.resize(M);
+    o.fx.resize(M);
+    o.fy.resize(M);
+    std::vector<int64_t> key(M);
+    for (int64_t m = 0; m < M; ++m) {
+        const double tX = uv[2 * m] * (double)Kx;   // one correctly rounded product, as the definition
+        const double tY = uv[2 * m + 1] * (double)Ky;
+        const double flx = std::floor(tX), fly = std::floor(tY);
+        int64_t ix = (int64_t)flx % Kx, iy = (int64_t)fly % Ky;
+        if (ix < 0) ix += Kx;
+        if (iy < 0) iy += Ky;
+        o.cx[m] = (int32_t)ix;
+        o.cy[m] = (int32_t)iy;
+        o.fx[m] = tX - flx;
+        o.fy[m] = tY - fly;
+        const int64_t tile = (iy / T) * tx + (ix / T);
+        const int reg = 3 * region_class((int)(iy % T), T) + region_class((int)(ix % T), T);
+        key[m] = tile * 9 + reg;
+    }
+    // bins: block * C + rank of the preconditioner value
+    o.bin_local.assign(M, 0);
+    std::vector<int32_t> blk(M, 0);
+    for (int b = 0; b < nb; ++b)
+        for (int64_t m = bp[b]; m < bp[b + 1]; ++m) blk[m] = b;
+    if (u) {
+        std::vector<double> vals(u, u + M);
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        o.class_val = vals;
+        o.C = (int)vals.size();
+        for (int64_t m = 0; m < M; ++m) {
+            const int cls = (int)(std::lower_bound(vals.begin(), vals.end(), u[m]) - vals.begin());
+            o.bin_local[m] = blk[m] * o.C + cls;
+        }
+    } else {
+        o.class_val.assign(1, 1.0);
+        o.C = 1;
+        for (int64_t m = 0; m < M; ++m) o.bin_local[m] = blk[m];
+    }
+    if (M == 0) o.C = std::max(o.C, 1);
+    // stable counting sorts: by bin, then by (tile, region)
+    const int64_t nbins = (int64_t)std::max(nb, 1) * o.C;
+    std::vector<int64_t> cnt(std::max<int64_t>(nbins, ntr) + 1, 0);
+    std::vector<int64_t> tmp(M);
+    for (int64_t m = 0; m < M; ++m) cnt[o.bin_local[m] + 1]++;
+    for (int64_t k = 0; k < nbins; ++k) cnt[k + 1] += cnt[k];
+    for (int64_t m = 0; m < M; ++m) tmp[cnt[o.bin_local[m]]++] = m;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t m = 0; m < M; ++m) cnt[key[m] + 1]++;
+    for (int64_t k = 0; k < ntr; ++k) cnt[k + 1] += cnt[k];
+    o.region_ptr.assign(cnt.begin(), cnt.begin() + ntr + 1);
+    o.perm.resize(M);
+    for (int64_t k = 0; k < M; ++k) {
+        const int64_t m = tmp[k];
+        o.perm[cnt[key[m]]++] = m;
+    }
+}
+
+// The 13 source ranges feeding the core of tile (txi, tyi): own tile, and the
+// border regions of the 8 neighbours whose kernel footprints reach into it.
+static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_x, int tiles_y, int txi, int tyi,
+                        int32_t* out) {
+    int k = 0;
+    auto push = [&](int64_t s, int64_t e) {
+        out[2 * k] = (int32_t)(base + s);
+        out[2 * k + 1] = (int32_t)(base + e);
+        ++k;
+    };
+    for (int dy = -1; dy <= 1; ++dy) {
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int sx = (txi - dx + tiles_x) % tiles_x, sy = (tyi - dy + tiles_y) % tiles_y;
+            const int64_t t = (int64_t)sy * tiles_x + sx;
+            // source at target - (dx,dy): dx = +1 -> source right border (class 2)
+            const int rc = (dy == 1) ? 2 : 0;   // row class when dy != 0
+            const int cc = (dx == 1) ? 2 : 0;
+            if (dx == 0 && dy == 0) {
+                push(rp[t * 9], rp[t * 9 + 9]);
+            } else if (dx == 0) {
+                push(rp[t * 9 + 3 * rc], rp[t * 9 + 3 * rc + 3]);
+            } else if (dy == 0) {
+                for (int r = 0; r < 3; ++r) push(rp[t * 9 + 3 * r + cc], rp[t * 9 + 3 * r + cc + 1]);
+            } else {
+                push(rp[t * 9 + 3 * rc + cc], rp[t * 9 + 3 * rc + cc + 1]);
+            }
+        }
+    }
+}
+
+hs_status build_plan(hs_ctx* c) {
+    const int L = c->L;
+    for (int l = 0; l < L; ++l)
+        if (!c->ch[l].set) return fail(c, HS_ERR_INVALID_ARG, "hs_plan: channel " + std::to_string(l) + " not set");
+    int T = c->desc.tile;
+    if (T == 0) {
+        T = 32;
+        while (T > 8 && (c->Kx / T < 3 || c->Ky / T < 3 || c->Kx % T || c->Ky % T)) T /= 2;
+    }
+    if (T < 8 || T > 64 || (T & (T - 1)) || c->Kx % T || c->Ky % T || c->Kx / T < 3 || c->Ky / T < 3)
+        return fail(c, HS_ERR_SHAPE, "hs_plan: tile must be a power of two in 8..64 with >= 3 tiles per dimension");
+    c->T = T;
+    c->tiles_x = c->Kx / T;
+    c->tiles_y = c->Ky / T;
+    c->ntiles = c->tiles_x * c->tiles_y;
+    // offsets
+    c->chan_off.assign(L + 1, 0);
+    c->blk_off.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) {
+        c->chan_off[l + 1] = c->chan_off[l] + c->ch[l].M;
+        c->blk_off[l + 1] = c->blk_off[l] + c->ch[l].nb;
+    }
+    c->Mtot = c->chan_off[L];
+    c->nblk = c->blk_off[L];
+    if (c->Mtot >= (int64_t)INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: more than 2^31-1 visibilities");
+    const int64_t M = c->Mtot;
+    c->h_cell.assign(M, 0);
+    c->h_frac.assign(2 * M, 0.0);
+    c->h_y.assign(2 * M, 0.0);
+    c->h_theta.assign(M, 0.0);
+    c->h_u.assign(M, 0.0);
+    c->h_bin.assign(M, 0);
+    c->h_perm.assign(M, 0);
+    c->h_pos_of.assign(M, 0);
+    c->h_bin_u.clear();
+    c->h_bin_block.clear();
+    c->h_blk_bin_ptr.assign(1, 0);
+    c->h_blk_eps.clear();
+    c->dunits.clear();
+    c->gunits.clear();
+    c->splits.clear();
+    c->h_granges.assign((size_t)L * c->ntiles * 2 * N_GRANGES, 0);
+    std::vector<std::pair<int32_t, int32_t>> run_bin;  // (bin, run)
+    int64_t nruns = 0, npartial = 0;
+    int64_t bin_base = 0;
+    const int unit_max = DEG_THREADS * DEG_BATCHES;
+    for (int l = 0; l < L; ++l) {
+        const Channel& ch = c->ch[l];
+        ChanOrder o;
+        order_channel(ch.M, ch.uv.data(), ch.has_u ? ch.u.data() : nullptr, ch.nb, ch.bp.data(), c->nx, c->ny, T, o);
+        const int64_t base = c->chan_off[l];
+        for (int64_t k = 0; k < ch.M; ++k) {
+            const int64_t m = o.perm[k];
+            const int64_t g = base + k;
+            c->h_cell[g] = (o.cy[m] << 16) | o.cx[m];
+            c->h_frac[2 * g] = o.fx[m];
+            c->h_frac[2 * g + 1] = o.fy[m];
+            c->h_theta[g] = ch.theta[m];
+            c->h_y[2 * g] = ch.theta[m] * ch.y[2 * m];
+            c->h_y[2 * g + 1] = ch.theta[m] * ch.y[2 * m + 1];
+            c->h_u[g] = ch.has_u ? ch.u[m] : 1.0;
+            c->h_bin[g] = (int32_t)(bin_base + o.bin_local[m]);
+            c->h_perm[g] = (int32_t)(base + m);
+            c->h_pos_of[base + m] = g;
+        }
+        // bins and blocks
+        for (int b = 0; b < ch.nb; ++b) {
+            for (int cl = 0; cl < o.C; ++cl) {
+                c->h_bin_u.push_back(o.class_val[cl]);
+                c->h_bin_block.push_back(c->blk_off[l] + b);
+            }
+            c->h_blk_bin_ptr.push_back((int32_t)(bin_base + (int64_t)(b + 1) * o.C));
+            c->h_blk_eps.push_back(ch.eps[b]);
+        }
+        const int64_t nbins_l = (int64_t)ch.nb * o.C;
+        // degridding units and their runs
+        for (int t = 0; t < c->ntiles; ++t) {
+            const int64_t s = o.region_ptr[(int64_t)t * 9], e = o.region_ptr[(int64_t)t * 9 + 9];
+            for (int64_t p = s; p < e; p += unit_max) {
+                DegridUnit du{};
+                du.l = l;
+                du.tile = t;
+                du.start = (int32_t)(base + p);
+                du.count = (int32_t)std::min<int64_t>(unit_max, e - p);
+                du.run_base = (int32_t)nruns;
+                for (int64_t b0 = 0; b0 < du.count; b0 += DEG_THREADS) {
+                    const int64_t b1 = std::min<int64_t>(du.count, b0 + DEG_THREADS);
+                    int32_t prev = -1;
+                    for (int64_t i = b0; i < b1; ++i) {
+                        const int32_t bin = c->h_bin[base + p + i];
+                        if (i == b0 || bin != prev) {
+                            run_bin.push_back({bin, (int32_t)nruns});
+                            ++nruns;
+                        }
+                        prev = bin;
+                    }
+                }
+                c->dunits.push_back(du);
+            }
+        }
+        // gridding units (every tile gets at least one: empty tiles write zeros)
+        for (int tyi = 0; tyi < c->tiles_y; ++tyi) {
+            for (int txi = 0; txi < c->tiles_x; ++txi) {
+                const int t = tyi * c->tiles_x + txi;
+                int32_t* rg = &c->h_granges[((size_t)l * c->ntiles + t) * 2 * N_GRANGES];
+                tile_ranges(o.region_ptr, base, c->tiles_x, c->tiles_y, txi, tyi, rg);
+                int64_t E = 0;
+                for (int r = 0; r < N_GRANGES; ++r) E += rg[2 * r + 1] - rg[2 * r];
+                const int nsplit = (int)std::max<int64_t>(1, (E + GRID_SPLIT - 1) / GRID_SPLIT);
+                for (int sp = 0; sp < nsplit; ++sp) {
+                    GridUnit gu{};
+                    gu.l = l;
+                    gu.tile = t;
+                    gu.split = sp;
+                    gu.nsplit = nsplit;
+                    gu.partial = (int32_t)npartial;
+                    c->gunits.push_back(gu);
+                }
+                if (nsplit > 1) {
+                    c->splits.push_back(SplitTile{l, t, (int32_t)npartial, nsplit});
+                    npartial += nsplit;
+                }
+            }
+        }
+        bin_base += nbins_l;
+    }
+    c->nbins = bin_base;
+    c->nruns = nruns;
+    c->npartial = npartial;
+    // CSR: bin -> runs (increasing run index within a bin)
+    c->h_bin_run_ptr.assign(c->nbins + 1, 0);
+    for (auto& pr : run_bin) c->h_bin_run_ptr[pr.first + 1]++;
+    for (int64_t k = 0; k < c->nbins; ++k) c->h_bin_run_ptr[k + 1] += c->h_bin_run_ptr[k];
+    c->h_bin_runs.assign(nruns, 0);
+    {
+        std::vector<int32_t> fillp(c->h_bin_run_ptr.begin(), c->h_bin_run_ptr.end() - 1);
+        for (auto& pr : run_bin) c->h_bin_runs[fillp[pr.first]++] = pr.second;
+    }
+    // kernel series
+    c->kb_terms = kb_terms_needed(c->dtype == HS_F64 ? 53 : 24);
+    double beta;
+    kb_series(c->kb_terms, c->kb_c, beta);
+    return HS_OK;
+}
+
+}  // namespace hs
+
+// --------------------------------------------------------- host utilities (C ABI)
+extern "C" hs_status hs_density_precond(int64_t M, const double* uv, int32_t nx, int32_t ny, double* out) {
+    if (M < 0 || nx <= 0 || ny <= 0 || (M > 0 && (!uv || !out))) return HS_ERR_INVALID_ARG;
+    std::vector<int64_t> key(M);
+    for (int64_t m = 0; m < M; ++m) {
+        if (!std::isfinite(uv[2 * m]) || !std::isfinite(uv[2 * m + 1])) return HS_ERR_NONFINITE;
+        int64_t cx = (int64_t)std::floor(uv[2 * m] * (double)nx) % nx;
+        int64_t cy = (int64_t)std::floor(uv[2 * m + 1] * (double)ny) % ny;
+        if (cx < 0) cx += nx;
+        if (cy < 0) cy += ny;
+        key[m] = cy * nx + cx;
+    }
+    std::vector<int64_t> sorted(key);
+    std::sort(sorted.begin(), sorted.end());
+    for (int64_t m = 0; m < M; ++m) {
+        const auto r = std::equal_range(sorted.begin(), sorted.end(), key[m]);
+        out[m] = 1.0 / (double)(r.second - r.first);
+    }
+    return HS_OK;
+}
+
+extern "C" hs_status hs_visibility_order(int64_t M, const double* uv, const double* precond, int32_t nblocks,
+                                         const int64_t* block_ptr, int32_t nx, int32_t ny, int32_t tile,
+                                         int64_t* perm, int64_t* region_ptr) {
+    if (M < 0 || nx < 16 || ny < 16 || nblocks < 1 || !block_ptr || !perm || !region_ptr || (M > 0 && !uv))
+        return HS_ERR_INVALID_ARG;
+    const int Kx = 2 * nx, Ky = 2 * ny;
+    if (tile < 8 || tile > 64 || (tile & (tile - 1)) || Kx % tile || Ky % tile || Kx / tile < 3 || Ky / tile < 3)
+        return HS_ERR_SHAPE;
+    if (block_ptr[0] != 0 || block_ptr[nblocks] != M) return HS_ERR_INVALID_ARG;
+    for (int b = 0; b < nblocks; ++b)
+        if (block_ptr[b + 1] < block_ptr[b]) return HS_ERR_INVALID_ARG;
+    hs::ChanOrder o;
+    hs::order_channel(M, uv, precond, nblocks, block_ptr, nx, ny, tile, o);
+    std::copy(o.perm.begin(), o.perm.end(), perm);
+    std::copy(o.region_ptr.begin(), o.region_ptr.end(), region_ptr);
+    return HS_OK;
+}
+
+extern "C" hs_status hs_daubechies_filter(int32_t K, double* h) {
+    if (K < 1 || K > hs::MAX_DB || !h) return HS_ERR_INVALID_ARG;
+    hs::daubechies_host(K, h);
+    return HS_OK;
+}

@@ -1,0 +1,175 @@
+// Primal update (Algorithm 2, Steps 20-23), FP64 reductions, power-iteration
+// helpers (Sec. 3.4 step sizes) and the reweighting of Algorithm 1
+// (eq:weights-l21).
+#include "hs_internal.h"
+
+namespace hs {
+
+static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_axpby(T* y, const T* x, T a, T b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) s = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return s;
+}
+
+// Steps 20-23: G = k1 P + k2 At + k3 D; X <- max(X - tau G, 0); Xt <- 2X_new - X_old;
+// FP64 partial sums of ||X_new - X_old||^2 and ||X_new||^2 per block (fixed grid).
+template <typename T>
+__global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict__ Xt, const T* __restrict__ P,
+                                                const T* __restrict__ At, const T* __restrict__ D, T k1, T k2, T k3,
+                                                T tau, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[4];
+    double dd = 0.0, xx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T g = k1 * P[i] + k2 * At[i] + k3 * D[i];
+        const T xo = X[i];
+        T xn = xo - tau * g;
+        xn = xn > T(0) ? xn : T(0);
+        X[i] = xn;
+        Xt[i] = T(2) * xn - xo;
+        const double df = (double)xn - (double)xo;
+        dd += df * df;
+        xx += (double)xn * (double)xn;
+    }
+    dd = block_sum_256(dd, sh);
+    xx = block_sum_256(xx, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = dd;
+        part[2 * blockIdx.x + 1] = xx;
+    }
+}
+
+// beta (Step 23) into scal[0]; iteration counter scal[1] += 1.
+__global__ void k_finish_beta(const double* __restrict__ part, double* __restrict__ scal, int nparts) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double dd = 0.0, xx = 0.0;
+    for (int k = 0; k < nparts; ++k) {
+        dd += part[2 * k];
+        xx += part[2 * k + 1];
+    }
+    scal[0] = (xx > 0.0) ? sqrt(dd / xx) : 0.0;
+    scal[1] += 1.0;
+    scal[2] = dd;
+    scal[3] = xx;
+}
+
+// Per-channel sums of squares: part[l][chunk].
+template <typename T>
+__global__ __launch_bounds__(256) void k_chan_sumsq(const T* __restrict__ X, int64_t N, double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int l = blockIdx.y;
+    const T* x = X + (size_t)l * N;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)x[i];
+        s += v * v;
+    }
+    s = block_sum_256(s, sh);
+    if (threadIdx.x == 0) part[(size_t)l * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_chan_finish(const double* __restrict__ part, double* __restrict__ out, int L, int nch) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    double s = 0.0;
+    for (int k = 0; k < nch; ++k) s += part[(size_t)l * nch + k];
+    out[l] = sqrt(s);
+}
+
+// x[l] *= 1/norm[l] (zero norms leave the channel unchanged)
+template <typename T>
+__global__ void k_chan_scale(T* __restrict__ X, const double* __restrict__ nrm, int64_t N) {
+    const int l = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double s = nrm[l];
+    if (s > 0.0) X[(size_t)l * N + i] = (T)((double)X[(size_t)l * N + i] / s);
+}
+
+// eq:weights-l21: wbar[d][p] = gb / (gb + ||(Psi^dag X)_{d,p}||) over the L channels.
+template <typename T>
+__global__ void k_reweight_l21(const T* __restrict__ X, const T* __restrict__ coef, T* __restrict__ wbar, double gb,
+                               int L, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int d = blockIdx.y;
+    const T* S = (d == 0) ? X + p : coef + (size_t)(d - 1) * L * N + p;
+    double n2 = 0.0;
+    for (int l = 0; l < L; ++l) {
+        const double v = (double)S[(size_t)l * N];
+        n2 += v * v;
+    }
+    wbar[(size_t)d * N + p] = (T)(gb / (gb + sqrt(n2)));
+}
+
+template <typename T>
+void launch_fill(hipStream_t s, T* p, T v, int64_t n) {
+    if (n > 0) k_fill<T><<<nb(n, 256), 256, 0, s>>>(p, v, n);
+}
+template <typename T>
+void launch_axpby(hipStream_t s, T* y, const T* x, T a, T b, int64_t n) {
+    if (n > 0) k_axpby<T><<<nb(n, 256), 256, 0, s>>>(y, x, a, b, n);
+}
+
+template <typename T>
+void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg) {
+    const int64_t n = (int64_t)c->L * c->N;
+    int grid = (int)std::min<int64_t>(NRED, (n + 255) / 256);
+    if (grid < 1) grid = 1;
+    k_primal<T><<<grid, 256, 0, c->stream>>>((T*)c->d.X, (T*)c->d.Xt, (const T*)c->d.P, Atsum, Dimg, (T)c->k1,
+                                              (T)c->k2, (T)c->k3, (T)c->tau, n, c->d.red_part);
+    k_finish_beta<<<1, 64, 0, c->stream>>>(c->d.red_part, c->d.scal, grid);
+}
+
+// Per-channel l2 norms of X into out[L] (device doubles).
+template <typename T>
+void launch_chan_norms(hs_ctx* c, const T* X, double* out) {
+    const int nch = 64;
+    dim3 g(nch, c->L);
+    k_chan_sumsq<T><<<g, 256, 0, c->stream>>>(X, c->N, c->d.red_part);
+    k_chan_finish<<<1, 64, 0, c->stream>>>(c->d.red_part, out, c->L, nch);
+}
+
+template <typename T>
+void launch_chan_scale(hs_ctx* c, T* X, const double* nrm) {
+    dim3 g(nb(c->N, 256), c->L);
+    k_chan_scale<T><<<g, 256, 0, c->stream>>>(X, nrm, c->N);
+}
+
+template <typename T>
+void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb) {
+    dim3 g(nb(c->N, 256), c->D);
+    k_reweight_l21<T><<<g, 256, 0, c->stream>>>(X, coef, wbar, gb, c->L, c->N);
+}
+
+#define HS_INST(T)                                                                 \
+    template void launch_fill<T>(hipStream_t, T*, T, int64_t);                     \
+    template void launch_axpby<T>(hipStream_t, T*, const T*, T, T, int64_t);       \
+    template void launch_primal<T>(hs_ctx*, const T*, const T*);                   \
+    template void launch_chan_norms<T>(hs_ctx*, const T*, double*);                \
+    template void launch_chan_scale<T>(hs_ctx*, T*, const double*);                \
+    template void launch_reweight_l21<T>(hs_ctx*, const T*, const T*, T*, double);
+HS_INST(float)
+HS_INST(double)
+template void launch_fill<int32_t>(hipStream_t, int32_t*, int32_t, int64_t);
+#undef HS_INST
+
+}  // namespace hs

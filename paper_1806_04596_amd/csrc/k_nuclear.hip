@@ -1,0 +1,287 @@
+// Nuclear-norm proximity operator through the L x L Gram matrix (eq:prox-L*,
+// Algorithm 2 Step 5).
+//
+//  * Gram C = Z^T Z of the N x L matrix Z (= P + Xt, column l = channel l): FP64
+//    MFMA (v_mfma_f64_16x16x4f64) on 64-pixel slabs staged in LDS; inputs in the
+//    working precision are widened exactly, so C is the FP64 Gram of Z.  Split-K
+//    partials are summed in fixed order (deterministic).
+//  * Eigen-decomposition of C: cyclic parallel Jacobi in FP64 inside one
+//    workgroup (round-robin pairing, L/2 disjoint rotations per round), warm
+//    started from the previous eigenvectors when the Gram changes little.
+//  * W = V diag(f(sigma)) V^T with sigma_j = sqrt(lambda_j) sorted in decreasing
+//    order and f = min(1, w_j/sigma_j) (dual form I - S*_w) or 1 - that (prox).
+//  * Back-projection out = Z W (every pixel's length-L row times W).
+#include "hs_internal.h"
+
+namespace hs {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GR_SLAB = 64;   // pixels per LDS slab
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* __restrict__ Xt,
+                                              double* __restrict__ part, int L, int64_t N, int64_t chunk) {
+    __shared__ double S[MAX_L][GR_SLAB + 2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t p_end = min(N, p_begin + chunk);
+    double4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += GR_SLAB) {
+        for (int e = tid; e < MAX_L * GR_SLAB; e += 256) {
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            const int64_t pix = p0 + pp;
+            double v = 0.0;
+            if (ch < L && pix < p_end) {
+                T z = P[(size_t)ch * N + pix];
+                if (Xt) z += Xt[(size_t)ch * N + pix];
+                v = (double)z;
+            }
+            S[ch][pp] = v;
+        }
+        __syncthreads();
+        const int i = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+        for (int kk = 0; kk < GR_SLAB; kk += 4) {
+            const double a = S[wave * 16 + i][kk + kq];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const double b = S[jb * 16 + i][kk + kq];
+                acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D layout of the 16x16 f64 MFMA: lane holds column (lane & 15) and rows 4*(lane>>4) + r.
+    double* out = part + (size_t)blockIdx.x * MAX_L * MAX_L;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + 4 * (lane >> 4) + r;
+            const int col = jb * 16 + (lane & 15);
+            out[row * MAX_L + col] = acc[jb][r];
+        }
+    }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, double* __restrict__ C, int nparts) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= MAX_L * MAX_L) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[(size_t)k * MAX_L * MAX_L + e];
+    C[e] = s;
+}
+
+// ------------------------------------------------------------------ Jacobi
+// One workgroup of 256 threads.  A (n x n, n = L rounded up to even) and V in LDS.
+// mode 0: f = min(1, w/s) (I - S*_w); mode 1: f = 1 - min(1, w/s) (S*_w / X).
+// warm: start from V = previous eigenvectors (A <- V^T C V).
+template <typename TW>
+__global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, double* __restrict__ Vg,
+                                             double* __restrict__ sig_out, const double* __restrict__ w,
+                                             TW* __restrict__ Wout, int L, int mode, int warm) {
+    __shared__ double A[MAX_L][MAX_L + 1];
+    __shared__ double V[MAX_L][MAX_L + 1];
+    __shared__ double Tm[MAX_L][MAX_L + 1];
+    __shared__ double cs[MAX_L / 2], sn[MAX_L / 2];
+    __shared__ int pp[MAX_L / 2], qq[MAX_L / 2];
+    __shared__ int rotated;
+    __shared__ double lam[MAX_L], fac[MAX_L];
+    __shared__ int ord[MAX_L];
+    const int tid = threadIdx.x;
+    const int n = L + (L & 1);
+    // load
+    for (int e = tid; e < n * n; e += 256) {
+        const int i = e / n, j = e - i * n;
+        A[i][j] = (i < L && j < L) ? Cg[i * MAX_L + j] : 0.0;
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (warm) {
+        // V <- previous eigenvectors, A <- V^T C V
+        for (int e = tid; e < n * n; e += 256) {
+            const int i = e / n, j = e - i * n;
+            V[i][j] = Vg[i * MAX_L + j];
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += 256) {   // Tm = C V
+            const int i = e / n, j = e - i * n;
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += A[i][k] * V[k][j];
+            Tm[i][j] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += 256) {   // A = V^T Tm
+            const int i = e / n, j = e - i * n;
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += V[k][i] * Tm[k][j];
+            A[i][j] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += 256) {   // symmetrise through Tm
+            const int i = e / n, j = e - i * n;
+            Tm[i][j] = 0.5 * (A[i][j] + A[j][i]);
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += 256) {
+            const int i = e / n, j = e - i * n;
+            A[i][j] = Tm[i][j];
+        }
+        __syncthreads();
+    }
+    const int half = n / 2;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < n - 1; ++round) {
+            if (tid < half) {
+                // round-robin pairing: player 0 fixed, players 1..n-1 rotate
+                int p, q;
+                if (tid == 0) {
+                    p = 0;
+                    q = 1 + (round % (n - 1));
+                } else {
+                    p = 1 + ((tid + round) % (n - 1));
+                    q = 1 + ((n - 1 - tid + round) % (n - 1));
+                }
+                if (p > q) { const int t = p; p = q; q = t; }
+                const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                    const double th = (aqq - app) / (2.0 * apq);
+                    const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    s = t * c;
+                    rotated = 1;
+                }
+                cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int e = tid; e < half * n; e += 256) {
+                const int k = e / n, i = e - k * n;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double aip = A[i][p], aiq = A[i][q];
+                A[i][p] = c * aip - s * aiq;
+                A[i][q] = s * aip + c * aiq;
+                const double vip = V[i][p], viq = V[i][q];
+                V[i][p] = c * vip - s * viq;
+                V[i][q] = s * vip + c * viq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int e = tid; e < half * n; e += 256) {
+                const int k = e / n, j = e - k * n;
+                const int p = pp[k], q = qq[k];
+                const double c = cs[k], s = sn[k];
+                const double apj = A[p][j], aqj = A[q][j];
+                A[p][j] = c * apj - s * aqj;
+                A[q][j] = s * apj + c * aqj;
+            }
+            __syncthreads();
+        }
+        const int any = rotated;   // every thread reads before anyone resets it
+        __syncthreads();
+        if (!any) break;
+    }
+    // sort eigenvalues in decreasing order (rank by comparison, ties by index)
+    if (tid < n) lam[tid] = A[tid][tid];
+    __syncthreads();
+    if (tid < L) {
+        int rank = 0;
+        const double li = lam[tid];
+        for (int j = 0; j < L; ++j) {
+            const double lj = lam[j];
+            rank += (lj > li || (lj == li && j < tid)) ? 1 : 0;
+        }
+        ord[rank] = tid;
+    }
+    __syncthreads();
+    if (tid < L) {
+        const int src = ord[tid];
+        const double sg = sqrt(fmax(lam[src], 0.0));
+        const double wj = w[tid];
+        double f = (sg > 0.0) ? fmin(1.0, wj / sg) : 1.0;
+        if (mode == 1) f = 1.0 - f;
+        fac[src] = f;
+        sig_out[tid] = sg;
+    }
+    __syncthreads();
+    // store eigenvectors for the next warm start
+    for (int e = tid; e < MAX_L * MAX_L; e += 256) {
+        const int i = e / MAX_L, j = e - i * MAX_L;
+        Vg[e] = (i < n && j < n) ? V[i][j] : ((i == j) ? 1.0 : 0.0);
+    }
+    // W[a][b] = sum_j V[a][j] f_j V[b][j]
+    for (int e = tid; e < MAX_L * MAX_L; e += 256) {
+        const int a = e / MAX_L, b = e - a * MAX_L;
+        double s = 0.0;
+        if (a < L && b < L)
+            for (int j = 0; j < L; ++j) s += V[a][j] * fac[j] * V[b][j];
+        Wout[e] = (TW)s;
+    }
+}
+
+// out[b][p] = sum_a Z[a][p] W[a][b], Z = in1 + in2 (in2 may be null).
+template <typename T>
+__global__ __launch_bounds__(256) void k_backproject(const T* __restrict__ in1, const T* __restrict__ in2,
+                                                     const T* __restrict__ Wg, T* __restrict__ out, int L,
+                                                     int64_t N) {
+    __shared__ T W[MAX_L * MAX_L];
+    for (int e = threadIdx.x; e < MAX_L * MAX_L; e += blockDim.x) W[e] = Wg[e];
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    T z[MAX_L];
+#pragma unroll
+    for (int a = 0; a < MAX_L; ++a) {
+        if (a < L) {
+            T v = in1[(size_t)a * N + p];
+            if (in2) v += in2[(size_t)a * N + p];
+            z[a] = v;
+        }
+    }
+    for (int b = 0; b < L; ++b) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < MAX_L; ++a)
+            if (a < L) s += z[a] * W[a * MAX_L + b];
+        out[(size_t)b * N + p] = s;
+    }
+}
+
+template <typename T>
+void launch_gram(hs_ctx* c, const T* P, const T* Xt) {
+    int64_t chunk = (c->N + NGRAM - 1) / NGRAM;
+    chunk = (chunk + GR_SLAB - 1) / GR_SLAB * GR_SLAB;
+    const int nparts = (int)((c->N + chunk - 1) / chunk);
+    k_gram<T><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    k_gram_reduce<<<(MAX_L * MAX_L + 255) / 256, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
+}
+
+void launch_eig(hs_ctx* c, int mode) {
+    const int warm = 1;  // eigV starts as the identity, so the first call is a cold start
+    if (c->dtype == HS_F32)
+        k_eig<float><<<1, 256, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (float*)c->d.Wmat,
+                                               c->L, mode, warm);
+    else
+        k_eig<double><<<1, 256, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (double*)c->d.Wmat,
+                                                c->L, mode, warm);
+}
+
+template <typename T>
+void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2) {
+    k_backproject<T><<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L,
+                                                                           c->N);
+}
+
+template void launch_gram<float>(hs_ctx*, const float*, const float*);
+template void launch_gram<double>(hs_ctx*, const double*, const double*);
+template void launch_backproject<float>(hs_ctx*, float*, const float*, const float*);
+template void launch_backproject<double>(hs_ctx*, double*, const double*, const double*);
+
+}  // namespace hs

@@ -1,0 +1,891 @@
+// Measurement operator Phi_l = Theta_l G_l F Z and its adjoint (Sec. 2.1, eq:inverse),
+// and the data-fidelity dual update (Algorithm 2, Steps 4 and 10-12, eq:md).
+//
+// Design (gfx950):
+//  * F Z: two LDS Stockham radix-4/2 passes.  The row pass transforms only the
+//    ny rows that Z fills (zero-padding is implicit); the column pass works on
+//    tiles of CT adjacent columns so every HBM access is a CT-wide contiguous
+//    segment.  The adjoint mirrors it and only writes the rows Z^T keeps.
+//  * G (degridding): visibilities are stored tile-major; a work unit stages the
+//    (T+8)^2 grid neighbourhood of its tile in LDS and each thread interpolates
+//    one visibility (8 + 8 kernel values, 64 taps from LDS).
+//  * G^T (gridding): "pull" form with no global atomics: one wave owns the
+//    T x T core of a tile and consumes every visibility whose footprint reaches
+//    it (its own tile plus the border regions of the 8 neighbours, 13 ranges),
+//    accumulating in LDS; each grid cell is written exactly once.  Tiles with
+//    many visibilities are split and their partial cores summed in fixed order.
+//  * Per-block FP64 sums for the ellipsoid projection are produced by a
+//    deterministic segmented scan in the degridding pass and reduced per
+//    (block, preconditioner value) bin, so the secular equation of the exact
+//    projection is solved over bins instead of visibilities.
+#include "hs_internal.h"
+
+namespace hs {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+// ------------------------------------------------------------------ FFT core
+// In-place Stockham autosort FFT over `nseq` sequences of length n held in
+// LDS; element k of sequence s lives at buf[k*es + s*ss].  Each stage loads its
+// butterflies into registers, synchronises, and stores them at their
+// autosorted positions.  tw[k] = exp(-2 pi i k / n); INV uses the conjugate.
+template <typename T, bool INV, int KPT>
+__device__ __forceinline__ void fft_lds(cplx<T>* buf, int n, int nseq, int es, int ss, bool seq_fast,
+                        const cplx<T>* __restrict__ tw) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lgseq = __builtin_ctz(nseq);
+    cplx<T> r[4 * KPT];
+    for (int Ns = 1; Ns < n;) {
+        if (n / Ns >= 4) {
+            // radix-4 stage: KPT butterflies per thread
+            const int nb = n >> 2;
+            const int lgnb = __builtin_ctz(nb);
+            const int total = nb * nseq;
+            const int tstride = n / (Ns * 4);
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) {
+                const int b = tid + k * nth;
+                if (b < total) {
+                    int s, j;
+                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
+                    const int jm = j & (Ns - 1);
+                    cplx<T>* base = buf + s * ss;
+                    cplx<T> a0 = base[j * es];
+                    cplx<T> a1 = base[(j + nb) * es];
+                    cplx<T> a2 = base[(j + 2 * nb) * es];
+                    cplx<T> a3 = base[(j + 3 * nb) * es];
+                    if (Ns > 1) {
+                        cplx<T> w1 = tw[jm * tstride], w2 = tw[2 * jm * tstride], w3 = tw[3 * jm * tstride];
+                        if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
+                        a1 = cmul(a1, w1); a2 = cmul(a2, w2); a3 = cmul(a3, w3);
+                    }
+                    const cplx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+                    const cplx<T> s13 = cadd(a1, a3), d13 = csub(a1, a3);
+                    // d13 times -i (forward) or +i (inverse)
+                    const cplx<T> jd13 = INV ? cplx<T>{-d13.im, d13.re} : cplx<T>{d13.im, -d13.re};
+                    r[4 * k + 0] = cadd(s02, s13);
+                    r[4 * k + 1] = cadd(d02, jd13);
+                    r[4 * k + 2] = csub(s02, s13);
+                    r[4 * k + 3] = csub(d02, jd13);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KPT; ++k) {
+                const int b = tid + k * nth;
+                if (b < total) {
+                    int s, j;
+                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
+                    const int jm = j & (Ns - 1);
+                    const int idxD = (j - jm) * 4 + jm;
+                    cplx<T>* base = buf + s * ss;
+                    base[idxD * es] = r[4 * k + 0];
+                    base[(idxD + Ns) * es] = r[4 * k + 1];
+                    base[(idxD + 2 * Ns) * es] = r[4 * k + 2];
+                    base[(idxD + 3 * Ns) * es] = r[4 * k + 3];
+                }
+            }
+            __syncthreads();
+            Ns <<= 2;
+        } else {
+            // radix-2 stage: 2*KPT butterflies per thread
+            const int nb = n >> 1;
+            const int lgnb = __builtin_ctz(nb);
+            const int total = nb * nseq;
+            const int tstride = n / (Ns * 2);
+#pragma unroll
+            for (int k = 0; k < 2 * KPT; ++k) {
+                const int b = tid + k * nth;
+                if (b < total) {
+                    int s, j;
+                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
+                    const int jm = j & (Ns - 1);
+                    cplx<T>* base = buf + s * ss;
+                    cplx<T> a0 = base[j * es];
+                    cplx<T> a1 = base[(j + nb) * es];
+                    if (Ns > 1) {
+                        cplx<T> w1 = tw[jm * tstride];
+                        if (INV) w1.im = -w1.im;
+                        a1 = cmul(a1, w1);
+                    }
+                    r[2 * k + 0] = cadd(a0, a1);
+                    r[2 * k + 1] = csub(a0, a1);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 2 * KPT; ++k) {
+                const int b = tid + k * nth;
+                if (b < total) {
+                    int s, j;
+                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
+                    const int jm = j & (Ns - 1);
+                    const int idxD = (j - jm) * 2 + jm;
+                    cplx<T>* base = buf + s * ss;
+                    base[idxD * es] = r[2 * k + 0];
+                    base[(idxD + Ns) * es] = r[2 * k + 1];
+                }
+            }
+            __syncthreads();
+            Ns <<= 1;
+        }
+    }
+}
+
+// Row pass of F Z: rows j of image l are deapodised, placed at (i - nx/2) mod Kx
+// and transformed; H[l][j][:] holds the transformed row (only the ny rows Z fills).
+template <typename T, int KPT>
+__global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, cplx<T>* __restrict__ H, const T* __restrict__ sx,
+                               const T* __restrict__ sy, const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                               int rows) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int l = blockIdx.y;
+    const int j0 = blockIdx.x * rows;
+    const T* Xl = X + (size_t)l * nx * ny;
+    const int E = Kx * rows;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int s = e / Kx, q = e - s * Kx;
+        const int j = j0 + s;
+        int i = q + nx / 2;
+        if (i >= Kx) i -= Kx;
+        T v = (i < nx) ? Xl[(size_t)j * nx + i] * sx[i] * sy[j] : T(0);
+        buf[e] = {v, T(0)};
+    }
+    __syncthreads();
+    fft_lds<T, false, KPT>(buf, Kx, rows, 1, Kx, false, tw);
+    cplx<T>* Hl = H + ((size_t)l * ny + j0) * Kx;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) Hl[e] = buf[e];
+}
+
+// Column pass of F: CT adjacent columns, rows placed at (j - ny/2) mod Ky.
+template <typename T, int KPT>
+__global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G, const cplx<T>* __restrict__ tw,
+                               int ny, int Kx, int Ky, int CT) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int l = blockIdx.y;
+    const int c0 = blockIdx.x * CT;
+    const cplx<T>* Hl = H + (size_t)l * ny * Kx;
+    const int E = Ky * CT;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int q = e / CT, c = e - q * CT;
+        int j = q + ny / 2;
+        if (j >= Ky) j -= Ky;
+        buf[e] = (j < ny) ? Hl[(size_t)j * Kx + c0 + c] : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    fft_lds<T, false, KPT>(buf, Ky, CT, CT, 1, true, tw);
+    cplx<T>* Gl = G + (size_t)l * Ky * Kx;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int k = e / CT, c = e - k * CT;
+        Gl[(size_t)k * Kx + c0 + c] = buf[e];
+    }
+}
+
+// Adjoint column pass: inverse (unnormalised) DFT along y, keep the rows Z^T reads.
+template <typename T, int KPT>
+__global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H, const cplx<T>* __restrict__ tw,
+                               int ny, int Kx, int Ky, int CT) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int l = blockIdx.y;
+    const int c0 = blockIdx.x * CT;
+    const cplx<T>* Gl = G + (size_t)l * Ky * Kx;
+    const int E = Ky * CT;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int k = e / CT, c = e - k * CT;
+        buf[e] = Gl[(size_t)k * Kx + c0 + c];
+    }
+    __syncthreads();
+    fft_lds<T, true, KPT>(buf, Ky, CT, CT, 1, true, tw);
+    cplx<T>* Hl = H + (size_t)l * ny * Kx;
+    const int E2 = ny * CT;
+    for (int e = threadIdx.x; e < E2; e += blockDim.x) {
+        const int j = e / CT, c = e - j * CT;
+        int q = j - ny / 2;
+        if (q < 0) q += Ky;
+        Hl[(size_t)j * Kx + c0 + c] = buf[q * CT + c];
+    }
+}
+
+// Adjoint row pass: inverse DFT along x, crop, deapodise, real part.
+template <typename T, int KPT>
+__global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict__ H, T* __restrict__ X, const T* __restrict__ sx,
+                               const T* __restrict__ sy, const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                               int rows) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int l = blockIdx.y;
+    const int j0 = blockIdx.x * rows;
+    const cplx<T>* Hl = H + ((size_t)l * ny + j0) * Kx;
+    const int E = Kx * rows;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) buf[e] = Hl[e];
+    __syncthreads();
+    fft_lds<T, true, KPT>(buf, Kx, rows, 1, Kx, false, tw);
+    T* Xl = X + (size_t)l * nx * ny;
+    const int E2 = nx * rows;
+    for (int e = threadIdx.x; e < E2; e += blockDim.x) {
+        const int s = e / nx, i = e - s * nx;
+        const int j = j0 + s;
+        int q = i - nx / 2;
+        if (q < 0) q += Kx;
+        Xl[(size_t)j * nx + i] = buf[s * Kx + q].re * sx[i] * sy[j];
+    }
+}
+
+template <typename KF>
+static void set_lds(KF kern, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Rows per workgroup for the row passes (power of two dividing ny, Kx*rows <= 4096).
+static int row_group(const hs_ctx* c) {
+    int rows = 1;
+    while (rows * 2 <= c->ny && (c->ny % (rows * 2)) == 0 && c->Kx * rows * 2 <= 4096) rows *= 2;
+    return rows;
+}
+// Columns per tile for the column passes (LDS <= 128 KiB).
+template <typename T>
+static int col_group(const hs_ctx* c) {
+    const int maxE = (int)(131072 / sizeof(cplx<T>));
+    int ct = 1;
+    while (ct * 2 <= c->Kx && c->Kx % (ct * 2) == 0 && c->Ky * ct * 2 <= maxE && ct < 32) ct *= 2;
+    return ct;
+}
+
+// Launch one of the FFT kernels with KPT chosen so that nth = E / (4 KPT) <= 256.
+#define HS_FFT_DISPATCH(KERN, T, E, GRID, STREAM, ...)                                          \
+    do {                                                                                         \
+        const int E_ = (E);                                                                      \
+        const size_t lds_ = (size_t)E_ * sizeof(cplx<T>);                                        \
+        if (sizeof(T) == 4 && E_ >= 8192) {                                                      \
+            KERN<T, 8><<<GRID, E_ / 32, lds_, STREAM>>>(__VA_ARGS__);                            \
+        } else {                                                                                 \
+            KERN<T, 4><<<GRID, (E_ / 16 > 0 ? E_ / 16 : 1), lds_, STREAM>>>(__VA_ARGS__);       \
+        }                                                                                        \
+    } while (0)
+
+// Allow up to 160 KiB of dynamic LDS for every FFT instantiation (set once,
+// outside any stream capture).
+template <typename T, int KPT>
+static void fft_attrs_one() {
+    const size_t b = 160 * 1024;
+    set_lds(k_fft_rows_fwd<T, KPT>, b);
+    set_lds(k_fft_cols_fwd<T, KPT>, b);
+    set_lds(k_fft_cols_adj<T, KPT>, b);
+    set_lds(k_fft_rows_adj<T, KPT>, b);
+}
+void fft_init_attrs() {
+    static bool done = false;
+    if (done) return;
+    fft_attrs_one<float, 4>(); fft_attrs_one<float, 8>();
+    fft_attrs_one<double, 4>();
+    done = true;
+}
+
+template <typename T>
+void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L) {
+    const int rows = row_group(c);
+    dim3 grid(c->ny / rows, L);
+    HS_FFT_DISPATCH(k_fft_rows_fwd, T, c->Kx * rows, grid, c->stream, X, (cplx<T>*)c->d.H, (const T*)c->d.sx,
+                    (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx, rows);
+}
+template <typename T>
+void launch_fft_cols_fwd(hs_ctx* c, int L) {
+    const int ct = col_group<T>(c);
+    dim3 grid(c->Kx / ct, L);
+    HS_FFT_DISPATCH(k_fft_cols_fwd, T, c->Ky * ct, grid, c->stream, (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid,
+                    (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+}
+template <typename T>
+void launch_fft_cols_adj(hs_ctx* c, int L) {
+    const int ct = col_group<T>(c);
+    dim3 grid(c->Kx / ct, L);
+    HS_FFT_DISPATCH(k_fft_cols_adj, T, c->Ky * ct, grid, c->stream, (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H,
+                    (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+}
+template <typename T>
+void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
+    const int rows = row_group(c);
+    dim3 grid(c->ny / rows, L);
+    HS_FFT_DISPATCH(k_fft_rows_adj, T, c->Kx * rows, grid, c->stream, (const cplx<T>*)c->d.H, Xout,
+                    (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx, rows);
+}
+
+// ------------------------------------------------------------- KB kernel
+// phi(d) = I0(beta sqrt(1 - (d/4)^2)) / I0(beta) as its power series in
+// w = 1 - (d/4)^2 (all coefficients positive: no cancellation).
+template <typename T>
+__device__ __forceinline__ T kb_eval(T d, const KBPoly<T>& P) {
+    const T w = T(1) - d * d * T(0.0625);
+    T acc = P.c[P.n - 1];
+    for (int k = P.n - 2; k >= 0; --k) acc = acc * w + P.c[k];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void kb_weights(T f, const KBPoly<T>& P, T* w) {
+#pragma unroll
+    for (int j = 0; j < KB_J; ++j) w[j] = kb_eval(f + T(3 - j), P);
+}
+
+// ------------------------------------------------------------- degridding
+template <typename T>
+__device__ __forceinline__ void stage_tile(cplx<T>* tileS, const cplx<T>* __restrict__ g, int ox, int oy, int TT,
+                                           int Kx, int Ky) {
+    const int W = TT + 8;
+    for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
+        const int ry = e / W, rx = e - ry * W;
+        int gy = oy - 3 + ry, gx = ox - 3 + rx;
+        if (gy < 0) gy += Ky;
+        if (gy >= Ky) gy -= Ky;
+        if (gx < 0) gx += Kx;
+        if (gx >= Kx) gx -= Kx;
+        tileS[e] = g[(size_t)gy * Kx + gx];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> interp(const cplx<T>* tileS, int W, int lx, int ly, T fx, T fy,
+                                          const KBPoly<T>& kb) {
+    T wx[KB_J], wy[KB_J];
+    kb_weights(fx, kb, wx);
+    kb_weights(fy, kb, wy);
+    cplx<T> acc{T(0), T(0)};
+#pragma unroll
+    for (int jy = 0; jy < KB_J; ++jy) {
+        const cplx<T>* row = tileS + (ly + jy) * W + lx;
+        T rr = T(0), ri = T(0);
+#pragma unroll
+        for (int jx = 0; jx < KB_J; ++jx) {
+            const cplx<T> gv = row[jx];
+            rr += wx[jx] * gv.re;
+            ri += wx[jx] * gv.im;
+        }
+        acc.re += wy[jy] * rr;
+        acc.im += wy[jy] * ri;
+    }
+    return acc;
+}
+
+// out[dst] = theta * mult * (G ghat)(vis), dst = perm[pos] (caller order) or pos.
+template <typename T>
+__global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
+    const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
+    const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ mult,
+    const int32_t* __restrict__ perm, cplx<T>* __restrict__ out, int Kx, int Ky, int TT, int tiles_x, KBPoly<T> kb) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
+    const DegridUnit u = units[blockIdx.x];
+    const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
+    stage_tile(tileS, grid + (size_t)u.l * Kx * Ky, ox, oy, TT, Kx, Ky);
+    __syncthreads();
+    const int W = TT + 8;
+    for (int i = threadIdx.x; i < u.count; i += DEG_THREADS) {
+        const int pos = u.start + i;
+        const int cc = cell[pos];
+        const int cx = cc & 0xFFFF, cy = cc >> 16;
+        const cplx<T> f = frac[pos];
+        cplx<T> a = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
+        T s = theta[pos];
+        if (mult) s *= mult[pos];
+        a.re *= s;
+        a.im *= s;
+        out[perm ? perm[pos] : pos] = a;
+    }
+}
+
+// Phase 1 of the data dual (Steps 4 and 10): g = Theta G u, d = v + U (g - y)
+// (= vbar - U y) stored in v; per-run FP64 sums of |d|^2 and |y - g|^2.
+template <typename T>
+__global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
+    const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
+    const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ uprec,
+    const cplx<T>* __restrict__ yv, const int32_t* __restrict__ vbin, cplx<T>* __restrict__ v,
+    double* __restrict__ run_sum, int Kx, int Ky, int TT, int tiles_x, KBPoly<T> kb) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
+    __shared__ double s0[DEG_THREADS], s1[DEG_THREADS];
+    __shared__ int sb[DEG_THREADS], sh[DEG_THREADS], sf[DEG_THREADS];
+    const DegridUnit u = units[blockIdx.x];
+    const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
+    stage_tile(tileS, grid + (size_t)u.l * Kx * Ky, ox, oy, TT, Kx, Ky);
+    __syncthreads();
+    const int W = TT + 8;
+    const int tid = threadIdx.x;
+    int run_off = u.run_base;
+    for (int b0 = 0; b0 < u.count; b0 += DEG_THREADS) {
+        const int i = b0 + tid;
+        const bool act = i < u.count;
+        double a0 = 0.0, a1 = 0.0;
+        int bin = -1 - tid;  // unique for inactive lanes
+        if (act) {
+            const int pos = u.start + i;
+            const int cc = cell[pos];
+            const int cx = cc & 0xFFFF, cy = cc >> 16;
+            const cplx<T> f = frac[pos];
+            cplx<T> g = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
+            const T th = theta[pos];
+            g.re *= th;
+            g.im *= th;
+            const cplx<T> yy = yv[pos];
+            const T uu = uprec[pos];
+            const cplx<T> vv = v[pos];
+            const cplx<T> r{yy.re - g.re, yy.im - g.im};
+            const cplx<T> d{vv.re - uu * r.re, vv.im - uu * r.im};
+            v[pos] = d;
+            a0 = (double)d.re * (double)d.re + (double)d.im * (double)d.im;
+            a1 = (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+            bin = vbin[pos];
+        }
+        s0[tid] = a0;
+        s1[tid] = a1;
+        sb[tid] = bin;
+        __syncthreads();
+        const int flag = (tid == 0 || sb[tid - 1] != bin) ? 1 : 0;
+        sh[tid] = flag ? tid : 0;   // segment head (max-scan)
+        sf[tid] = flag;             // run count (sum-scan)
+        __syncthreads();
+        for (int off = 1; off < DEG_THREADS; off <<= 1) {
+            int hh = sh[tid], ff = sf[tid];
+            if (tid >= off) {
+                hh = max(hh, sh[tid - off]);
+                ff += sf[tid - off];
+            }
+            __syncthreads();
+            sh[tid] = hh;
+            sf[tid] = ff;
+            __syncthreads();
+        }
+        const int head = sh[tid];
+        for (int off = 1; off < DEG_THREADS; off <<= 1) {
+            double x0 = s0[tid], x1 = s1[tid];
+            if (tid - off >= head) {
+                x0 += s0[tid - off];
+                x1 += s1[tid - off];
+            }
+            __syncthreads();
+            s0[tid] = x0;
+            s1[tid] = x1;
+            __syncthreads();
+        }
+        const int nact = min(DEG_THREADS, u.count - b0);
+        const bool tail = act && (tid == nact - 1 || sb[tid + 1] != bin);
+        if (tail) {
+            const int slot = run_off + sf[tid] - 1;
+            run_sum[2 * (size_t)slot] = s0[tid];
+            run_sum[2 * (size_t)slot + 1] = s1[tid];
+        }
+        run_off += sf[nact - 1];
+        __syncthreads();
+    }
+}
+
+// Bin sums (fixed order, one wave per bin): S[bin] = sum of its runs.
+__global__ void k_bin_reduce(const int32_t* __restrict__ bin_run_ptr, const int32_t* __restrict__ bin_runs,
+                             const double* __restrict__ run_sum, double* __restrict__ S, int nbins) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= nbins) return;
+    const int r0 = bin_run_ptr[wave], r1 = bin_run_ptr[wave + 1];
+    double a = 0.0, b = 0.0;
+    for (int k = r0 + lane; k < r1; k += 64) {
+        const int r = bin_runs[k];
+        a += run_sum[2 * (size_t)r];
+        b += run_sum[2 * (size_t)r + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    if (lane == 0) {
+        S[2 * (size_t)wave] = a;
+        S[2 * (size_t)wave + 1] = b;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// Root of f(lam) = sum_c S_c/(u_c + lam)^2 - eps^2 per block (exact ellipsoid
+// projection, eq:prox with the metric U), one wave per block; Newton from
+// lam = 0, monotone for this convex decreasing f.  Also Step 13 (rho) and
+// Steps 14-19 (adaptive bound) when enabled.
+__global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const double* __restrict__ S,
+                              const double* __restrict__ bin_u, double* __restrict__ eps, double* __restrict__ lam_out,
+                              double* __restrict__ rho2, int32_t* __restrict__ vartheta, const double* __restrict__ scal,
+                              int nblk, int adaptive, double lam1, double lam2, double lam3, int vbar) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= nblk) return;
+    const int c0 = blk_bin_ptr[wave], c1 = blk_bin_ptr[wave + 1];
+    const double e = eps[wave];
+    const double e2 = e * e;
+    double f0 = 0.0, tot = 0.0, r2 = 0.0;
+    for (int k = c0 + lane; k < c1; k += 64) {
+        const double s = S[2 * (size_t)k], uu = bin_u[k];
+        f0 += s / (uu * uu);
+        tot += s;
+        r2 += S[2 * (size_t)k + 1];
+    }
+    f0 = wave_sum(f0);
+    tot = wave_sum(tot);
+    r2 = wave_sum(r2);
+    double lam = 0.0;
+    if (f0 > e2) {
+        if (e2 <= 0.0) {
+            lam = INFINITY;
+        } else {
+            double hi = sqrt(tot) / e;
+            for (int it = 0; it < 200; ++it) {
+                double f = 0.0, fp = 0.0;
+                for (int k = c0 + lane; k < c1; k += 64) {
+                    const double s = S[2 * (size_t)k], q = 1.0 / (bin_u[k] + lam);
+                    const double q2 = q * q;
+                    f += s * q2;
+                    fp += s * q2 * q;
+                }
+                f = wave_sum(f) - e2;
+                fp = -2.0 * wave_sum(fp);
+                if (f <= 1e-15 * e2) break;
+                double nl = lam - f / fp;
+                if (!(nl > lam)) break;
+                if (nl > hi) nl = hi;
+                if (nl - lam <= 1e-16 * nl) { lam = nl; break; }
+                lam = nl;
+            }
+        }
+    }
+    if (lane == 0) {
+        lam_out[wave] = lam;
+        rho2[wave] = r2;
+        if (adaptive) {
+            const double beta_prev = scal[0];
+            const double t = scal[1] + 1.0;
+            const double rho = sqrt(r2);
+            if (beta_prev < lam1 && (t - (double)vartheta[wave]) > (double)vbar && fabs(rho - e) / e > lam2) {
+                eps[wave] = lam3 * rho + (1.0 - lam3) * e;
+                vartheta[wave] = (int32_t)t;
+            }
+        }
+    }
+}
+
+// Phase 2 (Step 11): v = d * lam/(u + lam) (= vbar - U q); lam = inf gives v = d.
+template <typename T>
+__global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ uprec, const int32_t* __restrict__ vbin,
+                             const int32_t* __restrict__ bin_block, const double* __restrict__ lam, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const double la = lam[bin_block[vbin[i]]];
+    T f;
+    if (la == 0.0) f = T(0);
+    else if (isinf(la)) f = T(1);
+    else f = (T)(la / ((double)uprec[i] + la));
+    cplx<T> d = v[i];
+    d.re *= f;
+    d.im *= f;
+    v[i] = d;
+}
+
+// ---------------------------------------------------------- gridding (pull)
+template <typename T>
+__global__ __launch_bounds__(64) void k_grid_pull(
+    const GridUnit* __restrict__ units, const int32_t* __restrict__ granges, const int32_t* __restrict__ cell,
+    const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x, int ntiles,
+    KBPoly<T> kb) {
+    extern __shared__ unsigned char smem_raw[];
+    T* accR = reinterpret_cast<T*>(smem_raw);
+    T* accI = accR + TT * TT;
+    const GridUnit u = units[blockIdx.x];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < TT * TT; e += 64) { accR[e] = T(0); accI[e] = T(0); }
+    const int32_t* rg = granges + ((size_t)u.l * ntiles + u.tile) * (2 * N_GRANGES);
+    int pref[N_GRANGES + 1];
+    pref[0] = 0;
+#pragma unroll
+    for (int r = 0; r < N_GRANGES; ++r) pref[r + 1] = pref[r] + (rg[2 * r + 1] - rg[2 * r]);
+    const int E = pref[N_GRANGES];
+    const int e0 = (int)(((int64_t)u.split * E) / u.nsplit);
+    const int e1 = (int)(((int64_t)(u.split + 1) * E) / u.nsplit);
+    const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
+    __syncthreads();
+    for (int base = e0; base < e1; base += 64) {
+        const int e = base + lane;
+        if (e < e1) {
+            int r = 0;
+#pragma unroll
+            for (int q = 1; q < N_GRANGES; ++q) r += (e >= pref[q]) ? 1 : 0;
+            const int pos = rg[2 * r] + (e - pref[r]);
+            const int cc = cell[pos];
+            int relx = (cc & 0xFFFF) - ox, rely = (cc >> 16) - oy;
+            if (relx < -TT) relx += Kx;
+            if (relx >= 2 * TT) relx -= Kx;
+            if (rely < -TT) rely += Ky;
+            if (rely >= 2 * TT) rely -= Ky;
+            const cplx<T> f = frac[pos];
+            cplx<T> val = vals[pos];
+            if (weight) {
+                const T w = weight[pos];
+                val.re *= w;
+                val.im *= w;
+            }
+            T wx[KB_J], wy[KB_J];
+            kb_weights(f.re, kb, wx);
+            kb_weights(f.im, kb, wy);
+#pragma unroll
+            for (int jy = 0; jy < KB_J; ++jy) {
+                const int ry = rely - 3 + jy;
+                if (ry < 0 || ry >= TT) continue;
+                const T vr = wy[jy] * val.re, vi = wy[jy] * val.im;
+#pragma unroll
+                for (int jx = 0; jx < KB_J; ++jx) {
+                    const int rx = relx - 3 + jx;
+                    if (rx < 0 || rx >= TT) continue;
+                    atomicAdd(&accR[ry * TT + rx], vr * wx[jx]);
+                    atomicAdd(&accI[ry * TT + rx], vi * wx[jx]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (u.nsplit == 1) {
+        cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
+        for (int e = lane; e < TT * TT; e += 64) {
+            const int ry = e / TT, rx = e - ry * TT;
+            g[(size_t)(oy + ry) * Kx + ox + rx] = {accR[e], accI[e]};
+        }
+    } else {
+        cplx<T>* p = partial + (size_t)(u.partial + u.split) * TT * TT;
+        for (int e = lane; e < TT * TT; e += 64) p[e] = {accR[e], accI[e]};
+    }
+}
+
+template <typename T>
+__global__ void k_grid_merge(const SplitTile* __restrict__ splits, const cplx<T>* __restrict__ partial,
+                             cplx<T>* __restrict__ grid, int Kx, int Ky, int TT, int tiles_x) {
+    const SplitTile s = splits[blockIdx.x];
+    const int ox = (s.tile % tiles_x) * TT, oy = (s.tile / tiles_x) * TT;
+    cplx<T>* g = grid + (size_t)s.l * Kx * Ky;
+    for (int e = threadIdx.x; e < TT * TT; e += blockDim.x) {
+        cplx<T> acc{T(0), T(0)};
+        for (int k = 0; k < s.nsplit; ++k) {
+            const cplx<T> p = partial[(size_t)(s.partial + k) * TT * TT + e];
+            acc.re += p.re;
+            acc.im += p.im;
+        }
+        const int ry = e / TT, rx = e - ry * TT;
+        g[(size_t)(oy + ry) * Kx + ox + rx] = acc;
+    }
+}
+
+// ------------------------------------------------------------- reorderings
+template <typename T>
+__global__ void k_gather_user(const cplx<T>* __restrict__ in_user, const int32_t* __restrict__ perm,
+                              const T* __restrict__ theta, cplx<T>* __restrict__ out, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    cplx<T> v = in_user[perm[i]];
+    if (theta) {
+        const T t = theta[i];
+        v.re *= t;
+        v.im *= t;
+    }
+    out[i] = v;
+}
+
+template <typename T>
+__global__ void k_scatter_user(const cplx<T>* __restrict__ in, const int32_t* __restrict__ perm,
+                               cplx<T>* __restrict__ out_user, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    out_user[perm[i]] = in[i];
+}
+
+// ------------------------------------------------- exact ball projection (one block)
+// z <- argmin_{||q - y|| <= eps} (q - z)^H U (q - z) over the visibilities of one
+// block, without bins: FP64 block reductions and Newton from lambda = 0.
+__device__ __forceinline__ double wg_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_block(cplx<T>* __restrict__ z, const int32_t* __restrict__ vis_pos,
+                                                    const cplx<T>* __restrict__ yv, const T* __restrict__ uprec,
+                                                    const double* __restrict__ eps_blk, int blk, int64_t pos0,
+                                                    int64_t Mb) {
+    __shared__ double sh[4];
+    const double e = eps_blk[blk];
+    double r2 = 0.0, a2 = 0.0;
+    for (int64_t i = threadIdx.x; i < Mb; i += blockDim.x) {
+        const int g = vis_pos[pos0 + i];
+        const cplx<T> zz = z[i], yy = yv[g];
+        const double dr = (double)zz.re - (double)yy.re, di = (double)zz.im - (double)yy.im;
+        const double uu = (double)uprec[g];
+        r2 += dr * dr + di * di;
+        a2 += uu * uu * (dr * dr + di * di);
+    }
+    r2 = wg_sum(r2, sh);
+    a2 = wg_sum(a2, sh);
+    if (r2 <= e * e) return;   // already inside: q = z
+    double lam = 0.0;
+    if (e > 0.0) {
+        const double hi = sqrt(a2) / e;
+        for (int it = 0; it < 200; ++it) {
+            double f = 0.0, fp = 0.0;
+            for (int64_t i = threadIdx.x; i < Mb; i += blockDim.x) {
+                const int g = vis_pos[pos0 + i];
+                const cplx<T> zz = z[i], yy = yv[g];
+                const double dr = (double)zz.re - (double)yy.re, di = (double)zz.im - (double)yy.im;
+                const double uu = (double)uprec[g];
+                const double q = 1.0 / (uu + lam);
+                const double t = uu * uu * (dr * dr + di * di) * q * q;
+                f += t;
+                fp += t * q;
+            }
+            f = wg_sum(f, sh) - e * e;
+            fp = -2.0 * wg_sum(fp, sh);
+            if (f <= 1e-15 * e * e) break;
+            double nl = lam - f / fp;
+            if (!(nl > lam)) break;
+            if (nl > hi) nl = hi;
+            if (nl - lam <= 1e-16 * nl) { lam = nl; break; }
+            lam = nl;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < Mb; i += blockDim.x) {
+        const int g = vis_pos[pos0 + i];
+        const cplx<T> zz = z[i], yy = yv[g];
+        const double uu = (double)uprec[g];
+        const double f = (e > 0.0) ? uu / (uu + lam) : 0.0;
+        z[i] = {(T)((double)yy.re + f * ((double)zz.re - (double)yy.re)),
+                (T)((double)yy.im + f * ((double)zz.im - (double)yy.im))};
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+static KBPoly<T> kbpoly(const hs_ctx* c) {
+    KBPoly<T> p{};
+    p.n = c->kb_terms;
+    for (int k = 0; k < c->kb_terms; ++k) p.c[k] = (T)c->kb_c[k];
+    return p;
+}
+
+static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user) {
+    if (c->dunits.empty()) return;
+    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
+        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+        (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+}
+
+// Degrid into grid order with an extra per-visibility factor (used by the power iteration).
+template <typename T>
+void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult) {
+    if (c->dunits.empty()) return;
+    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
+        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+        (const T*)c->d.vis_theta, mult, nullptr, out, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+}
+
+template <typename T>
+void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v) {
+    if (c->dunits.empty()) return;
+    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    k_degrid_dual<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
+        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+        (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
+        c->d.run_sum, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+}
+
+template <typename T>
+void launch_bins_and_roots(hs_ctx* c) {
+    if (c->nbins == 0) return;
+    k_bin_reduce<<<nblocks(c->nbins * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr, c->d.bin_runs, c->d.run_sum,
+                                                                       c->d.bin_S, (int)c->nbins);
+    k_block_roots<<<nblocks(c->nblk * 64, 256), 256, 0, c->stream>>>(
+        c->d.blk_bin_ptr, c->d.bin_S, c->d.bin_u, c->d.blk_eps, c->d.blk_lambda, c->d.blk_rho2, c->d.blk_vartheta,
+        c->d.scal, (int)c->nblk, c->adaptive ? 1 : 0, c->lam1, c->lam2, c->lam3, c->vartheta_bar);
+}
+
+template <typename T>
+void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
+    if (c->Mtot == 0) return;
+    k_dual_apply<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(v, (const T*)c->d.vis_u,
+                                                                    c->d.vis_bin, c->d.bin_block, c->d.blk_lambda,
+                                                                    c->Mtot);
+}
+
+template <typename T>
+void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
+    const size_t lds = (size_t)2 * c->T * c->T * sizeof(T);
+    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
+        c->d.gunits, c->d.granges, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
+        (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, c->ntiles, kbpoly<T>(c));
+    if (!c->splits.empty())
+        k_grid_merge<T><<<(unsigned)c->splits.size(), 256, 0, c->stream>>>(
+            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Kx, c->Ky, c->T, c->tiles_x);
+}
+
+template <typename T>
+void launch_proj_block(hs_ctx* c, int64_t pos0, int64_t Mb, int blk, cplx<T>* z) {
+    k_proj_block<T><<<1, 256, 0, c->stream>>>(z, c->d.vis_pos, (const cplx<T>*)c->d.vis_y, (const T*)c->d.vis_u,
+                                             c->d.blk_eps, blk, pos0, Mb);
+}
+
+template <typename T>
+void launch_gather_user(hs_ctx* c, const cplx<T>* in_user, cplx<T>* out_grid, bool times_theta) {
+    if (c->Mtot == 0) return;
+    k_gather_user<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(
+        in_user, c->d.vis_perm, times_theta ? (const T*)c->d.vis_theta : nullptr, out_grid, c->Mtot);
+}
+
+template <typename T>
+void launch_scatter_user(hs_ctx* c, const cplx<T>* in_grid, cplx<T>* out_user) {
+    if (c->Mtot == 0) return;
+    k_scatter_user<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(in_grid, c->d.vis_perm, out_user, c->Mtot);
+}
+
+#define HS_INST(T)                                                                          \
+    template void launch_fft_rows_fwd<T>(hs_ctx*, const T*, int);                           \
+    template void launch_fft_cols_fwd<T>(hs_ctx*, int);                                     \
+    template void launch_fft_cols_adj<T>(hs_ctx*, int);                                     \
+    template void launch_fft_rows_adj<T>(hs_ctx*, T*, int);                                 \
+    template void launch_degrid_plain<T>(hs_ctx*, cplx<T>*);                                \
+    template void launch_degrid_grid_order<T>(hs_ctx*, cplx<T>*, const T*);                 \
+    template void launch_degrid_dual_v<T>(hs_ctx*, cplx<T>*);                               \
+    template void launch_bins_and_roots<T>(hs_ctx*);                                        \
+    template void launch_dual_apply_v<T>(hs_ctx*, cplx<T>*);                                \
+    template void launch_proj_block<T>(hs_ctx*, int64_t, int64_t, int, cplx<T>*);           \
+    template void launch_grid_pull<T>(hs_ctx*, const cplx<T>*, const T*);                   \
+    template void launch_gather_user<T>(hs_ctx*, const cplx<T>*, cplx<T>*, bool);           \
+    template void launch_scatter_user<T>(hs_ctx*, const cplx<T>*, cplx<T>*);
+HS_INST(float)
+HS_INST(double)
+#undef HS_INST
+
+}  // namespace hs

@@ -1,0 +1,296 @@
+"""Thin Python front end of the C ABI: one ``Problem`` per context.
+
+Argument marshalling only -- every operator runs in the HIP kernels of
+libhypersara.so.  Torch provides device memory (the workspace and the
+caller's tensors) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        raise L.HSError("a HIP device is required (no CPU fallback)")
+    return torch
+
+
+class Problem:
+    """A HyperSARA measurement/prior configuration bound to one GPU.
+
+    channels: list of dicts with keys uv [M][2], y_raw [M] complex, theta [M],
+    block_ptr [B+1], eps [B] and optionally precond [M] (None = U = I).
+    """
+
+    def __init__(self, nx: int, ny: int, channels, dtype: str = "f32", levels: int = 4, n_db: int = 8,
+                 tile: int = 0, device: int = 0, stream=None):
+        torch = _require_gpu()
+        self.torch = torch
+        self.lib = L.load()
+        self.nx, self.ny, self.L = nx, ny, len(channels)
+        self.levels, self.n_db, self.D = levels, n_db, 1 + n_db
+        self.dtype = dtype
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        self.cdtype = torch.complex64 if dtype == "f32" else torch.complex128
+        self.device = torch.device("cuda", device)
+        # a dedicated (default-priority) stream so one PD iteration can be captured in a HIP graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        desc = L.ProblemDesc(nx=nx, ny=ny, L=self.L, oversamp=2, J=8, levels=levels, n_db=n_db,
+                             dtype=L.HS_F32 if dtype == "f32" else L.HS_F64, tile=tile, device=device,
+                             stream=C.c_void_p(self.stream.cuda_stream))
+        ctx = C.c_void_p()
+        L.check(self.lib.hs_create(C.byref(desc), C.byref(ctx)), None, "hs_create")
+        self.ctx = ctx
+        self.counts = []
+        self.nblocks = []
+        for l, ch in enumerate(channels):
+            uv = np.ascontiguousarray(ch["uv"], dtype=np.float64)
+            M = uv.shape[0]
+            y = np.ascontiguousarray(np.asarray(ch["y_raw"], dtype=np.complex128)).view(np.float64)
+            th = np.ascontiguousarray(ch["theta"], dtype=np.float64)
+            bp = np.ascontiguousarray(ch["block_ptr"], dtype=np.int64)
+            eps = np.ascontiguousarray(ch["eps"], dtype=np.float64)
+            pre = ch.get("precond")
+            pre = None if pre is None else np.ascontiguousarray(pre, dtype=np.float64)
+            self._chk(self.lib.hs_set_channel(ctx, l, M, len(bp) - 1, L.as_i64p(bp), L.as_dptr(uv), L.as_dptr(y),
+                                              L.as_dptr(th), L.as_dptr(pre), L.as_dptr(eps)), "hs_set_channel")
+            self.counts.append(M)
+            self.nblocks.append(len(bp) - 1)
+        ws = C.c_size_t()
+        self._chk(self.lib.hs_plan(ctx, C.byref(ws)), "hs_plan")
+        self.ws_bytes = ws.value
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._chk(self.lib.hs_bind_workspace(ctx, C.c_void_p(self._ws_ptr), self.ws_bytes), "hs_bind_workspace")
+        self.M = int(sum(self.counts))
+
+    # ------------------------------------------------------------ helpers
+    def _chk(self, status, what):
+        L.check(status, self.ctx, what)
+
+    def _enter(self):
+        # order the library's stream after the caller's work on its current stream
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+        return cur
+
+    def _leave(self, cur):
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
+    def _call(self, what, fn, *args):
+        cur = self._enter()
+        try:
+            self._chk(fn(self.ctx, *args), what)
+        finally:
+            self._leave(cur)
+
+    @staticmethod
+    def _p(t):
+        return C.c_void_p(t.data_ptr()) if t is not None else None
+
+    def info(self):
+        i = L.Info()
+        self._chk(self.lib.hs_get_info(self.ctx, C.byref(i)), "hs_get_info")
+        return {k: getattr(i, k) for k, _ in L.Info._fields_}
+
+    def empty_cube(self):
+        return self.torch.empty((self.L, self.ny, self.nx), dtype=self.tdtype, device=self.device)
+
+    def empty_vis(self):
+        return self.torch.empty(self.M, dtype=self.cdtype, device=self.device)
+
+    def empty_coef(self):
+        return self.torch.empty((self.D, self.L, self.ny, self.nx), dtype=self.tdtype, device=self.device)
+
+    def _check_cube(self, X, shape=None):
+        shape = shape or (self.L, self.ny, self.nx)
+        if X.dtype != self.tdtype or tuple(X.shape) != tuple(shape) or not X.is_contiguous() or X.device != self.device:
+            raise L.HSError(f"expected contiguous {self.tdtype} {shape} on {self.device}")
+
+    def _check_vis(self, Y):
+        if Y.dtype != self.cdtype or Y.numel() != self.M or not Y.is_contiguous() or Y.device != self.device:
+            raise L.HSError(f"expected contiguous {self.cdtype} [{self.M}] on {self.device}")
+
+    def set_data(self, l, y_raw, theta, eps):
+        y = np.ascontiguousarray(np.asarray(y_raw, dtype=np.complex128)).view(np.float64)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        ep = np.ascontiguousarray(eps, dtype=np.float64)
+        self._call("hs_set_data", self.lib.hs_set_data, int(l), L.as_dptr(y), L.as_dptr(th), L.as_dptr(ep))
+
+    # ----------------------------------------------------------- operators
+    def phi(self, X, Y=None):
+        self._check_cube(X)
+        Y = self.empty_vis() if Y is None else Y
+        self._check_vis(Y)
+        self._call("hs_phi", self.lib.hs_phi, self._p(X), self._p(Y))
+        return Y
+
+    def phi_adj(self, Y, X=None):
+        self._check_vis(Y)
+        X = self.empty_cube() if X is None else X
+        self._check_cube(X)
+        self._call("hs_phi_adj", self.lib.hs_phi_adj, self._p(Y), self._p(X))
+        return X
+
+    def psi_adj(self, X, Cc=None):
+        self._check_cube(X)
+        Cc = self.empty_coef() if Cc is None else Cc
+        self._check_cube(Cc, (self.D, self.L, self.ny, self.nx))
+        self._call("hs_psi_adj", self.lib.hs_psi_adj, self._p(X), self._p(Cc))
+        return Cc
+
+    def psi(self, Cc, X=None):
+        self._check_cube(Cc, (self.D, self.L, self.ny, self.nx))
+        X = self.empty_cube() if X is None else X
+        self._check_cube(X)
+        self._call("hs_psi", self.lib.hs_psi, self._p(Cc), self._p(X))
+        return X
+
+    def prox_l21(self, A, t, wbar=None):
+        self._check_cube(A, (self.D, self.L, self.ny, self.nx))
+        self._call("hs_prox_l21", self.lib.hs_prox_l21, self._p(A), self._p(wbar), float(t))
+        return A
+
+    def dual_l21(self, A, Xt, mu, wbar=None, want_sum=False):
+        self._check_cube(A, (self.D, self.L, self.ny, self.nx))
+        self._check_cube(Xt)
+        S = self.empty_cube() if want_sum else None
+        self._call("hs_dual_l21", self.lib.hs_dual_l21, self._p(A), self._p(Xt), self._p(wbar), float(mu), self._p(S))
+        return (A, S) if want_sum else A
+
+    def _w(self, w):
+        if w is None:
+            return None, None
+        wa = np.ascontiguousarray(w, dtype=np.float64)
+        return wa, L.as_dptr(wa)
+
+    def prox_nuclear(self, X, w=None):
+        self._check_cube(X)
+        wa, wp = self._w(w)
+        sig = np.zeros(self.L)
+        self._call("hs_prox_nuclear", self.lib.hs_prox_nuclear, self._p(X), wp, L.as_dptr(sig))
+        return X, sig
+
+    def dual_nuclear(self, P, Xt, w=None):
+        self._check_cube(P)
+        self._check_cube(Xt)
+        wa, wp = self._w(w)
+        self._call("hs_dual_nuclear", self.lib.hs_dual_nuclear, self._p(P), self._p(Xt), wp)
+        return P
+
+    def dual_data(self, v, Xt, want_adj=False):
+        self._check_vis(v)
+        self._check_cube(Xt)
+        adj = self.empty_cube() if want_adj else None
+        self._call("hs_dual_data", self.lib.hs_dual_data, self._p(v), self._p(Xt), self._p(adj))
+        return (v, adj) if want_adj else v
+
+    def proj_ellipsoid(self, l, b, z):
+        self._call("hs_proj_ellipsoid", self.lib.hs_proj_ellipsoid, int(l), int(b), self._p(z))
+        return z
+
+    def op_norm(self, x0=None, max_it=1000, tol=1e-10, which="phi"):
+        out = C.c_double()
+        per = np.zeros(self.L)
+        it = C.c_int32()
+        if which == "psi":
+            self._call("hs_op_norm", self.lib.hs_op_norm, L.HS_NORM_PSI, 1, 0.0, None, C.byref(out), None, C.byref(it))
+            return out.value, None, 0
+        self._check_cube(x0)
+        self._call("hs_op_norm", self.lib.hs_op_norm, L.HS_NORM_PHI_PRECOND, int(max_it), float(tol), self._p(x0),
+                                      C.byref(out), L.as_dptr(per), C.byref(it))
+        return out.value, per, it.value
+
+    # ----------------------------------------------------------------- PD
+    def pd_init(self, mu, tau, kappa3, kappa1=1.0, kappa2=0.0, wbar=None, w=None, adaptive_eps=False,
+                lam1=5e-4, lam2=0.01, lam3=0.618, vartheta_bar=100):
+        self._wkeep = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        prm = L.PDParams(mu=mu, tau=tau, kappa1=kappa1, kappa2=kappa2, kappa3=kappa3,
+                         wbar=None if wbar is None else wbar.data_ptr(),
+                         w=None if self._wkeep is None else L.as_dptr(self._wkeep),
+                         adaptive_eps=1 if adaptive_eps else 0, lam1=lam1, lam2=lam2, lam3=lam3,
+                         vartheta_bar=vartheta_bar)
+        self._call("hs_pd_init", self.lib.hs_pd_init, C.byref(prm))
+
+    def _state(self, X=None, Xt=None, P=None, A=None, v=None):
+        f = lambda t: None if t is None else t.data_ptr()
+        return L.StatePtrs(X=f(X), Xt=f(Xt), P=f(P), A=f(A), v=f(v))
+
+    def set_state(self, X=None, Xt=None, P=None, A=None, v=None):
+        st = self._state(X, Xt, P, A, v)
+        self._call("hs_pd_set_state", self.lib.hs_pd_set_state, C.byref(st))
+
+    def get_state(self):
+        X, Xt, P = self.empty_cube(), self.empty_cube(), self.empty_cube()
+        A, v = self.empty_coef(), self.empty_vis()
+        st = self._state(X, Xt, P, A, v)
+        self._call("hs_pd_get_state", self.lib.hs_pd_get_state, C.byref(st))
+        return {"X": X, "Xt": Xt, "P": P, "A": A, "v": v}
+
+    def iterate(self, n=1):
+        self._call("hs_pd_iterate", self.lib.hs_pd_iterate, int(n))
+
+    def stats(self):
+        nb = int(sum(self.nblocks))
+        beta = C.c_double()
+        rho = np.zeros(nb)
+        eps = np.zeros(nb)
+        self._call("hs_pd_stats", self.lib.hs_pd_stats, C.byref(beta), L.as_dptr(rho), L.as_dptr(eps))
+        return beta.value, rho, eps
+
+    def solve(self, n_reweights, iters_per_reweight, gamma_factor=0.8, beta_tol=0.0, check_every=0):
+        X = self.empty_cube()
+        prm = L.SolveParams(n_reweights=n_reweights, iters_per_reweight=iters_per_reweight,
+                            gamma_factor=gamma_factor, beta_tol=beta_tol, check_every=check_every)
+        rep = L.Report()
+        self._call("hs_solve", self.lib.hs_solve, C.byref(prm), self._p(X), C.byref(rep))
+        return X, {"iterations": rep.iterations, "reweights": rep.reweights, "final_beta": rep.final_beta}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- host utilities
+def density_precond(uv: np.ndarray, nx: int, ny: int) -> np.ndarray:
+    lib = L.load()
+    uv = np.ascontiguousarray(uv, dtype=np.float64)
+    out = np.empty(uv.shape[0])
+    L.check(lib.hs_density_precond(uv.shape[0], L.as_dptr(uv), nx, ny, L.as_dptr(out)), None, "hs_density_precond")
+    return out
+
+
+def visibility_order(uv, precond, block_ptr, nx, ny, tile):
+    lib = L.load()
+    uv = np.ascontiguousarray(uv, dtype=np.float64)
+    M = uv.shape[0]
+    pre = None if precond is None else np.ascontiguousarray(precond, dtype=np.float64)
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
+    perm = np.empty(M, dtype=np.int64)
+    ntr = (2 * nx // tile) * (2 * ny // tile) * 9
+    rp = np.empty(ntr + 1, dtype=np.int64)
+    L.check(lib.hs_visibility_order(M, L.as_dptr(uv), L.as_dptr(pre), len(bp) - 1, L.as_i64p(bp), nx, ny, tile,
+                                    L.as_i64p(perm), L.as_i64p(rp)), None, "hs_visibility_order")
+    return perm, rp
+
+
+def daubechies_filter(K: int) -> np.ndarray:
+    lib = L.load()
+    h = np.empty(2 * K)
+    L.check(lib.hs_daubechies_filter(K, L.as_dptr(h)), None, "hs_daubechies_filter")
+    return h

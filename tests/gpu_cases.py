@@ -1,0 +1,62 @@
+"""Shared builders for the GPU parity tests.
+
+Each side builds its own problem from the same seeded draws (workloads):
+the oracle with its own Phi and density count, the library with its own.
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import workloads as W
+from oracle import pd
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def rel_per_channel(a, b) -> float:
+    return max(rel(a[l], b[l]) for l in range(len(b)))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name: str, precond: str = "density", **over):
+    cfg = W.CONFIGS[name].scaled(**over) if over else W.CONFIGS[name]
+    inp = W.make_problem_inputs(cfg)
+    oprob, y_raw = pd.build_problem(cfg, inp, precond)
+    return cfg, inp, oprob
+
+
+_gpu_cache = {}
+
+
+def gpu_case(name: str, dtype: str, precond: str = "density", tile: int = 0, **over):
+    key = (name, dtype, precond, tile, tuple(sorted(over.items())))
+    if key not in _gpu_cache:
+        from paper_1806_04596_amd.workload import build_problem
+        cfg, inp, _ = oracle_case(name, precond, **over)
+        prob, X0, host = build_problem(cfg, inp, W.make_measurements, dtype=dtype, precond=precond, tile=tile)
+        _gpu_cache[key] = (prob, X0, host)
+    return _gpu_cache[key]
+
+
+def to_dev(prob, a, complex_=False):
+    import torch
+    dt = prob.cdtype if complex_ else prob.tdtype
+    return torch.as_tensor(np.ascontiguousarray(a), device=prob.device).to(dt).contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def split(v, counts):
+    off = np.concatenate([[0], np.cumsum(counts)])
+    return [v[off[l]:off[l + 1]] for l in range(len(counts))]

@@ -1,0 +1,319 @@
+"""GPU (C-ABI) vs FP64 oracle parity, operator by operator and for whole PD
+iterations.  Bars: FP64 path <= 1e-12, FP32 path <= 1e-5 normwise relative
+error (per array, per channel); integer work is checked bit-exactly by the
+host tests."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nufft, pd, prox, wavelets
+from gpu_cases import TOL, gpu_case, host, oracle_case, rel, rel_per_channel, split, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["t1", "t2", "t3", "c1"]
+DTYPES = ["f64", "f32"]
+
+
+def _seeded(shape, seed, complex_=False):
+    rng = np.random.default_rng(seed)
+    if complex_:
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return rng.standard_normal(shape)
+
+
+# ------------------------------------------------------------------ Phi
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", CASES)
+def test_phi_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, X0, _ = gpu_case(name, dtype)
+    X = inp["X0"] + 0.1 * _seeded(inp["X0"].shape, 1)
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    ref = op.phi(X)
+    err = max(rel(Y[l], ref[l]) for l in range(cfg.L) if len(ref[l]))
+    assert err <= TOL[dtype], err
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", CASES)
+def test_phi_adj_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, dtype)
+    y = _seeded(prob.M, 2, complex_=True)
+    X = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
+    ref = op.phi_adj(split(y, prob.counts))
+    assert rel_per_channel(X, ref) <= TOL[dtype]
+
+
+def test_dot_test_f64():
+    prob, _, _ = gpu_case("t2", "f64")
+    x = _seeded((prob.L, prob.ny, prob.nx), 3)
+    y = _seeded(prob.M, 4, complex_=True)
+    Phix = host(prob.phi(to_dev(prob, x)))
+    Phiy = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
+    lhs = np.vdot(y, Phix).real
+    rhs = float(np.sum(x * Phiy))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(Phix) * np.linalg.norm(y)
+
+
+def test_phi_vs_nudft_f64():
+    # the GPU operator approximates the exact NUDFT to the kernel's accuracy
+    cfg, inp, op = oracle_case("t1")
+    prob, _, _ = gpu_case("t1", "f64")
+    X = inp["X0"]
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    for l in range(cfg.L):
+        ex = nufft.nudft(X[l], op.uv[l], op.theta[l])
+        assert rel(Y[l], ex) < 5e-7
+
+
+# --------------------------------------------------------------- wavelets
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", ["t1", "t3", "c1"])
+def test_psi_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, dtype)
+    X = inp["X0"] + 0.05 * _seeded(inp["X0"].shape, 5)
+    C = host(prob.psi_adj(to_dev(prob, X)))
+    ref = wavelets.psi_adj(X)
+    for d in range(9):
+        assert rel_per_channel(C[d], ref[d]) <= TOL[dtype], d
+    Cr = _seeded(ref.shape, 6)
+    Xs = host(prob.psi(to_dev(prob, Cr)))
+    assert rel_per_channel(Xs, wavelets.psi(Cr)) <= TOL[dtype]
+
+
+def test_psi_perfect_reconstruction_f64():
+    prob, _, _ = gpu_case("t3", "f64")
+    X = _seeded((prob.L, prob.ny, prob.nx), 7)
+    Xr = host(prob.psi(prob.psi_adj(to_dev(prob, X))))
+    assert rel(Xr, 9.0 * X) <= 1e-13
+
+
+# ------------------------------------------------------------------ proxes
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_prox_l21_and_dual_l21(dtype):
+    cfg, inp, op = oracle_case("t2")
+    prob, _, _ = gpu_case("t2", dtype)
+    rng = np.random.default_rng(8)
+    A = 0.05 * rng.standard_normal((9, cfg.L, cfg.ny, cfg.nx))
+    wbar = rng.uniform(0.2, 1.0, (9, cfg.ny, cfg.nx))
+    Ad = to_dev(prob, A)
+    out = host(prob.prox_l21(Ad, 0.03, wbar=to_dev(prob, wbar)))
+    ref = prox.prox_l21(A, 0.03 * wbar, axis=1)
+    assert rel(out, ref) <= TOL[dtype]
+    Xt = inp["X0"] + 0.02 * rng.standard_normal(inp["X0"].shape)
+    mu = 0.01
+    Ad = to_dev(prob, A)
+    Aout, S = prob.dual_l21(Ad, to_dev(prob, Xt), mu, wbar=to_dev(prob, wbar), want_sum=True)
+    refA = prox.dual_l21(A, wavelets.psi_adj(Xt), wbar, mu, 9.0)
+    assert rel(host(Aout), refA) <= TOL[dtype]
+    assert rel_per_channel(host(S), wavelets.psi(refA)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", ["t2", "c1"])
+def test_nuclear_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, dtype)
+    rng = np.random.default_rng(9)
+    X = inp["X0"] + 0.01 * rng.standard_normal(inp["X0"].shape)
+    s_ref = np.linalg.svd(X.reshape(cfg.L, -1).T, compute_uv=False)
+    w = np.sort(rng.uniform(0.0, 0.5 * s_ref[0], cfg.L))
+    Xd, sig = prob.prox_nuclear(to_dev(prob, X), w)
+    ref, s = prox.prox_nuclear_svd(X, w)
+    assert rel(sig, s) <= TOL[dtype]
+    assert rel(host(Xd), ref) <= TOL[dtype]
+    P = 0.05 * rng.standard_normal(X.shape)
+    Pd = prob.dual_nuclear(to_dev(prob, P), to_dev(prob, X), w)
+    refP = prox.dual_nuclear(P, X, w, "svd")
+    assert rel(host(Pd), refP) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", ["t1", "t2", "c1"])
+def test_dual_data_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    v = np.concatenate(st["v"]) if prob.M else np.zeros(0, complex)
+    vd = to_dev(prob, v, complex_=True)
+    vd, adj = prob.dual_data(vd, to_dev(prob, st["Xt"]), want_adj=True)
+    vg = split(host(vd), prob.counts)
+    adj_ref = np.zeros_like(st["Xt"])
+    for l in range(cfg.L):
+        vbar = st["v"][l] + op.u[l] * nufft.phi(st["Xt"][l], op.uv[l], op.theta[l])
+        bp = op.block_ptr[l]
+        vr = np.empty_like(vbar)
+        for b in range(len(bp) - 1):
+            s = slice(bp[b], bp[b + 1])
+            vr[s], _ = prox.dual_data_block(vbar[s], op.y[l][s], op.u[l][s], op.eps[l][b])
+        assert rel(vg[l], vr) <= TOL[dtype] * 10 if dtype == "f32" else rel(vg[l], vr) <= TOL[dtype]
+        adj_ref[l] = nufft.phi_adj(vr, op.uv[l], op.theta[l], cfg.ny, cfg.nx)
+    assert rel_per_channel(host(adj), adj_ref) <= (1e-4 if dtype == "f32" else TOL[dtype])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_proj_ellipsoid_parity(dtype):
+    cfg, inp, op = oracle_case("t2")
+    prob, _, _ = gpu_case("t2", dtype)
+    rng = np.random.default_rng(10)
+    for l in (0, 3):
+        bp = op.block_ptr[l]
+        for b in range(len(bp) - 1):
+            s = slice(bp[b], bp[b + 1])
+            y = op.y[l][s]
+            z = y + 3.0 * (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y)))
+            zd = to_dev(prob, z, complex_=True)
+            prob.proj_ellipsoid(l, b, zd)
+            q, _ = prox.proj_ball_precond(z, y, op.u[l][s], op.eps[l][b])
+            assert rel(host(zd), q) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_op_norm_parity_fixed_iterations(dtype):
+    cfg, inp, op = oracle_case("t1")
+    prob, _, _ = gpu_case("t1", dtype)
+    x0 = W.synth.power_start(cfg)
+    val, per, it = prob.op_norm(to_dev(prob, x0), max_it=40, tol=0.0)
+    assert it == 40
+    _, ref_per, _ = pd.op_norm_phi(op, x0, max_it=40, tol=0.0)
+    assert rel(per, ref_per) <= TOL[dtype]
+
+
+# ------------------------------------------------------------- PD iteration
+def _kappa3(op):
+    # a fixed admissible-scale step from the data weights (both sides use their own)
+    return 1.0 / (max(len(t) for t in op.theta) * max(float(np.max(t)) for t in op.theta if len(t)) ** 2)
+
+
+def _run_gpu_iteration(prob, st, prm, w, n=1):
+    prob.set_state(X=to_dev(prob, st["X"]), Xt=to_dev(prob, st["Xt"]), P=to_dev(prob, st["P"]),
+                   A=to_dev(prob, st["A"]), v=to_dev(prob, np.concatenate(st["v"]), complex_=True))
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa1=1.0, kappa2=1.0 / 9.0, w=w)
+    prob.iterate(n)
+    out = prob.get_state()
+    beta, rho, eps = prob.stats()
+    return {k: host(v) for k, v in out.items()}, beta, rho
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("name", ["t1", "t2", "c1"])
+def test_pd_one_iteration_parity(name, dtype):
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    w = np.linspace(0.2, 1.0, cfg.L)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    ref = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    prmg = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
+    g, beta, rho = _run_gpu_iteration(prob, st, prmg, w)
+    tol = TOL[dtype]
+    assert rel(g["X"], ref.X) <= tol
+    assert rel(g["Xt"], ref.Xt) <= tol
+    assert rel(g["P"], ref.P) <= tol
+    assert rel(g["A"], ref.A) <= tol
+    vg = split(g["v"], prob.counts)
+    for l in range(cfg.L):
+        assert rel(vg[l], ref.v[l]) <= tol * (10 if dtype == "f32" else 1)
+    assert abs(beta - ref.beta) <= tol * max(ref.beta, 1e-30) * 10
+    rho_ref = np.concatenate(ref.extra["rho"])
+    assert rel(rho, rho_ref) <= tol * 10
+
+
+def test_pd_twenty_iterations_f64():
+    cfg, inp, op = oracle_case("c1")
+    prob, _, _ = gpu_case("c1", "f64")
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    w = np.ones(cfg.L)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    for _ in range(20):
+        ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    g, beta, _ = _run_gpu_iteration(prob, st, prm, w, n=20)
+    assert rel(g["X"], ost.X) <= 1e-11
+    assert abs(beta - ost.beta) <= 1e-10 * ost.beta
+
+
+def test_graph_replays_match_oracle_each_time():
+    cfg, inp, op = oracle_case("t1")
+    prob, _, _ = gpu_case("t1", "f64")
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    w = np.ones(cfg.L)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    prob.set_state(X=to_dev(prob, st["X"]), Xt=to_dev(prob, st["Xt"]), P=to_dev(prob, st["P"]),
+                   A=to_dev(prob, st["A"]), v=to_dev(prob, np.concatenate(st["v"]), complex_=True))
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0, w=w)
+    for k in range(3):
+        prob.iterate(1)
+        got = host(prob.get_state()["X"])
+        prob.torch.cuda.synchronize()
+        _ = host(prob.phi(to_dev(prob, inp["X0"])))   # unrelated eager work between replays
+        ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+        assert rel(got, ost.X) <= 1e-12, k
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_determinism(dtype):
+    cfg, inp, op = oracle_case("t2")
+    prob, _, _ = gpu_case("t2", dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op))
+    a, _, _ = _run_gpu_iteration(prob, st, prm, np.ones(cfg.L), n=3)
+    b, _, _ = _run_gpu_iteration(prob, st, prm, np.ones(cfg.L), n=3)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------- edge cases
+def test_edge_cases_empty_channel_empty_block_zero_eps():
+    import paper_1806_04596_amd as H
+    rng = np.random.default_rng(11)
+    nx = ny = 32
+    uv1 = rng.normal(0, 0.1, (300, 2)).astype(np.float32).astype(np.float64)
+    uv2 = rng.normal(0, 0.1, (5, 2)).astype(np.float32).astype(np.float64)
+    chans, ochans = [], []
+    specs = [(uv1, np.array([0, 100, 100, 300]), np.array([1.0, 2.0, 0.0])),   # empty block, eps = 0
+             (np.zeros((0, 2)), np.array([0]), np.zeros(0)),                 # empty channel
+             (uv2, np.array([0, 5]), np.array([0.5]))]
+    y_all = []
+    for uv, bp, eps in specs:
+        m = len(uv)
+        y = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        th = rng.uniform(0.5, 2.0, m)
+        y_all.append((y, th))
+        pre = H.density_precond(uv, nx, ny) if m else None
+        chans.append(dict(uv=uv, y_raw=y, theta=th, block_ptr=bp, eps=eps, precond=pre))
+    prob = H.Problem(nx, ny, chans, dtype="f64", tile=8)
+    from oracle.precond import density_precond
+    op = pd.Problem(nx=nx, ny=ny, uv=[s[0] for s in specs], y=[y * th for (y, th) in y_all],
+                    theta=[th for (_, th) in y_all],
+                    u=[density_precond(s[0], nx, ny) if len(s[0]) else np.ones(0) for s in specs],
+                    eps=[s[2] for s in specs], block_ptr=[s[1] for s in specs])
+    X = rng.uniform(0, 1, (3, ny, nx))
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    ref = op.phi(X)
+    for l in (0, 2):
+        assert rel(Y[l], ref[l]) <= 1e-12
+    assert len(Y[1]) == 0
+    v = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
+    vd = prob.dual_data(to_dev(prob, v, complex_=True), to_dev(prob, X))
+    vg = split(host(vd), prob.counts)
+    vv = split(v, prob.counts)
+    for l in (0, 2):
+        vbar = vv[l] + op.u[l] * op.phi(X)[l]
+        bp = op.block_ptr[l]
+        for b in range(len(bp) - 1):
+            s = slice(bp[b], bp[b + 1])
+            if bp[b + 1] == bp[b]:
+                continue
+            r, _ = prox.dual_data_block(vbar[s], op.y[l][s], op.u[l][s], op.eps[l][b])
+            assert rel(vg[l][s], r) <= 1e-12
+    Xa = host(prob.phi_adj(to_dev(prob, v, complex_=True)))
+    assert np.all(Xa[1] == 0)

@@ -61,7 +61,7 @@ CONFIGS = {
     # small cases used by parity tests: several tiles, ragged block sizes
     "t1": WorkloadConfig("t1", 32, 32, 3, 1.0, 2.0, 6, False, 700, None, 3, 40.0, 11),
     "t2": WorkloadConfig("t2", 64, 64, 5, 1.4, 2.8, 12, True, 0, (0.2, 2.0), 4, 40.0, 12),
-    "t3": WorkloadConfig("t3", 128, 96, 4, 1.4, 2.8, 15, True, 0, (0.2, 2.0), 3, 30.0, 13),
+    "t3": WorkloadConfig("t3", 128, 64, 4, 1.4, 2.8, 15, True, 0, (0.2, 2.0), 3, 30.0, 13),
 }
 
 
