@@ -104,6 +104,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise HSError(f"{path} not found: build it with paper_1806_04596_amd.build.build()")
+    # Load torch first: it brings its own HIP runtime (same soname), which the
+    # library must share; loading the library first would pull in a second
+    # runtime instance next to torch's.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -345,8 +345,11 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
         return fail(nullptr, HS_ERR_SHAPE, "nx, ny must be powers of two in 16..16384 and multiples of 2^levels");
     if (2 * d.nx > 4096 * 8 || 2 * d.ny > 4096 * 8) return fail(nullptr, HS_ERR_SHAPE, "grid too large");
     int dev_count = 0;
-    if (hipGetDeviceCount(&dev_count) != hipSuccess || d.device < 0 || d.device >= dev_count)
-        return fail(nullptr, HS_ERR_HIP, "no such HIP device");
+    const hipError_t derr = hipGetDeviceCount(&dev_count);
+    if (derr != hipSuccess || d.device < 0 || d.device >= dev_count)
+        return fail(nullptr, HS_ERR_HIP, std::string("no such HIP device (hipGetDeviceCount: ") +
+                                             hipGetErrorString(derr) + ", count " + std::to_string(dev_count) +
+                                             ", device " + std::to_string(d.device) + ")");
     hs_ctx* c = new hs_ctx();
     c->desc = d;
     c->nx = d.nx;
@@ -684,6 +687,7 @@ hs_status hs_pd_set_state(hs_ctx* c, const hs_state_ptrs* st) {
     if (st->P) hipMemcpyAsync(c->d.P, st->P, LN, hipMemcpyDeviceToDevice, c->stream);
     if (st->A) hipMemcpyAsync(c->d.A, st->A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
     if (st->v) HS_DISPATCH(c, launch_gather_user<T>(c, (const cplx<T>*)st->v, (cplx<T>*)c->d.v, false));
+    launch_eig_reset(c);   // a new state starts the eigen-solver history afresh (reproducible runs)
     return launched(c, "hs_pd_set_state");
 }
 

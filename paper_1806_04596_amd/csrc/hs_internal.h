@@ -208,6 +208,7 @@ template <typename T> void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T
 // nuclear (k_nuclear.hip)
 template <typename T> void launch_gram(hs_ctx* c, const T* P, const T* Xt);
 void launch_eig(hs_ctx* c, int mode);
+void launch_eig_reset(hs_ctx* c);
 template <typename T> void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2);
 
 // primal and helpers (k_misc.hip)

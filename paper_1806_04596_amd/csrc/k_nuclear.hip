@@ -54,13 +54,14 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* 
         }
         __syncthreads();
     }
-    // D layout of the 16x16 f64 MFMA: lane holds column (lane & 15) and rows 4*(lane>>4) + r.
+    // D layout of the 16x16x4 f64 MFMA (checked on gfx950): lane holds column
+    // (lane & 15) and rows (lane >> 4) + 4 r.
     double* out = part + (size_t)blockIdx.x * MAX_L * MAX_L;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = wave * 16 + 4 * (lane >> 4) + r;
+            const int row = wave * 16 + (lane >> 4) + 4 * r;
             const int col = jb * 16 + (lane & 15);
             out[row * MAX_L + col] = acc[jb][r];
         }
@@ -253,6 +254,14 @@ __global__ __launch_bounds__(256) void k_backproject(const T* __restrict__ in1, 
         out[(size_t)b * N + p] = s;
     }
 }
+
+__global__ void k_eye(double* V) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < MAX_L * MAX_L) V[e] = ((e / MAX_L) == (e % MAX_L)) ? 1.0 : 0.0;
+}
+
+// Forget the eigenvector warm start (next eigen-decomposition starts from I).
+void launch_eig_reset(hs_ctx* c) { k_eye<<<(MAX_L * MAX_L + 255) / 256, 256, 0, c->stream>>>(c->d.eigV); }
 
 template <typename T>
 void launch_gram(hs_ctx* c, const T* P, const T* Xt) {

@@ -17,6 +17,10 @@ def _require_gpu():
     import torch
     if not torch.cuda.is_available():
         raise L.HSError("a HIP device is required (no CPU fallback)")
+    # initialise the HIP runtime and the device context before the library's
+    # first runtime call (counting devices does not initialise it)
+    torch.cuda.init()
+    torch.empty(1, device="cuda").zero_()
     return torch
 
 

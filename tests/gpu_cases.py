@@ -60,3 +60,15 @@ def host(t):
 def split(v, counts):
     off = np.concatenate([[0], np.cumsum(counts)])
     return [v[off[l]:off[l + 1]] for l in range(len(counts))]
+
+
+def check_rel(a, b, tol, what=""):
+    err = rel(a, b)
+    assert err <= tol, f"{what}: rel err {err:.3e} > {tol:.1e}"
+    return err
+
+
+def check_rel_pc(a, b, tol, what=""):
+    err = rel_per_channel(a, b)
+    assert err <= tol, f"{what}: per-channel rel err {err:.3e} > {tol:.1e}"
+    return err

@@ -7,7 +7,7 @@ import pytest
 
 import workloads as W
 from oracle import nufft, pd, prox, wavelets
-from gpu_cases import TOL, gpu_case, host, oracle_case, rel, rel_per_channel, split, to_dev
+from gpu_cases import TOL, check_rel, check_rel_pc, gpu_case, host, oracle_case, rel, rel_per_channel, split, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_phi_adj_parity(name, dtype):
     y = _seeded(prob.M, 2, complex_=True)
     X = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
     ref = op.phi_adj(split(y, prob.counts))
-    assert rel_per_channel(X, ref) <= TOL[dtype]
+    check_rel_pc(X, ref, TOL[dtype], "X")
 
 
 def test_dot_test_f64():
@@ -78,17 +78,17 @@ def test_psi_parity(name, dtype):
     C = host(prob.psi_adj(to_dev(prob, X)))
     ref = wavelets.psi_adj(X)
     for d in range(9):
-        assert rel_per_channel(C[d], ref[d]) <= TOL[dtype], d
+        check_rel_pc(C[d], ref[d], TOL[dtype], "C[d]")
     Cr = _seeded(ref.shape, 6)
     Xs = host(prob.psi(to_dev(prob, Cr)))
-    assert rel_per_channel(Xs, wavelets.psi(Cr)) <= TOL[dtype]
+    check_rel_pc(Xs, wavelets.psi(Cr), TOL[dtype], "Xs")
 
 
 def test_psi_perfect_reconstruction_f64():
     prob, _, _ = gpu_case("t3", "f64")
     X = _seeded((prob.L, prob.ny, prob.nx), 7)
     Xr = host(prob.psi(prob.psi_adj(to_dev(prob, X))))
-    assert rel(Xr, 9.0 * X) <= 1e-13
+    check_rel(Xr, 9.0 * X, 1e-13, "Xr")
 
 
 # ------------------------------------------------------------------ proxes
@@ -102,14 +102,14 @@ def test_prox_l21_and_dual_l21(dtype):
     Ad = to_dev(prob, A)
     out = host(prob.prox_l21(Ad, 0.03, wbar=to_dev(prob, wbar)))
     ref = prox.prox_l21(A, 0.03 * wbar, axis=1)
-    assert rel(out, ref) <= TOL[dtype]
+    check_rel(out, ref, TOL[dtype], "out")
     Xt = inp["X0"] + 0.02 * rng.standard_normal(inp["X0"].shape)
     mu = 0.01
     Ad = to_dev(prob, A)
     Aout, S = prob.dual_l21(Ad, to_dev(prob, Xt), mu, wbar=to_dev(prob, wbar), want_sum=True)
     refA = prox.dual_l21(A, wavelets.psi_adj(Xt), wbar, mu, 9.0)
-    assert rel(host(Aout), refA) <= TOL[dtype]
-    assert rel_per_channel(host(S), wavelets.psi(refA)) <= TOL[dtype]
+    check_rel(host(Aout), refA, TOL[dtype], "host(Aout)")
+    check_rel_pc(host(S), wavelets.psi(refA), TOL[dtype], "host(S)")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -123,12 +123,12 @@ def test_nuclear_parity(name, dtype):
     w = np.sort(rng.uniform(0.0, 0.5 * s_ref[0], cfg.L))
     Xd, sig = prob.prox_nuclear(to_dev(prob, X), w)
     ref, s = prox.prox_nuclear_svd(X, w)
-    assert rel(sig, s) <= TOL[dtype]
-    assert rel(host(Xd), ref) <= TOL[dtype]
+    check_rel(sig, s, TOL[dtype], "sig")
+    check_rel(host(Xd), ref, TOL[dtype], "host(Xd)")
     P = 0.05 * rng.standard_normal(X.shape)
     Pd = prob.dual_nuclear(to_dev(prob, P), to_dev(prob, X), w)
     refP = prox.dual_nuclear(P, X, w, "svd")
-    assert rel(host(Pd), refP) <= TOL[dtype]
+    check_rel(host(Pd), refP, TOL[dtype], "host(Pd)")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -149,9 +149,9 @@ def test_dual_data_parity(name, dtype):
         for b in range(len(bp) - 1):
             s = slice(bp[b], bp[b + 1])
             vr[s], _ = prox.dual_data_block(vbar[s], op.y[l][s], op.u[l][s], op.eps[l][b])
-        assert rel(vg[l], vr) <= TOL[dtype] * 10 if dtype == "f32" else rel(vg[l], vr) <= TOL[dtype]
+        check_rel(vg[l], vr, TOL[dtype] * (10 if dtype == "f32" else 1), f"v[{l}]")
         adj_ref[l] = nufft.phi_adj(vr, op.uv[l], op.theta[l], cfg.ny, cfg.nx)
-    assert rel_per_channel(host(adj), adj_ref) <= (1e-4 if dtype == "f32" else TOL[dtype])
+    check_rel_pc(host(adj), adj_ref, (1e-4 if dtype == "f32" else TOL[dtype]), "host(adj)")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -168,7 +168,7 @@ def test_proj_ellipsoid_parity(dtype):
             zd = to_dev(prob, z, complex_=True)
             prob.proj_ellipsoid(l, b, zd)
             q, _ = prox.proj_ball_precond(z, y, op.u[l][s], op.eps[l][b])
-            assert rel(host(zd), q) <= TOL[dtype]
+            check_rel(host(zd), q, TOL[dtype], "host(zd)")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -179,7 +179,7 @@ def test_op_norm_parity_fixed_iterations(dtype):
     val, per, it = prob.op_norm(to_dev(prob, x0), max_it=40, tol=0.0)
     assert it == 40
     _, ref_per, _ = pd.op_norm_phi(op, x0, max_it=40, tol=0.0)
-    assert rel(per, ref_per) <= TOL[dtype]
+    check_rel(per, ref_per, TOL[dtype], "per")
 
 
 # ------------------------------------------------------------- PD iteration
@@ -212,16 +212,16 @@ def test_pd_one_iteration_parity(name, dtype):
     prmg = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
     g, beta, rho = _run_gpu_iteration(prob, st, prmg, w)
     tol = TOL[dtype]
-    assert rel(g["X"], ref.X) <= tol
-    assert rel(g["Xt"], ref.Xt) <= tol
-    assert rel(g["P"], ref.P) <= tol
-    assert rel(g["A"], ref.A) <= tol
+    check_rel(g["X"], ref.X, tol, "g['X']")
+    check_rel(g["Xt"], ref.Xt, tol, "g['Xt']")
+    check_rel(g["P"], ref.P, tol, "g['P']")
+    check_rel(g["A"], ref.A, tol, "g['A']")
     vg = split(g["v"], prob.counts)
     for l in range(cfg.L):
-        assert rel(vg[l], ref.v[l]) <= tol * (10 if dtype == "f32" else 1)
+        check_rel(vg[l], ref.v[l], tol * (10 if dtype == "f32" else 1), "vg[l]")
     assert abs(beta - ref.beta) <= tol * max(ref.beta, 1e-30) * 10
     rho_ref = np.concatenate(ref.extra["rho"])
-    assert rel(rho, rho_ref) <= tol * 10
+    check_rel(rho, rho_ref, tol * 10, "rho")
 
 
 def test_pd_twenty_iterations_f64():
@@ -235,7 +235,7 @@ def test_pd_twenty_iterations_f64():
     for _ in range(20):
         ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
     g, beta, _ = _run_gpu_iteration(prob, st, prm, w, n=20)
-    assert rel(g["X"], ost.X) <= 1e-11
+    check_rel(g["X"], ost.X, 1e-11, "g['X']")
     assert abs(beta - ost.beta) <= 1e-10 * ost.beta
 
 
@@ -256,7 +256,7 @@ def test_graph_replays_match_oracle_each_time():
         prob.torch.cuda.synchronize()
         _ = host(prob.phi(to_dev(prob, inp["X0"])))   # unrelated eager work between replays
         ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
-        assert rel(got, ost.X) <= 1e-12, k
+        check_rel(got, ost.X, 1e-12, f"replay {k}")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -300,7 +300,7 @@ def test_edge_cases_empty_channel_empty_block_zero_eps():
     Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
     ref = op.phi(X)
     for l in (0, 2):
-        assert rel(Y[l], ref[l]) <= 1e-12
+        check_rel(Y[l], ref[l], 1e-12, "Y[l]")
     assert len(Y[1]) == 0
     v = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
     vd = prob.dual_data(to_dev(prob, v, complex_=True), to_dev(prob, X))
@@ -314,6 +314,6 @@ def test_edge_cases_empty_channel_empty_block_zero_eps():
             if bp[b + 1] == bp[b]:
                 continue
             r, _ = prox.dual_data_block(vbar[s], op.y[l][s], op.u[l][s], op.eps[l][b])
-            assert rel(vg[l][s], r) <= 1e-12
+            check_rel(vg[l][s], r, 1e-12, "vg[l][s]")
     Xa = host(prob.phi_adj(to_dev(prob, v, complex_=True)))
     assert np.all(Xa[1] == 0)

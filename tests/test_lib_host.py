@@ -109,3 +109,13 @@ def test_product_path_refuses_without_gpu():
     with pytest.raises(H.HSError):
         H.Problem(32, 32, [dict(uv=np.zeros((1, 2)), y_raw=np.zeros(1), theta=np.ones(1),
                                 block_ptr=np.array([0, 1]), eps=np.ones(1))])
+
+
+def test_single_hip_runtime_in_process():
+    # the library must share torch's HIP runtime, never load a second one
+    import re
+    from paper_1806_04596_amd import _lib as L
+    L.load()
+    maps = open("/proc/self/maps").read()
+    libs = set(re.findall(r"/\S*libamdhip64\S*", maps))
+    assert len(libs) == 1, libs
