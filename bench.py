@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the HyperSARA primal-dual hot path on one MI355X.
+
+A step is one iteration of Algorithm 2 (all operators: Phi, Phi^dagger, the
+SARA dictionary, the nuclear, l2,1 and data-fidelity duals, the primal update)
+over the whole synthetic 512 x 512 x 60 cube with uneven channels (workload
+"c3"), batched in FP32 and replayed from a captured HIP graph.  Prints one JSON
+line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="c3")
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-channels", type=int, default=3, help="channels of the oracle's CPU sample")
+    p.add_argument("--phase-iters", type=int, default=5)
+    return p.parse_args()
+
+
+def algorithmic_bytes(cfg, M: int, r: int = 4):
+    """Compulsory HBM bytes per iteration of each phase (r = bytes per real).
+
+    N pixels, L channels, c = 2r bytes per complex, K = 4N grid cells per channel.
+    """
+    N, L, D, nb = cfg.N, cfg.L, 9, 8
+    c = 2 * r
+    lev = sum(0.25 ** k for k in range(4))            # fraction of pixels touched over 4 levels
+    return {
+        # read x, write and read the ny compact rows, write the oversampled grid
+        "fft_fwd": L * N * (r + 2 * c + 2 * c + 4 * c),
+        # grid read + per visibility: cell(4) frac(2r) theta(r) u(r) y(c) v(c) bin(4) write v(c)
+        "degrid": L * 4 * N * c + M * (4 + 2 * r + r + r + c + c + 4 + c),
+        "roots": 0,
+        # v read/write, u, bin
+        "dual_apply": M * (2 * c + r + 4),
+        # per visibility cell, frac, v, theta; grid written once
+        "grid": M * (4 + 2 * r + c + r) + L * 4 * N * c,
+        "fft_adj": L * N * (4 * c + 2 * c + 2 * c + r),
+        "gram": 2 * L * N * r,
+        "eig": 0,
+        "backproject": 3 * L * N * r,
+        # per level: read the LL region once per basis and write tmp, read tmp and write coefficients
+        "psi_adj": nb * L * N * r * 4 * lev,
+        # read A (D bases), the 8 analysis outputs and Xt, write A
+        "l21": L * N * r * (D + nb + 1 + D),
+        # per level: read details and LL, write tmp; read tmp, write level output; final sum
+        "psi": nb * L * N * r * 4 * lev + L * N * r * (nb + 2),
+        # read X, P, At, D; write X, Xt
+        "primal": 6 * L * N * r,
+    }
+
+
+def source_hash(*names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1806_04596_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_phase: str, src_file: str):
+    """Measured HBM bytes per iteration for a phase from committed rocprofv3
+    counter summaries (profiles/traffic.json); None if absent or stale."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        ent = t.get(kernel_phase)
+        if not ent or ent.get("src_hash") != source_hash(src_file):
+            return None
+        return ent["bytes_per_iteration"]
+    except Exception:
+        return None
+
+
+PHASE_SRC = {"fft_fwd": "k_nufft.hip", "degrid": "k_nufft.hip", "roots": "k_nufft.hip", "dual_apply": "k_nufft.hip",
+             "grid": "k_nufft.hip", "fft_adj": "k_nufft.hip", "gram": "k_nuclear.hip", "eig": "k_nuclear.hip",
+             "backproject": "k_nuclear.hip", "psi_adj": "k_wavelet.hip", "l21": "k_wavelet.hip",
+             "psi": "k_wavelet.hip", "primal": "k_misc.hip"}
+
+
+def cpu_baseline(cfg, inputs, n_ch: int):
+    """The FP64 oracle, as it stands, timed for one PD iteration on the first
+    n_ch channels of the same workload (single-threaded BLAS), scaled to the
+    full cube's iterations per second."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import workloads as W
+    from oracle import pd
+
+    sub = cfg.scaled(L=n_ch)
+    inp = {"X0": inputs["X0"][:n_ch], "uv": inputs["uv"][:n_ch], "block_ptr": inputs["block_ptr"][:n_ch],
+           "noise": inputs["noise"][:n_ch]}
+    import contextlib
+    lim = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
+    with lim:
+        op, _ = pd.build_problem(sub, inp, "density")
+        st = W.make_state(sub, inp["X0"], [len(u) for u in inp["uv"]])
+        ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                       eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+        prm = pd.Params(mu=0.01, tau=0.33)
+        k3 = 1.0 / (max(len(t) for t in op.theta) * max(float(t.max()) for t in op.theta) ** 2)
+        t0 = time.perf_counter()
+        pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, k3))
+        dt = time.perf_counter() - t0
+    scale = cfg.L / n_ch
+    m_sub = sum(len(u) for u in inp["uv"])
+    return {"value": 1.0 / (dt * scale), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"one PD iteration on channels 0..{n_ch - 1} of {cfg.name} ({m_sub} visibilities) in "
+                      f"{dt:.2f} s, scaled by L/{n_ch} = {scale:.0f} to the full cube"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
+                                   "(see DESIGN.md for how the path would shard)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1806_04596_amd.workload import build_problem
+
+    cfg = W.CONFIGS[args.workload]
+    t_setup = time.perf_counter()
+    inputs = W.make_problem_inputs(cfg)
+    prob, X0, host_data = build_problem(cfg, inputs, W.make_measurements, dtype="f32")
+    info = prob.info()
+    x0 = torch.as_tensor(W.synth.power_start(cfg), dtype=prob.tdtype, device=prob.device).contiguous()
+    nrm, _, it_norm = prob.op_norm(x0, max_it=30, tol=1e-6)
+    kappa3 = 1.0 / nrm
+    mu, tau = 0.01, 0.33
+    prob.pd_init(mu=mu, tau=tau, kappa3=kappa3)
+    setup_s = time.perf_counter() - t_setup
+    stream = prob.stream
+
+    # warm-up (the first call captures one iteration into a HIP graph)
+    prob.iterate(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    prob.iterate(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    value = args.steps / wall
+    beta, _, _ = prob.stats()
+
+    # Phi and Phi^dagger throughput (library stream, HIP events)
+    X = prob.get_state()["X"]
+    Y = prob.phi(X)
+    reps = 10
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            prob.phi(X, Y)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_phi = e0.elapsed_time(e1) / reps / 1e3
+    Xa = prob.empty_cube()
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            prob.phi_adj(Y, Xa)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_adj = e0.elapsed_time(e1) / reps / 1e3
+
+    # per-phase durations (HIP events between phases, same stream, eager launches)
+    phases = prob.profile_phases(args.phase_iters)
+    torch.cuda.synchronize()
+    ab = algorithmic_bytes(cfg, prob.M)
+    dom = max(phases, key=lambda k: phases[k])
+    ach = ab[dom] / (phases[dom] * 1e-3) / 1e9 if ab[dom] > 0 else 0.0
+    traffic = traffic_from_profiles(dom, PHASE_SRC[dom])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": int(ab[dom]), "avg_ms": round(phases[dom], 4)}
+    iter_bytes = sum(ab.values())
+
+    # FP64 comparison: same kernels in FP64 from the FP32 run's current state
+    fp64 = None
+    if not args.no_fp64:
+        st = prob.get_state()
+        torch.cuda.synchronize()
+        del Y, Xa
+        p64, _, _ = build_problem(cfg, inputs, W.make_measurements, dtype="f64")
+        p64.pd_init(mu=mu, tau=tau, kappa3=kappa3)
+        s64 = {k: v.to(torch.complex128 if v.is_complex() else torch.float64) for k, v in st.items()}
+        p64.set_state(**s64)
+        prob.set_state(**st)
+        p64.iterate(1)
+        prob.iterate(1)
+        g32, g64 = prob.get_state()["X"].double(), p64.get_state()["X"]
+        rel = float(torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64))
+        p64.iterate(2)
+        torch.cuda.synchronize()
+        n64 = max(5, args.steps // 5)
+        t0 = time.perf_counter()
+        p64.iterate(n64)
+        torch.cuda.synchronize()
+        v64 = n64 / (time.perf_counter() - t0)
+        fp64 = {"iters_per_s": round(v64, 3), "fp32_speedup": round(value / v64, 3),
+                "one_iter_rel_err_fp32_vs_fp64": rel}
+        del p64
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, inputs, args.cpu_channels)
+
+    out = {
+        "metric": "PD iters/s + Φ/Φ† vis/s, batched FP32 vs plain FP64 at ≤1e-5 rel err",
+        "value": round(value, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4), "gpu_ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} image, L={cfg.L} channels, "
+                               f"{prob.M} visibilities (uneven per channel), {cfg.n_blocks} blocks/channel, "
+                               f"Dirac+db1-db8 x 4 levels, KB 8x8 2x oversampled, FP32 batched graph replay",
+                   "n_vis": prob.M, "tile": info["tile"]},
+        "phi_vis_per_s": round(prob.M / t_phi, 1), "phi_adj_vis_per_s": round(prob.M / t_adj, 1),
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "iteration_algorithmic_GB": round(iter_bytes / 1e9, 3),
+        "iteration_effective_GBs": round(iter_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "beta_last": beta, "op_norm_iters": it_norm, "setup_s": round(setup_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -264,6 +264,29 @@ hs_status hs_pd_iterate(hs_ctx* ctx, int32_t n);
  * (Step 13, host [n_blocks], may be NULL) and bounds eps (host [n_blocks],
  * may be NULL).  Synchronising. */
 hs_status hs_pd_stats(hs_ctx* ctx, double* beta, double* rho, double* eps);
+/* Diagnostics: phases of one iteration, in execution order. */
+enum {
+    HS_PH_FFT_FWD = 0,   /* Z and F of Xt (Step 4) */
+    HS_PH_DEGRID,        /* Theta G and the dual pre-step (Step 10), per-run FP64 sums */
+    HS_PH_ROOTS,         /* per-bin sums and per-block projection roots (Steps 11, 13-19) */
+    HS_PH_DUAL_APPLY,    /* v update (Step 11) */
+    HS_PH_GRID,          /* G^T Theta^T v (Step 12) */
+    HS_PH_FFT_ADJ,       /* F^H and Z^T, real part (Step 20 data term) */
+    HS_PH_GRAM,          /* L x L Gram of P + Xt (Step 5) */
+    HS_PH_EIG,           /* FP64 eigen-decomposition and W (Step 5) */
+    HS_PH_BACKPROJ,      /* P <- (P + Xt) W (Step 5) */
+    HS_PH_PSI_ADJ,       /* Psi^dagger Xt (Step 7) */
+    HS_PH_L21,           /* l2,1 dual update (Step 7) */
+    HS_PH_PSI,           /* sum_d Psi_d A_d (Steps 8, 20) */
+    HS_PH_PRIMAL,        /* Steps 20-23 */
+    HS_NPHASES
+};
+/* Runs n eager iterations of Algorithm 2 with HIP events between the phases
+ * above (on the context stream) and returns the mean duration of each phase in
+ * milliseconds in times_ms[HS_NPHASES].  Advances the state like hs_pd_iterate.
+ * Synchronising. */
+hs_status hs_profile_phases(hs_ctx* ctx, int32_t n, double* times_ms);
+
 /* Algorithm 1 on the current state; X_out (device real [L][ny][nx], may be NULL). */
 hs_status hs_solve(hs_ctx* ctx, const hs_solve_params* params, void* X_out, hs_report* report);
 

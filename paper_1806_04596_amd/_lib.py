@@ -88,7 +88,11 @@ SIGNATURES = {
     "hs_pd_iterate": (C.c_int32, [ctxp, C.c_int32]),
     "hs_pd_stats": (C.c_int32, [ctxp, dptr, dptr, dptr]),
     "hs_solve": (C.c_int32, [ctxp, C.POINTER(SolveParams), P, C.POINTER(Report)]),
+    "hs_profile_phases": (C.c_int32, [ctxp, C.c_int32, dptr]),
 }
+
+PHASES = ["fft_fwd", "degrid", "roots", "dual_apply", "grid", "fft_adj", "gram", "eig", "backproject", "psi_adj",
+          "l21", "psi", "primal"]
 
 _lib = None
 

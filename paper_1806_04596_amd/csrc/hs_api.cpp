@@ -200,44 +200,71 @@ static void phi_adj_impl(hs_ctx* c, const cplx<T>* Y, T* X) {
     adj_from_grid_order<T>(c, (const cplx<T>*)c->d.vwork, nullptr, X);
 }
 
+// Event hook between the phases of one iteration (diagnostics only).
+struct PhaseMarks {
+    hipEvent_t* ev = nullptr;
+    void mark(hs_ctx* c, int k) const {
+        if (ev) (void)hipEventRecord(ev[k], c->stream);
+    }
+};
+
 // Steps 4, 10, 11 on dual v (grid order, in place); Step 12 + F^H Z^T into adj if given.
 template <typename T>
-static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj) {
+static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const PhaseMarks& pm = PhaseMarks()) {
     launch_fft_rows_fwd<T>(c, Xt, c->L);
     launch_fft_cols_fwd<T>(c, c->L);
+    pm.mark(c, HS_PH_FFT_FWD + 1);
     launch_degrid_dual_v<T>(c, v);
+    pm.mark(c, HS_PH_DEGRID + 1);
     launch_bins_and_roots<T>(c);
+    pm.mark(c, HS_PH_ROOTS + 1);
     launch_dual_apply_v<T>(c, v);
-    if (adj) adj_from_grid_order<T>(c, v, (const T*)c->d.vis_theta, adj);
+    pm.mark(c, HS_PH_DUAL_APPLY + 1);
+    if (adj) {
+        launch_grid_pull<T>(c, v, (const T*)c->d.vis_theta);
+        pm.mark(c, HS_PH_GRID + 1);
+        launch_fft_cols_adj<T>(c, c->L);
+        launch_fft_rows_adj<T>(c, adj, c->L);
+        pm.mark(c, HS_PH_FFT_ADJ + 1);
+    }
 }
 
 template <typename T>
-static void dual_nuclear_impl(hs_ctx* c, T* P, const T* Xt) {
+static void dual_nuclear_impl(hs_ctx* c, T* P, const T* Xt, const PhaseMarks& pm = PhaseMarks()) {
     launch_gram<T>(c, P, Xt);
+    pm.mark(c, HS_PH_GRAM + 1);
     launch_eig(c, 0);
+    pm.mark(c, HS_PH_EIG + 1);
     launch_backproject<T>(c, P, P, Xt);
+    pm.mark(c, HS_PH_BACKPROJ + 1);
 }
 
 template <typename T>
-static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu, T* At_sum) {
+static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu, T* At_sum,
+                          const PhaseMarks& pm = PhaseMarks()) {
     launch_psi_adj<T>(c, Xt, nullptr);
+    pm.mark(c, HS_PH_PSI_ADJ + 1);
     launch_l21_dual<T>(c, A, Xt, (const T*)c->d.coef, wbar, mu * (double)c->D, 0);
+    pm.mark(c, HS_PH_L21 + 1);
     if (At_sum) launch_psi_sum<T>(c, A + (size_t)c->L * c->N, A, At_sum);
+    pm.mark(c, HS_PH_PSI + 1);
 }
 
 // One iteration of Algorithm 2 on the context state.
 template <typename T>
-static void pd_iter_impl(hs_ctx* c) {
+static void pd_iter_impl(hs_ctx* c, const PhaseMarks& pm = PhaseMarks()) {
     Dev& d = c->d;
     T* Xt = (T*)d.Xt;
+    pm.mark(c, 0);
     // data fidelity (Steps 3-4, 9-12) -> img0 = Re Phi^dag v
-    dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0);
+    dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0, pm);
     // low rankness (Step 5)
-    dual_nuclear_impl<T>(c, (T*)d.P, Xt);
+    dual_nuclear_impl<T>(c, (T*)d.P, Xt, pm);
     // joint average sparsity (Steps 6-8) -> img1 = sum_d Psi_d A_d
-    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
+    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1, pm);
     // primal (Steps 20-23)
     launch_primal<T>(c, (const T*)d.img1, (const T*)d.img0);
+    pm.mark(c, HS_PH_PRIMAL + 1);
 }
 
 template <typename T>
@@ -741,6 +768,33 @@ hs_status hs_pd_iterate(hs_ctx* c, int32_t n) {
         if (s) return s;
     }
     c->t_iter += n;
+    return HS_OK;
+}
+
+hs_status hs_profile_phases(hs_ctx* c, int32_t n, double* times_ms) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
+    if (n < 1 || !times_ms) return fail(c, HS_ERR_INVALID_ARG, "bad profile arguments");
+    hipEvent_t ev[HS_NPHASES + 1];
+    for (int k = 0; k <= HS_NPHASES; ++k)
+        if ((s = hip_check(c, hipEventCreate(&ev[k]), "hipEventCreate"))) return s;
+    std::vector<double> acc(HS_NPHASES, 0.0);
+    PhaseMarks pm;
+    pm.ev = ev;
+    for (int it = 0; it < n && !s; ++it) {
+        HS_DISPATCH(c, pd_iter_impl<T>(c, pm));
+        s = hip_check(c, hipStreamSynchronize(c->stream), "hs_profile_phases");
+        for (int k = 0; k < HS_NPHASES && !s; ++k) {
+            float ms = 0.f;
+            s = hip_check(c, hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
+            acc[k] += ms;
+        }
+    }
+    for (int k = 0; k <= HS_NPHASES; ++k) (void)hipEventDestroy(ev[k]);
+    if (s) return s;
+    c->t_iter += n;
+    for (int k = 0; k < HS_NPHASES; ++k) times_ms[k] = acc[k] / n;
     return HS_OK;
 }
 

@@ -42,8 +42,13 @@ struct SplitTile {
     int32_t l, tile, partial, nsplit;
 };
 
+// Terms of the kernel polynomial per precision (rounding-level accuracy).
+template <typename T> struct KBTerms;
+template <> struct KBTerms<float> { static constexpr int n = 13; };
+template <> struct KBTerms<double> { static constexpr int n = 20; };
+
 template <typename T>
-struct KBPoly {                 // phi(d) = sum_k c[k] w^k, w = 1 - (2d/J)^2
+struct KBPoly {                 // phi(d) = sum_k c[k] s^k, s = 1 - d^2/8 = 2(1 - (2d/J)^2) - 1
     T c[KB_MAX_TERMS];
     int n;
 };
@@ -176,6 +181,7 @@ namespace hs {
 hs_status fail(hs_ctx* c, hs_status s, const std::string& msg);
 hs_status hip_check(hs_ctx* c, hipError_t e, const char* what);
 void kb_series(int terms_for_bits, std::vector<double>& coef, double& beta);
+void kb_chebyshev(int terms, std::vector<double>& coef);
 int kb_terms_needed(int mantissa_bits);
 double kb_ft(double xi);
 void daubechies_host(int K, double* h);

@@ -57,6 +57,55 @@ void kb_series(int terms, std::vector<double>& coef, double& beta) {
     beta = (double)b;
 }
 
+// Chebyshev interpolant of phi as a function of s = 2w - 1 on [-1, 1]
+// (w = 1 - (2d/J)^2), converted to monomial coefficients in s.  phi is the
+// entire function I0(beta sqrt(w))/I0(beta) of w, so the interpolant converges
+// geometrically; every coefficient comes out positive (stable Horner).
+void kb_chebyshev(int terms, std::vector<double>& coef) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double b = kb_beta_ld();
+    std::vector<long double> t;
+    i0_terms(b, t, 200);
+    const long double I0 = i0_of_beta();
+    auto phi_w = [&](long double w) {
+        long double acc = 0.0L;
+        for (int k = 199; k >= 0; --k) acc = acc * w + t[k];
+        return acc / I0;
+    };
+    const int n = terms;
+    std::vector<long double> cc(n, 0.0L);
+    for (int j = 0; j < n; ++j) {
+        long double sum = 0.0L;
+        for (int k = 0; k < n; ++k) {
+            const long double th = pi * ((long double)k + 0.5L) / (long double)n;
+            const long double sk = std::cos(th);
+            sum += phi_w(0.5L * (sk + 1.0L)) * std::cos((long double)j * th);
+        }
+        cc[j] = sum * 2.0L / (long double)n;
+    }
+    cc[0] *= 0.5L;
+    // Chebyshev -> monomial in s: T_0 = 1, T_1 = s, T_{j+1} = 2 s T_j - T_{j-1}
+    std::vector<long double> m(n, 0.0L), Tm1(n, 0.0L), T0(n, 0.0L), T1(n, 0.0L);
+    T0[0] = 1.0L;
+    m[0] += cc[0];
+    if (n > 1) {
+        T1[1] = 1.0L;
+        m[1] += cc[1];
+    }
+    for (int j = 2; j < n; ++j) {
+        std::vector<long double> Tn(n, 0.0L);
+        for (int k = 0; k < n; ++k) {
+            if (k + 1 < n) Tn[k + 1] += 2.0L * T1[k];
+            Tn[k] -= T0[k];
+        }
+        for (int k = 0; k < n; ++k) m[k] += cc[j] * Tn[k];
+        T0 = T1;
+        T1 = Tn;
+    }
+    coef.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) coef[k] = (double)m[k];
+}
+
 // Continuous Fourier transform of the normalised kernel (closed form).
 double kb_ft(double xi) {
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -382,10 +431,9 @@ hs_status build_plan(hs_ctx* c) {
         std::vector<int32_t> fillp(c->h_bin_run_ptr.begin(), c->h_bin_run_ptr.end() - 1);
         for (auto& pr : run_bin) c->h_bin_runs[fillp[pr.first]++] = pr.second;
     }
-    // kernel series
-    c->kb_terms = kb_terms_needed(c->dtype == HS_F64 ? 53 : 24);
-    double beta;
-    kb_series(c->kb_terms, c->kb_c, beta);
+    // kernel polynomial (Chebyshev interpolant, rounding-level accurate)
+    c->kb_terms = c->dtype == HS_F64 ? KBTerms<double>::n : KBTerms<float>::n;
+    kb_chebyshev(c->kb_terms, c->kb_c);
     return HS_OK;
 }
 

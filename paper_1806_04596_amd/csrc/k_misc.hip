@@ -57,18 +57,25 @@ __global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict
     }
 }
 
-// beta (Step 23) into scal[0]; iteration counter scal[1] += 1.
+// beta (Step 23) into scal[0]; iteration counter scal[1] += 1.  One wave:
+// lane-strided partial sums, then a fixed butterfly (deterministic).
 __global__ void k_finish_beta(const double* __restrict__ part, double* __restrict__ scal, int nparts) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int lane = threadIdx.x;
     double dd = 0.0, xx = 0.0;
-    for (int k = 0; k < nparts; ++k) {
+    for (int k = lane; k < nparts; k += 64) {
         dd += part[2 * k];
         xx += part[2 * k + 1];
     }
-    scal[0] = (xx > 0.0) ? sqrt(dd / xx) : 0.0;
-    scal[1] += 1.0;
-    scal[2] = dd;
-    scal[3] = xx;
+    for (int off = 32; off > 0; off >>= 1) {
+        dd += __shfl_xor(dd, off);
+        xx += __shfl_xor(xx, off);
+    }
+    if (lane == 0) {
+        scal[0] = (xx > 0.0) ? sqrt(dd / xx) : 0.0;
+        scal[1] += 1.0;
+        scal[2] = dd;
+        scal[3] = xx;
+    }
 }
 
 // Per-channel sums of squares: part[l][chunk].

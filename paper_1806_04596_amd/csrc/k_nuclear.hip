@@ -71,9 +71,15 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* 
 __global__ void k_gram_reduce(const double* __restrict__ part, double* __restrict__ C, int nparts) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= MAX_L * MAX_L) return;
-    double s = 0.0;
-    for (int k = 0; k < nparts; ++k) s += part[(size_t)k * MAX_L * MAX_L + e];
-    C[e] = s;
+    // eight independent partial sums (fixed assignment), then a fixed combine
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= nparts; k += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += part[(size_t)(k + j) * MAX_L * MAX_L + e];
+    }
+    for (; k < nparts; ++k) s[k & 7] += part[(size_t)k * MAX_L * MAX_L + e];
+    C[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // ------------------------------------------------------------------ Jacobi
@@ -133,6 +139,16 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
         }
         __syncthreads();
     }
+    __shared__ double tr_sh;
+    if (tid == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) tr += fabs(A[i][i]);
+        tr_sh = tr;
+    }
+    __syncthreads();
+    // rotations below this size are rounding noise (rank-deficient Grams have
+    // near-zero diagonals where a purely relative test never stops)
+    const double floor_abs = 1e-18 * tr_sh;
     const int half = n / 2;
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (tid == 0) rotated = 0;
@@ -151,7 +167,7 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
                 if (p > q) { const int t = p; p = q; q = t; }
                 const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
                 double c = 1.0, s = 0.0;
-                if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
                     const double th = (aqq - app) / (2.0 * apq);
                     const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                     c = 1.0 / sqrt(t * t + 1.0);

@@ -321,13 +321,17 @@ void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
 }
 
 // ------------------------------------------------------------- KB kernel
-// phi(d) = I0(beta sqrt(1 - (d/4)^2)) / I0(beta) as its power series in
-// w = 1 - (d/4)^2 (all coefficients positive: no cancellation).
+// phi(d) = I0(beta sqrt(1 - (d/4)^2)) / I0(beta) through its Chebyshev
+// interpolant in s = 1 - d^2/8 (coefficients from the plan, all positive),
+// evaluated by Horner with a compile-time number of terms so the coefficients
+// stay in scalar registers.
 template <typename T>
 __device__ __forceinline__ T kb_eval(T d, const KBPoly<T>& P) {
-    const T w = T(1) - d * d * T(0.0625);
-    T acc = P.c[P.n - 1];
-    for (int k = P.n - 2; k >= 0; --k) acc = acc * w + P.c[k];
+    constexpr int NT = KBTerms<T>::n;
+    const T s = T(1) - d * d * T(0.125);
+    T acc = P.c[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) acc = acc * s + P.c[k];
     return acc;
 }
 
@@ -599,6 +603,15 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 }
 
 // ---------------------------------------------------------- gridding (pull)
+// One wave owns the T x T core of a tile (accumulator in LDS, rows padded to
+// T + GR_PAD cells so the 8 rows of a footprint fall in different banks).
+// Visibilities are consumed in batches of 64: first lane i computes the 8 + 8
+// kernel values of visibility i into LDS; then the wave walks the batch one
+// visibility at a time with lane (jx, jy) owning tap (jx, jy).  The 64 taps of
+// one visibility are 64 distinct cells, so each lane does a plain LDS
+// read-modify-write: no atomics, and the summation order is fixed.
+constexpr int GR_PAD = 8;
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
     const GridUnit* __restrict__ units, const int32_t* __restrict__ granges, const int32_t* __restrict__ cell,
@@ -606,11 +619,14 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x, int ntiles,
     KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
-    T* accR = reinterpret_cast<T*>(smem_raw);
-    T* accI = accR + TT * TT;
+    const int TS = TT + GR_PAD;
+    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);        // [TT][TS]
+    T* wts = reinterpret_cast<T*>(acc + TT * TS);                // [64][16]
+    cplx<T>* vv = reinterpret_cast<cplx<T>*>(wts + 64 * 16);     // [64]
+    int* rel = reinterpret_cast<int*>(vv + 64);                  // [64] packed tap origin
     const GridUnit u = units[blockIdx.x];
     const int lane = threadIdx.x;
-    for (int e = lane; e < TT * TT; e += 64) { accR[e] = T(0); accI[e] = T(0); }
+    for (int e = lane; e < TT * TS; e += 64) acc[e] = {T(0), T(0)};
     const int32_t* rg = granges + ((size_t)u.l * ntiles + u.tile) * (2 * N_GRANGES);
     int pref[N_GRANGES + 1];
     pref[0] = 0;
@@ -620,9 +636,10 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     const int e0 = (int)(((int64_t)u.split * E) / u.nsplit);
     const int e1 = (int)(((int64_t)(u.split + 1) * E) / u.nsplit);
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    __syncthreads();
+    const int jx = lane & 7, jy = lane >> 3;
     for (int base = e0; base < e1; base += 64) {
         const int e = base + lane;
+        int packed = (int)(0x8000u << 16);   // sentinel: every tap falls outside the core
         if (e < e1) {
             int r = 0;
 #pragma unroll
@@ -641,34 +658,46 @@ __global__ __launch_bounds__(64) void k_grid_pull(
                 val.re *= w;
                 val.im *= w;
             }
-            T wx[KB_J], wy[KB_J];
-            kb_weights(f.re, kb, wx);
-            kb_weights(f.im, kb, wy);
+            T w8[KB_J];
+            kb_weights(f.re, kb, w8);
 #pragma unroll
-            for (int jy = 0; jy < KB_J; ++jy) {
-                const int ry = rely - 3 + jy;
-                if (ry < 0 || ry >= TT) continue;
-                const T vr = wy[jy] * val.re, vi = wy[jy] * val.im;
+            for (int j = 0; j < KB_J; ++j) wts[lane * 16 + j] = w8[j];
+            kb_weights(f.im, kb, w8);
 #pragma unroll
-                for (int jx = 0; jx < KB_J; ++jx) {
-                    const int rx = relx - 3 + jx;
-                    if (rx < 0 || rx >= TT) continue;
-                    atomicAdd(&accR[ry * TT + rx], vr * wx[jx]);
-                    atomicAdd(&accI[ry * TT + rx], vi * wx[jx]);
-                }
+            for (int j = 0; j < KB_J; ++j) wts[lane * 16 + 8 + j] = w8[j];
+            vv[lane] = val;
+            packed = ((rely - 3) << 16) | ((relx - 3) & 0xFFFF);
+        }
+        rel[lane] = packed;
+        __syncthreads();
+        const int nv = min(64, e1 - base);
+        for (int v = 0; v < nv; ++v) {
+            const int pk = rel[v];
+            const int ry = (pk >> 16) + jy;
+            const int rx = (int)(short)(pk & 0xFFFF) + jx;
+            if (ry >= 0 && ry < TT && rx >= 0 && rx < TT) {
+                const T w = wts[v * 16 + jx] * wts[v * 16 + 8 + jy];
+                const cplx<T> val = vv[v];
+                cplx<T> a = acc[ry * TS + rx];
+                a.re += w * val.re;
+                a.im += w * val.im;
+                acc[ry * TS + rx] = a;
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     if (u.nsplit == 1) {
         cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
         for (int e = lane; e < TT * TT; e += 64) {
             const int ry = e / TT, rx = e - ry * TT;
-            g[(size_t)(oy + ry) * Kx + ox + rx] = {accR[e], accI[e]};
+            g[(size_t)(oy + ry) * Kx + ox + rx] = acc[ry * TS + rx];
         }
     } else {
         cplx<T>* p = partial + (size_t)(u.partial + u.split) * TT * TT;
-        for (int e = lane; e < TT * TT; e += 64) p[e] = {accR[e], accI[e]};
+        for (int e = lane; e < TT * TT; e += 64) {
+            const int ry = e / TT, rx = e - ry * TT;
+            p[e] = acc[ry * TS + rx];
+        }
     }
 }
 
@@ -786,8 +815,8 @@ __global__ __launch_bounds__(256) void k_proj_block(cplx<T>* __restrict__ z, con
 template <typename T>
 static KBPoly<T> kbpoly(const hs_ctx* c) {
     KBPoly<T> p{};
-    p.n = c->kb_terms;
-    for (int k = 0; k < c->kb_terms; ++k) p.c[k] = (T)c->kb_c[k];
+    p.n = KBTerms<T>::n;
+    for (int k = 0; k < p.n; ++k) p.c[k] = (T)c->kb_c[k];
     return p;
 }
 
@@ -842,7 +871,8 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
 
 template <typename T>
 void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    const size_t lds = (size_t)2 * c->T * c->T * sizeof(T);
+    const size_t lds = (size_t)c->T * (c->T + GR_PAD) * sizeof(cplx<T>) + 64 * 16 * sizeof(T) +
+                       64 * sizeof(cplx<T>) + 64 * sizeof(int);
     k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
         c->d.gunits, c->d.granges, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
         (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, c->ntiles, kbpoly<T>(c));

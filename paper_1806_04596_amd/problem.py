@@ -242,6 +242,11 @@ class Problem:
     def iterate(self, n=1):
         self._call("hs_pd_iterate", self.lib.hs_pd_iterate, int(n))
 
+    def profile_phases(self, n=5):
+        t = np.zeros(len(L.PHASES))
+        self._call("hs_profile_phases", self.lib.hs_profile_phases, int(n), L.as_dptr(t))
+        return dict(zip(L.PHASES, t.tolist()))
+
     def stats(self):
         nb = int(sum(self.nblocks))
         beta = C.c_double()
