@@ -172,6 +172,7 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = args.steps / wall
     beta, _, _ = prob.stats()
+    dg = prob.diag()
 
     # Phi and Phi^dagger throughput (library stream, HIP events)
     X = prob.get_state()["X"]
@@ -252,7 +253,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": fp64,
-        "beta_last": beta, "op_norm_iters": it_norm, "setup_s": round(setup_s, 1),
+        "beta_last": beta, "eig_sweeps_last": dg["eig_sweeps"], "op_norm_iters": it_norm,
+        "setup_s": round(setup_s, 1),
     }
     print(json.dumps(out), flush=True)
 

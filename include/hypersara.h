@@ -287,6 +287,12 @@ enum {
  * Synchronising. */
 hs_status hs_profile_phases(hs_ctx* ctx, int32_t n, double* times_ms);
 
+/* Diagnostics: out[0] = beta of the last iteration, out[1] = iterations run on
+ * the device counter, out[2] = Jacobi sweeps of the last eigen-decomposition,
+ * out[3] = iterations issued by the host; n = number of values wanted (<= 4).
+ * Synchronising. */
+hs_status hs_get_diag(hs_ctx* ctx, double* out, int32_t n);
+
 /* Algorithm 1 on the current state; X_out (device real [L][ny][nx], may be NULL). */
 hs_status hs_solve(hs_ctx* ctx, const hs_solve_params* params, void* X_out, hs_report* report);
 

@@ -89,6 +89,7 @@ SIGNATURES = {
     "hs_pd_stats": (C.c_int32, [ctxp, dptr, dptr, dptr]),
     "hs_solve": (C.c_int32, [ctxp, C.POINTER(SolveParams), P, C.POINTER(Report)]),
     "hs_profile_phases": (C.c_int32, [ctxp, C.c_int32, dptr]),
+    "hs_get_diag": (C.c_int32, [ctxp, dptr, C.c_int32]),
 }
 
 PHASES = ["fft_fwd", "degrid", "roots", "dual_apply", "grid", "fft_adj", "gram", "eig", "backproject", "psi_adj",

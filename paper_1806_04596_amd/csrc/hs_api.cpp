@@ -250,6 +250,30 @@ static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu
     pm.mark(c, HS_PH_PSI + 1);
 }
 
+// One iteration of Algorithm 2 as three independent branches (data fidelity,
+// low rankness, joint sparsity) joined before the primal update; used for the
+// captured graph so the branches overlap on the device.
+template <typename T>
+static void pd_iter_forked(hs_ctx* c) {
+    Dev& d = c->d;
+    T* Xt = (T*)d.Xt;
+    hipStream_t main = c->stream;
+    (void)hipEventRecord(c->ev_fork, main);
+    (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0);
+    (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0);
+    c->stream = c->side[0];
+    dual_nuclear_impl<T>(c, (T*)d.P, Xt);
+    (void)hipEventRecord(c->ev_join[0], c->side[0]);
+    c->stream = c->side[1];
+    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
+    (void)hipEventRecord(c->ev_join[1], c->side[1]);
+    c->stream = main;
+    dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0);
+    (void)hipStreamWaitEvent(main, c->ev_join[0], 0);
+    (void)hipStreamWaitEvent(main, c->ev_join[1], 0);
+    launch_primal<T>(c, (const T*)d.img1, (const T*)d.img0);
+}
+
 // One iteration of Algorithm 2 on the context state.
 template <typename T>
 static void pd_iter_impl(hs_ctx* c, const PhaseMarks& pm = PhaseMarks()) {
@@ -404,6 +428,11 @@ hs_status hs_destroy(hs_ctx* c) {
     if (!c) return HS_ERR_INVALID_ARG;
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
+    for (int k = 0; k < 2; ++k) {
+        if (c->side[k]) hipStreamDestroy(c->side[k]);
+        if (c->ev_join[k]) hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
     delete c;
     return HS_OK;
 }
@@ -734,9 +763,17 @@ hs_status hs_pd_get_state(hs_ctx* c, const hs_state_ptrs* st) {
 static hs_status pd_capture(hs_ctx* c) {
     if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
     if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
-    hs_status s = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
+    hs_status s = HS_OK;
+    for (int k = 0; k < 2 && !s; ++k) {
+        if (!c->side[k]) s = hip_check(c, hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking), "side stream");
+        if (!s && !c->ev_join[k])
+            s = hip_check(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming), "join event");
+    }
+    if (!s && !c->ev_fork) s = hip_check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
     if (s) return s;
-    HS_DISPATCH(c, pd_iter_impl<T>(c));
+    s = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
+    if (s) return s;
+    HS_DISPATCH(c, pd_iter_forked<T>(c));
     hipError_t le = hipGetLastError();
     s = hip_check(c, hipStreamEndCapture(c->stream, &c->graph), "end capture");
     if (s) return s;
@@ -815,6 +852,20 @@ hs_status hs_pd_stats(hs_ctx* c, double* beta, double* rho, double* eps) {
     if (rho)
         for (int64_t b = 0; b < c->nblk; ++b) rho[b] = std::sqrt(r2[b]);
     if (eps) std::copy(ep.begin(), ep.end(), eps);
+    return HS_OK;
+}
+
+hs_status hs_get_diag(hs_ctx* c, double* out, int32_t n) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!out || n < 1) return fail(c, HS_ERR_INVALID_ARG, "bad diag arguments");
+    double sc[16];
+    s = hip_check(c, hipMemcpyAsync(sc, c->d.scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream), "diag");
+    if (s) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_get_diag");
+    if (s) return s;
+    const double vals[4] = {sc[0], sc[1], sc[8], (double)c->t_iter};
+    for (int k = 0; k < n && k < 4; ++k) out[k] = vals[k];
     return HS_OK;
 }
 

@@ -172,6 +172,8 @@ struct hs_ctx {
     std::vector<double> w_host;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipStream_t side[2] = {nullptr, nullptr};   // fork/join branches of the captured iteration
+    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
     bool graph_valid = false;
 };
 

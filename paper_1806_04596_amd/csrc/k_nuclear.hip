@@ -89,7 +89,8 @@ __global__ void k_gram_reduce(const double* __restrict__ part, double* __restric
 template <typename TW>
 __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, double* __restrict__ Vg,
                                              double* __restrict__ sig_out, const double* __restrict__ w,
-                                             TW* __restrict__ Wout, int L, int mode, int warm) {
+                                             TW* __restrict__ Wout, int L, int mode, int warm,
+                                             double* __restrict__ diag) {
     __shared__ double A[MAX_L][MAX_L + 1];
     __shared__ double V[MAX_L][MAX_L + 1];
     __shared__ double Tm[MAX_L][MAX_L + 1];
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
         __syncthreads();
     }
     __shared__ double tr_sh;
+    __shared__ int sweeps_done;
     if (tid == 0) {
         double tr = 0.0;
         for (int i = 0; i < n; ++i) tr += fabs(A[i][i]);
@@ -150,8 +152,10 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
     // near-zero diagonals where a purely relative test never stops)
     const double floor_abs = 1e-18 * tr_sh;
     const int half = n / 2;
+    __shared__ double maxrel_sh[MAX_L / 2];
     for (int sweep = 0; sweep < 60; ++sweep) {
         if (tid == 0) rotated = 0;
+        double sweep_max = 0.0;   // largest |a_pq| / sqrt(a_pp a_qq) rotated in this sweep (thread < half)
         __syncthreads();
         for (int round = 0; round < n - 1; ++round) {
             if (tid < half) {
@@ -166,45 +170,59 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
                 }
                 if (p > q) { const int t = p; p = q; q = t; }
                 const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+                const double den = sqrt(fabs(app * aqq));
                 double c = 1.0, s = 0.0;
-                if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * den) {
                     const double th = (aqq - app) / (2.0 * apq);
                     const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                     c = 1.0 / sqrt(t * t + 1.0);
                     s = t * c;
                     rotated = 1;
+                    sweep_max = fmax(sweep_max, den > 0.0 ? fabs(apq) / den : 1.0);
                 }
                 cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int e = tid; e < half * n; e += 256) {
-                const int k = e / n, i = e - k * n;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                const double aip = A[i][p], aiq = A[i][q];
-                A[i][p] = c * aip - s * aiq;
-                A[i][q] = s * aip + c * aiq;
-                const double vip = V[i][p], viq = V[i][q];
-                V[i][p] = c * vip - s * viq;
-                V[i][q] = s * vip + c * viq;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < half * n; e += 256) {
-                const int k = e / n, j = e - k * n;
-                const int p = pp[k], q = qq[k];
-                const double c = cs[k], s = sn[k];
-                const double apj = A[p][j], aqj = A[q][j];
-                A[p][j] = c * apj - s * aqj;
-                A[q][j] = s * apj + c * aqj;
+            // A <- J^T A J as independent 2x2 blocks B(k, m) <- R_k^T B R_m, and V <- V J;
+            // every entry is read and written by one thread (no intermediate barrier)
+            for (int e = tid; e < half * half + half * n; e += 256) {
+                if (e < half * half) {
+                    const int k = e / half, m = e - k * half;
+                    const int pk = pp[k], qk = qq[k], pm = pp[m], qm = qq[m];
+                    const double ck = cs[k], sk = sn[k], cm = cs[m], sm = sn[m];
+                    const double b00 = A[pk][pm], b01 = A[pk][qm], b10 = A[qk][pm], b11 = A[qk][qm];
+                    // columns (right multiply by R_m)
+                    const double c00 = cm * b00 - sm * b01, c01 = sm * b00 + cm * b01;
+                    const double c10 = cm * b10 - sm * b11, c11 = sm * b10 + cm * b11;
+                    // rows (left multiply by R_k^T)
+                    double d00 = ck * c00 - sk * c10, d01 = ck * c01 - sk * c11;
+                    double d10 = sk * c00 + ck * c10, d11 = sk * c01 + ck * c11;
+                    if (k == m && sk != 0.0) { d01 = 0.0; d10 = 0.0; }   // the rotated pair is exactly zeroed
+                    A[pk][pm] = d00; A[pk][qm] = d01; A[qk][pm] = d10; A[qk][qm] = d11;
+                } else {
+                    const int f = e - half * half;
+                    const int m = f / n, i = f - m * n;
+                    const int pm = pp[m], qm = qq[m];
+                    const double cm = cs[m], sm = sn[m];
+                    const double vip = V[i][pm], viq = V[i][qm];
+                    V[i][pm] = cm * vip - sm * viq;
+                    V[i][qm] = sm * vip + cm * viq;
+                }
             }
             __syncthreads();
         }
+        if (tid < half) maxrel_sh[tid] = sweep_max;
         const int any = rotated;   // every thread reads before anyone resets it
         __syncthreads();
-        if (!any) break;
+        double mr = 0.0;
+        for (int k = 0; k < half; ++k) mr = fmax(mr, maxrel_sh[k]);
+        __syncthreads();
+        if (tid == 0) sweeps_done = sweep + 1;
+        // Jacobi converges quadratically: after a sweep whose rotations were all
+        // below 1e-8 (relative) the next one would only rotate rounding noise.
+        if (!any || mr < 1e-8) break;
     }
+    if (tid == 0 && diag) diag[0] = (double)sweeps_done;
     // sort eigenvalues in decreasing order (rank by comparison, ties by index)
     if (tid < n) lam[tid] = A[tid][tid];
     __syncthreads();
@@ -292,10 +310,10 @@ void launch_eig(hs_ctx* c, int mode) {
     const int warm = 1;  // eigV starts as the identity, so the first call is a cold start
     if (c->dtype == HS_F32)
         k_eig<float><<<1, 256, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (float*)c->d.Wmat,
-                                               c->L, mode, warm);
+                                               c->L, mode, warm, c->d.scal + 8);
     else
         k_eig<double><<<1, 256, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (double*)c->d.Wmat,
-                                                c->L, mode, warm);
+                                                c->L, mode, warm, c->d.scal + 8);
 }
 
 template <typename T>

@@ -11,107 +11,187 @@
 namespace hs {
 
 // filt: [n_db][2][16] (h then g, zero padded), basis b = db(b+1) with 2(b+1) taps.
-template <typename T>
-__global__ void k_dwt_rows(const T* __restrict__ X, const T* __restrict__ srcb, T* __restrict__ dst,
-                           const T* __restrict__ filt, int L, int nx, int ny, int mx, int my, int from_x) {
-    const int half = mx >> 1;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= my * half) return;
-    const int l = blockIdx.y, b = blockIdx.z;
-    const size_t N = (size_t)nx * ny;
-    const int r = e / half, k = e - r * half;
-    const T* s = (from_x ? X + (size_t)l * N : srcb + ((size_t)b * L + l) * N) + (size_t)r * nx;
-    const T* h = filt + b * 32;
-    const T* g = h + 16;
-    const int taps = 2 * (b + 1);
-    T a = T(0), d = T(0);
-    int idx = (2 * k) % mx;
-    for (int j = 0; j < taps; ++j) {
-        const T x = s[idx];
-        a += h[j] * x;
-        d += g[j] * x;
-        if (++idx == mx) idx = 0;
-    }
-    T* o = dst + ((size_t)b * L + l) * N + (size_t)r * nx;
-    o[k] = a;
-    o[half + k] = d;
-}
+//
+// Analysis, one launch per level: a workgroup owns a TB x TB tile of each of the
+// four subbands of one channel, stages the (2TB + 14)^2 input window (periodic
+// wrap) in LDS, filters rows then columns in LDS and writes the three detail
+// subbands to their Mallat positions; the approximation goes to a compact
+// buffer for the next level (or to its Mallat place at the last level).  At
+// level 0 the input X is shared by every basis, so one workgroup loops over
+// the bases and reads X once.
+constexpr int WV_TB = 16;   // analysis output tile per subband
+constexpr int WV_TO = 32;   // synthesis output tile
+constexpr int WV_HALO = 14; // 2 * 8 - 2
 
 template <typename T>
-__global__ void k_dwt_cols(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ filt, int L, int nx,
-                           int ny, int mx, int my) {
-    const int half = my >> 1;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= half * mx) return;
-    const int l = blockIdx.y, b = blockIdx.z;
+__global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, const T* __restrict__ llin,
+                                                   T* __restrict__ coef, T* __restrict__ llout,
+                                                   const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
+                                                   int lev0, int last, int n_db) {
+    constexpr int TB = WV_TB;
+    constexpr int WI = 2 * TB + WV_HALO;   // input window edge
+    __shared__ T inS[WI][WI + 1];
+    __shared__ T tmpS[WI][2 * TB + 1];
+    const int hx = mx >> 1, hy = my >> 1;
+    const int ntx = (hx + TB - 1) / TB;
+    const int ky0 = (blockIdx.x / ntx) * TB, kx0 = (blockIdx.x % ntx) * TB;
+    const int l = blockIdx.y;
     const size_t N = (size_t)nx * ny;
-    const int k = e / mx, c = e - k * mx;
-    const T* s = src + ((size_t)b * L + l) * N + c;
-    const T* h = filt + b * 32;
-    const T* g = h + 16;
-    const int taps = 2 * (b + 1);
-    T a = T(0), d = T(0);
-    int idx = (2 * k) % my;
-    for (int j = 0; j < taps; ++j) {
-        const T x = s[(size_t)idx * nx];
-        a += h[j] * x;
-        d += g[j] * x;
-        if (++idx == my) idx = 0;
+    const int tid = threadIdx.x;
+    const int b_first = lev0 ? 0 : (int)blockIdx.z;
+    const int b_last = lev0 ? n_db : (int)blockIdx.z + 1;
+    for (int b = b_first; b < b_last; ++b) {
+        // stage the input window (level 0: once for all bases)
+        if (b == b_first) {
+            const T* src = lev0 ? X + (size_t)l * N : llin + ((size_t)b * L + l) * (size_t)my * mx;
+            const int stride = lev0 ? nx : mx;
+            for (int e = tid; e < WI * WI; e += 256) {
+                const int r = e / WI, cc = e - r * WI;
+                const int gy = (2 * ky0 + r) % my, gx = (2 * kx0 + cc) % mx;
+                inS[r][cc] = src[(size_t)gy * stride + gx];
+            }
+            __syncthreads();
+        } else if (!lev0) {
+            __syncthreads();
+        }
+        const T* h = filt + b * 32;
+        const T* g = h + 16;
+        const int nt = 2 * (b + 1);
+        const int nrows = 2 * TB + nt - 2;
+        // rows (x): a | d for every needed input row
+        for (int e = tid; e < nrows * TB; e += 256) {
+            const int r = e / TB, kx = e - r * TB;
+            T a = T(0), d = T(0);
+            for (int j = 0; j < nt; ++j) {
+                const T x = inS[r][2 * kx + j];
+                a += h[j] * x;
+                d += g[j] * x;
+            }
+            tmpS[r][kx] = a;
+            tmpS[r][TB + kx] = d;
+        }
+        __syncthreads();
+        // columns (y): four subbands
+        for (int e = tid; e < TB * TB; e += 256) {
+            const int ky = e / TB, kx = e - ky * TB;
+            T aa = T(0), da = T(0), ad = T(0), dd = T(0);
+            for (int j = 0; j < nt; ++j) {
+                const T lo = tmpS[2 * ky + j][kx], hi = tmpS[2 * ky + j][TB + kx];
+                aa += h[j] * lo;
+                da += g[j] * lo;
+                ad += h[j] * hi;
+                dd += g[j] * hi;
+            }
+            const int gy = ky0 + ky, gx = kx0 + kx;
+            if (gy < hy && gx < hx) {
+                T* cb = coef + ((size_t)b * L + l) * N;
+                cb[(size_t)gy * nx + hx + gx] = ad;
+                cb[(size_t)(hy + gy) * nx + gx] = da;
+                cb[(size_t)(hy + gy) * nx + hx + gx] = dd;
+                if (last) cb[(size_t)gy * nx + gx] = aa;
+                else llout[((size_t)b * L + l) * (size_t)hy * hx + (size_t)gy * hx + gx] = aa;
+            }
+        }
+        __syncthreads();
     }
-    T* o = dst + ((size_t)b * L + l) * N + c;
-    o[(size_t)k * nx] = a;
-    o[(size_t)(half + k) * nx] = d;
 }
 
-// Inverse along y of level region my x mx.  Rows < my/2 are approximation
-// coefficients: for columns < mx/2 they come from the coarser synthesis
-// (pyr) unless this is the coarsest level; everything else from C.
+// Synthesis, one launch per level (coarse to fine): a workgroup owns a TO x TO
+// tile of the synthesised region, stages windows of the four subbands
+// (approximation from the coarser synthesis, or from C at the coarsest level),
+// inverts along y then x in LDS, and writes a compact approximation for the
+// next finer level.  At level 0 it loops over the bases and writes
+// Xout = C0 + sum_b Psi_b C_b once.
 template <typename T>
-__global__ void k_idwt_cols(const T* __restrict__ C, const T* __restrict__ pyr, T* __restrict__ dst,
-                            const T* __restrict__ filt, int L, int nx, int ny, int mx, int my, int coarsest) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= my * mx) return;
-    const int l = blockIdx.y, b = blockIdx.z;
+__global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
+                                                    T* __restrict__ out, const T* __restrict__ C0,
+                                                    const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
+                                                    int coarsest, int final_level, int n_db) {
+    constexpr int TO = WV_TO;
+    constexpr int W = TO / 2 + 8;          // coefficient window per subband
+    __shared__ T S[4][W][W + 1];           // subband (sy*2 + sx)
+    __shared__ T Tm[2][TO][W + 1];         // after the column inverse, per x-subband
+    const int hx = mx >> 1, hy = my >> 1;
+    const int ntx = (mx + TO - 1) / TO;
+    const int m0y = (blockIdx.x / ntx) * TO, m0x = (blockIdx.x % ntx) * TO;
+    const int l = blockIdx.y;
     const size_t N = (size_t)nx * ny;
-    const size_t off = ((size_t)b * L + l) * N;
-    const int m = e / mx, c = e - m * mx;
-    const int half = my >> 1;
-    const T* h = filt + b * 32;
-    const T* g = h + 16;
-    const int taps = 2 * (b + 1);
-    const T* asrc = (!coarsest && c < (mx >> 1)) ? pyr + off : C + off;
-    T x = T(0);
-    for (int j = (m & 1); j < taps; j += 2) {
-        int q = (m - j) % my;
-        if (q < 0) q += my;
-        const int k = q >> 1;
-        x += h[j] * asrc[(size_t)k * nx + c] + g[j] * C[off + (size_t)(half + k) * nx + c];
+    const int tid = threadIdx.x;
+    int kylo = (m0y / 2 - 8) % hy;
+    if (kylo < 0) kylo += hy;
+    int kxlo = (m0x / 2 - 8) % hx;
+    if (kxlo < 0) kxlo += hx;
+    constexpr int PER = (TO * TO + 255) / 256;
+    T accv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) accv[k] = T(0);
+    const int b_first = final_level ? 0 : (int)blockIdx.z;
+    const int b_last = final_level ? n_db : (int)blockIdx.z + 1;
+    for (int b = b_first; b < b_last; ++b) {
+        const T* Cb = C + ((size_t)b * L + l) * N;
+        const T* LLb = coarsest ? nullptr : llin + ((size_t)b * L + l) * (size_t)hy * hx;
+        for (int e = tid; e < 4 * W * W; e += 256) {
+            const int sb = e / (W * W), r = (e / W) % W, cc = e % W;
+            const int sy = sb >> 1, sx = sb & 1;
+            int ky = kylo + r, kx = kxlo + cc;
+            while (ky >= hy) ky -= hy;
+            while (kx >= hx) kx -= hx;
+            T v;
+            if (sb == 0 && !coarsest) v = LLb[(size_t)ky * hx + kx];
+            else v = Cb[(size_t)(sy * hy + ky) * nx + sx * hx + kx];
+            S[sb][r][cc] = v;
+        }
+        __syncthreads();
+        const T* h = filt + b * 32;
+        const T* g = h + 16;
+        const int nt = 2 * (b + 1);
+        // inverse along y: Tm[sx][m][wx]
+        for (int e = tid; e < 2 * TO * W; e += 256) {
+            const int sx = e / (TO * W), m = (e / W) % TO, wx = e % W;
+            const int gm = m0y + m;
+            T x = T(0);
+            // window row r holds coefficient (m0y/2 - 8 + r) mod hy, so tap j of
+            // output row m0y + m reads row (m - j)/2 + 8 (m0y even, j = m mod 2)
+            for (int j = (m & 1); j < nt; j += 2) {
+                const int w = ((m - j) >> 1) + 8;
+                x += h[j] * S[sx][w][wx] + g[j] * S[2 + sx][w][wx];
+            }
+            Tm[sx][m][wx] = x;
+        }
+        __syncthreads();
+        // inverse along x
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * 256;
+            if (e < TO * TO) {
+                const int m = e / TO, n = e % TO;
+                const int gn = m0x + n;
+                T x = T(0);
+                for (int j = (n & 1); j < nt; j += 2) {
+                    const int w = ((n - j) >> 1) + 8;
+                    x += h[j] * Tm[0][m][w] + g[j] * Tm[1][m][w];
+                }
+                if (final_level) accv[k] += x;
+                else if (m0y + m < my && gn < mx)
+                    out[((size_t)b * L + l) * (size_t)my * mx + (size_t)(m0y + m) * mx + gn] = x;
+            }
+        }
+        __syncthreads();
     }
-    dst[off + (size_t)m * nx + c] = x;
-}
-
-template <typename T>
-__global__ void k_idwt_rows(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ filt, int L, int nx,
-                            int ny, int mx, int my) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= my * mx) return;
-    const int l = blockIdx.y, b = blockIdx.z;
-    const size_t N = (size_t)nx * ny;
-    const size_t off = ((size_t)b * L + l) * N;
-    const int r = e / mx, m = e - r * mx;
-    const int half = mx >> 1;
-    const T* h = filt + b * 32;
-    const T* g = h + 16;
-    const int taps = 2 * (b + 1);
-    const T* s = src + off + (size_t)r * nx;
-    T x = T(0);
-    for (int j = (m & 1); j < taps; j += 2) {
-        int q = (m - j) % mx;
-        if (q < 0) q += mx;
-        const int k = q >> 1;
-        x += h[j] * s[k] + g[j] * s[half + k];
+    if (final_level) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * 256;
+            if (e < TO * TO) {
+                const int m = e / TO, n = e % TO;
+                const int gy = m0y + m, gx = m0x + n;
+                if (gy < my && gx < mx) {
+                    const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
+                    out[idx] = (C0 ? C0[idx] : T(0)) + accv[k];
+                }
+            }
+        }
     }
-    dst[off + (size_t)r * nx + m] = x;
 }
 
 // X = C0 + sum_b Y_b  (C0 may be null)
@@ -160,21 +240,26 @@ __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restr
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Psi_d^dagger for the n_db wavelet bases of X into Cout [n_db][L][N] (coef if null).
+// Intermediate approximations live in two compact slots of wtmp.
 template <typename T>
 void launch_psi_adj(hs_ctx* c, const T* X, T* Cout) {
     if (c->n_db == 0) return;
     T* out = Cout ? Cout : (T*)c->d.coef;
-    T* tmp = (T*)c->d.wtmp;
+    T* slotA = (T*)c->d.wtmp;
+    T* slotB = slotA + (size_t)c->n_db * c->L * (c->N / 4);
     const T* filt = (const T*)c->d.filt;
+    const T* llin = nullptr;
     for (int lev = 0; lev < c->levels; ++lev) {
         const int mx = c->nx >> lev, my = c->ny >> lev;
-        dim3 g1(nblk((int64_t)my * (mx / 2), 256), c->L, c->n_db);
-        k_dwt_rows<T><<<g1, 256, 0, c->stream>>>(X, out, tmp, filt, c->L, c->nx, c->ny, mx, my, lev == 0 ? 1 : 0);
-        dim3 g2(nblk((int64_t)(my / 2) * mx, 256), c->L, c->n_db);
-        k_dwt_cols<T><<<g2, 256, 0, c->stream>>>(tmp, out, filt, c->L, c->nx, c->ny, mx, my);
+        const int hx = mx / 2, hy = my / 2;
+        const int tiles = ((hy + WV_TB - 1) / WV_TB) * ((hx + WV_TB - 1) / WV_TB);
+        T* llout = (lev % 2 == 0) ? slotA : slotB;
+        const int last = (lev == c->levels - 1) ? 1 : 0;
+        dim3 g(tiles, c->L, lev == 0 ? 1 : c->n_db);
+        k_dwt_level<T><<<g, 256, 0, c->stream>>>(X, llin, out, llout, filt, c->L, c->nx, c->ny, mx, my,
+                                                 lev == 0 ? 1 : 0, last, c->n_db);
+        llin = llout;
     }
-    // detail and approximation coefficients outside the last LL are written by
-    // the level that produced them; nothing else to copy.
 }
 
 // Xout = C0 + sum_b Psi_b Cdb[b]; C0 (Dirac coefficients) may be null.
@@ -185,17 +270,20 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout) {
         k_psi_sum<T><<<nblk(LN, 256), 256, 0, c->stream>>>(nullptr, C0, Xout, 0, LN);
         return;
     }
-    T* pyr = (T*)c->d.coef;   // synthesis pyramid (overwrites the analysis scratch)
-    T* tmp = (T*)c->d.wtmp;
+    T* slotA = (T*)c->d.wtmp;
+    T* slotB = slotA + (size_t)c->n_db * c->L * (c->N / 4);
     const T* filt = (const T*)c->d.filt;
+    const T* llin = nullptr;
     for (int lev = c->levels - 1; lev >= 0; --lev) {
         const int mx = c->nx >> lev, my = c->ny >> lev;
-        dim3 g(nblk((int64_t)my * mx, 256), c->L, c->n_db);
-        k_idwt_cols<T><<<g, 256, 0, c->stream>>>(Cdb, pyr, tmp, filt, c->L, c->nx, c->ny, mx, my,
-                                                 lev == c->levels - 1 ? 1 : 0);
-        k_idwt_rows<T><<<g, 256, 0, c->stream>>>(tmp, pyr, filt, c->L, c->nx, c->ny, mx, my);
+        const int tiles = ((my + WV_TO - 1) / WV_TO) * ((mx + WV_TO - 1) / WV_TO);
+        const int fin = (lev == 0) ? 1 : 0;
+        T* out = fin ? Xout : ((lev % 2 == 1) ? slotA : slotB);
+        dim3 g(tiles, c->L, fin ? 1 : c->n_db);
+        k_idwt_level<T><<<g, 256, 0, c->stream>>>(Cdb, llin, out, C0, filt, c->L, c->nx, c->ny, mx, my,
+                                                  lev == c->levels - 1 ? 1 : 0, fin, c->n_db);
+        llin = out;
     }
-    k_psi_sum<T><<<nblk(LN, 256), 256, 0, c->stream>>>(pyr, C0, Xout, c->n_db, LN);
 }
 
 template <typename T>

@@ -247,6 +247,11 @@ class Problem:
         self._call("hs_profile_phases", self.lib.hs_profile_phases, int(n), L.as_dptr(t))
         return dict(zip(L.PHASES, t.tolist()))
 
+    def diag(self):
+        out = np.zeros(4)
+        self._call("hs_get_diag", self.lib.hs_get_diag, L.as_dptr(out), 4)
+        return {"beta": out[0], "device_iterations": out[1], "eig_sweeps": out[2], "host_iterations": out[3]}
+
     def stats(self):
         nb = int(sum(self.nblocks))
         beta = C.c_double()
