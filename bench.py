@@ -58,12 +58,14 @@ def algorithmic_bytes(cfg, M: int, r: int = 4):
         "gram": 2 * L * N * r,
         "eig": 0,
         "backproject": 3 * L * N * r,
-        # per level: read the LL region once per basis and write tmp, read tmp and write coefficients
-        "psi_adj": nb * L * N * r * 4 * lev,
+        # fused level kernels: X~ read once at level 1; per basis every level writes its four
+        # subbands (sum N * lev) and levels 2..4 read the previous low-pass (N * (lev - 1))
+        "psi_adj": L * N * r * (1 + nb * lev + nb * (lev - 1)),
         # read A (D bases), the 8 analysis outputs and Xt, write A
         "l21": L * N * r * (D + nb + 1 + D),
-        # per level: read details and LL, write tmp; read tmp, write level output; final sum
-        "psi": nb * L * N * r * 4 * lev + L * N * r * (nb + 2),
+        # per basis each level reads its four subbands (N * lev) and levels 4..2 write the next
+        # low-pass (N * (lev - 1)); the finest level adds the Dirac term and writes the sum once
+        "psi": L * N * r * (nb * lev + nb * (lev - 1) + 2),
         # read X, P, At, D; write X, Xt
         "primal": 6 * L * N * r,
     }

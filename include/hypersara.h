@@ -254,7 +254,10 @@ hs_status hs_op_norm(hs_ctx* ctx, int32_t which, int32_t max_it, double tol, con
 /* -------------------------------------------------------------- PD solver */
 /* Sets parameters of Algorithm 2 (does not reset the state). */
 hs_status hs_pd_init(hs_ctx* ctx, const hs_pd_params* params);
-/* Copy a state into / out of the context (device-to-device, on the stream). */
+/* Copy a state into / out of the context (device-to-device, on the stream).
+ * hs_pd_set_state also restarts Algorithm 2's bookkeeping: iteration count
+ * t = 0, beta = 1, the l2 bounds of hs_set_data and their last-update
+ * iterations (vartheta) = 0; the eigen-solver warm start is reset too. */
 hs_status hs_pd_set_state(hs_ctx* ctx, const hs_state_ptrs* st);
 hs_status hs_pd_get_state(hs_ctx* ctx, const hs_state_ptrs* st);
 /* n iterations of Algorithm 2 (Steps 3-23).  The first call captures one

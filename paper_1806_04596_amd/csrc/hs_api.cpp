@@ -104,6 +104,17 @@ static void upload(void* dst, const std::vector<V>& src) {
     if (!src.empty()) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
 }
 
+// Algorithm 2's initial values: t = 0, beta = 1 (Step 14 cannot fire before a
+// real iteration), the l2 bounds given by hs_set_data and their last-update
+// iterations vartheta = 0.
+static void restart_counters(hs_ctx* c) {
+    launch_fill<double>(c->stream, c->d.scal, 1.0, 1);
+    launch_fill<double>(c->stream, c->d.scal + 1, 0.0, 1);
+    launch_fill<int32_t>(c->stream, c->d.blk_vartheta, 0, c->nblk);
+    if (c->nblk)
+        hipMemcpyAsync(c->d.blk_eps, c->h_blk_eps.data(), (size_t)c->nblk * 8, hipMemcpyHostToDevice, c->stream);
+}
+
 template <typename T>
 static hs_status bind_impl(hs_ctx* c) {
     Dev& d = c->d;
@@ -172,7 +183,7 @@ static hs_status bind_impl(hs_ctx* c) {
     launch_fill<T>(c->stream, (T*)d.v, T(0), 2 * c->Mtot);
     launch_fill<T>(c->stream, (T*)d.wbar, T(1), (int64_t)c->D * c->N);
     launch_fill<double>(c->stream, d.scal, 0.0, 64);
-    launch_fill<int32_t>(c->stream, d.blk_vartheta, 0, c->nblk);
+    restart_counters(c);
     launch_fill<double>(c->stream, d.blk_lambda, 0.0, c->nblk);
     launch_fill<double>(c->stream, d.blk_rho2, 0.0, c->nblk);
     return hip_check(c, hipStreamSynchronize(c->stream), "hs_bind_workspace");
@@ -744,6 +755,7 @@ hs_status hs_pd_set_state(hs_ctx* c, const hs_state_ptrs* st) {
     if (st->A) hipMemcpyAsync(c->d.A, st->A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
     if (st->v) HS_DISPATCH(c, launch_gather_user<T>(c, (const cplx<T>*)st->v, (cplx<T>*)c->d.v, false));
     launch_eig_reset(c);   // a new state starts the eigen-solver history afresh (reproducible runs)
+    restart_counters(c);
     return launched(c, "hs_pd_set_state");
 }
 

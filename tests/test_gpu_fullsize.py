@@ -1,0 +1,146 @@
+"""Parity at the benchmark size: the 512x512x60 uneven cube (16.3 M
+visibilities, 8 blocks per channel) in FP32, built and launched exactly as
+the benchmark builds it (automatic tile, batched kernels, graph replay).
+
+Channel-separable outputs (Phi, Phi^dagger, Psi^dagger, Psi, the data-fidelity
+dual) are compared element by element with the oracle on sampled channels
+(the smallest, a middle and the largest); the channel-coupled nuclear dual is
+compared on the whole cube; the full PD iteration is checked through
+properties that hold at any size and against the FP64 instantiation."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import nufft, pd, prox, wavelets
+from gpu_cases import TOL, check_rel, host, rel, split, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+CFG = W.CONFIGS["c3"]
+
+
+@pytest.fixture(scope="module")
+def big():
+    from paper_1806_04596_amd.workload import build_problem
+    inp = W.make_problem_inputs(CFG)
+    counts = np.array([len(u) for u in inp["uv"]])
+    S = sorted({int(np.argmin(counts)), CFG.L // 2, int(np.argmax(counts))})
+    prob, X0, hd = build_problem(CFG, inp, W.make_measurements, dtype="f32")
+    # the oracle's own problem for the sampled channels (each channel's data,
+    # weights, bounds and preconditioner depend on that channel only)
+    sub = {"X0": inp["X0"][S], "uv": [inp["uv"][l] for l in S], "block_ptr": [inp["block_ptr"][l] for l in S],
+           "noise": [inp["noise"][l] for l in S]}
+    op, _ = pd.build_problem(CFG.scaled(L=len(S)), sub)
+    print(f"c3 full size: sampled channels {S}, M = {prob.M}", flush=True)
+    return {"inp": inp, "prob": prob, "S": S, "op": op}
+
+
+def test_phi_full_size(big):
+    prob, S, op, inp = big["prob"], big["S"], big["op"], big["inp"]
+    rng = np.random.default_rng(40)
+    X = inp["X0"] + 0.05 * inp["X0"].max() * rng.standard_normal(inp["X0"].shape)
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    for j, l in enumerate(S):
+        ref = nufft.phi(X[l], op.uv[j], op.theta[j])
+        check_rel(Y[l], ref, TOL["f32"], f"Phi channel {l}")
+
+
+def test_phi_adj_full_size(big):
+    prob, S, op = big["prob"], big["S"], big["op"]
+    rng = np.random.default_rng(41)
+    y = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
+    X = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
+    ys = split(y, prob.counts)
+    for j, l in enumerate(S):
+        ref = nufft.phi_adj(ys[l], op.uv[j], op.theta[j], CFG.ny, CFG.nx)
+        check_rel(X[l], ref, TOL["f32"], f"Phi^dag channel {l}")
+
+
+def test_psi_full_size(big):
+    prob, S = big["prob"], big["S"]
+    rng = np.random.default_rng(42)
+    X = rng.standard_normal((CFG.L, CFG.ny, CFG.nx))
+    C = host(prob.psi_adj(to_dev(prob, X)))
+    ref = wavelets.psi_adj(X[S])
+    for j, l in enumerate(S):
+        for d in range(9):
+            check_rel(C[d, l], ref[d, j], TOL["f32"], f"Psi^dag basis {d} channel {l}")
+    Cr = rng.standard_normal((9, CFG.L, CFG.ny, CFG.nx)).astype(np.float32)
+    Xs = host(prob.psi(to_dev(prob, Cr)))
+    ref = wavelets.psi(Cr[:, S].astype(np.float64))
+    for j, l in enumerate(S):
+        check_rel(Xs[l], ref[j], TOL["f32"], f"Psi channel {l}")
+
+
+def test_dual_nuclear_full_size(big):
+    prob, inp = big["prob"], big["inp"]
+    rng = np.random.default_rng(43)
+    X = inp["X0"] + 0.01 * inp["X0"].max() * rng.standard_normal(inp["X0"].shape)
+    P = 0.05 * inp["X0"].max() * rng.standard_normal(X.shape)
+    s = np.linalg.svd(X.reshape(CFG.L, -1).T, compute_uv=False)
+    w = np.sort(rng.uniform(0.0, 0.5 * s[0], CFG.L))
+    Pd = host(prob.dual_nuclear(to_dev(prob, P), to_dev(prob, X), w))
+    ref = prox.dual_nuclear(P, X, w, "gram")
+    check_rel(Pd, ref, TOL["f32"], "P")
+
+
+def test_dual_data_full_size(big):
+    prob, S, op, inp = big["prob"], big["S"], big["op"], big["inp"]
+    rng = np.random.default_rng(44)
+    Xt = inp["X0"] + 0.05 * inp["X0"].max() * rng.standard_normal(inp["X0"].shape)
+    v = 0.05 * (rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M))
+    vd = host(prob.dual_data(to_dev(prob, v, complex_=True), to_dev(prob, Xt)))
+    vg, vs = split(vd, prob.counts), split(v, prob.counts)
+    for j, l in enumerate(S):
+        vbar = vs[l] + op.u[j] * nufft.phi(Xt[l], op.uv[j], op.theta[j])
+        bp = op.block_ptr[j]
+        vr = np.empty_like(vbar)
+        for b in range(len(bp) - 1):
+            sl = slice(bp[b], bp[b + 1])
+            vr[sl], _ = prox.dual_data_block(vbar[sl], op.y[j][sl], op.u[j][sl], op.eps[j][b])
+        check_rel(vg[l], vr, 10 * TOL["f32"], f"v channel {l}")
+
+
+def test_pd_iteration_full_size_properties(big):
+    """Graph replay (as timed by the benchmark) equals the eager iteration bit
+    for bit; X >= 0; X~ = 2X - X_prev exactly; beta = ||X - X_prev|| / ||X||;
+    the FP32 iteration agrees with the FP64 instantiation to 1e-5."""
+    import torch
+    from paper_1806_04596_amd.workload import build_problem
+    prob, inp = big["prob"], big["inp"]
+    amp = float(inp["X0"].max())
+    g = torch.Generator(device="cpu").manual_seed(45)
+
+    def r(*shape):
+        return torch.randn(*shape, generator=g, dtype=torch.float64)
+    X = (torch.as_tensor(inp["X0"]) * (1 + 0.2 * r(*inp["X0"].shape))).clamp_min(0)
+    st = {"X": X, "Xt": X + 0.02 * amp * r(*X.shape), "P": 0.05 * amp * r(*X.shape),
+          "A": 0.05 * amp * r(9, *X.shape), "v": 0.05 * torch.complex(r(prob.M), r(prob.M))}
+    kappa3 = 1.0 / prob.op_norm(to_dev(prob, W.synth.power_start(CFG)), max_it=30, tol=1e-6)[0]
+
+    def run(p, eager):
+        dev = {k: t.to(p.device, p.cdtype if k == "v" else p.tdtype).contiguous() for k, t in st.items()}
+        p.set_state(**dev)
+        p.pd_init(mu=0.01, tau=0.33, kappa3=kappa3, kappa2=1.0 / 9.0)
+        if eager:
+            p.profile_phases(1)
+        else:
+            p.iterate(1)
+        out = p.get_state()
+        return out, p.stats()[0], dev["X"]
+
+    a, beta_a, Xp = run(prob, eager=False)
+    b, beta_b, _ = run(prob, eager=True)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    assert beta_a == beta_b
+    assert bool((a["X"] >= 0).all())
+    assert torch.equal(a["Xt"], 2 * a["X"] - Xp)
+    bref = float((a["X"].double() - Xp.double()).norm() / a["X"].double().norm())
+    assert abs(beta_a - bref) <= 1e-6 * bref
+    p64, _, _ = build_problem(CFG, inp, W.make_measurements, dtype="f64")
+    c, _, _ = run(p64, eager=False)
+    for k in ("X", "Xt", "P", "A"):
+        err = rel(host(a[k]), host(c[k]))
+        assert err <= TOL["f32"], (k, err)
+    p64.close()

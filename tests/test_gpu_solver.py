@@ -1,0 +1,79 @@
+"""Algorithm 1 (reweighted outer loop) and Algorithm 2 Steps 13-19 (adaptive
+l2 bounds) through the C-ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pd
+from gpu_cases import TOL, check_rel, host, oracle_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _kappa3(op):
+    return 1.0 / (max(len(t) for t in op.theta) * max(float(np.max(t)) for t in op.theta if len(t)) ** 2)
+
+
+def _fresh(name, dtype):
+    # a problem of its own: these tests change the bounds and the weights
+    from paper_1806_04596_amd.workload import build_problem
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = build_problem(cfg, inp, W.make_measurements, dtype=dtype)
+    return cfg, inp, op, prob
+
+
+def _oracle_state(st, op):
+    return pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                    eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+
+
+def _set(prob, st):
+    prob.set_state(X=to_dev(prob, st["X"]), Xt=to_dev(prob, st["Xt"]), P=to_dev(prob, st["P"]),
+                   A=to_dev(prob, st["A"]), v=to_dev(prob, np.concatenate(st["v"]), complex_=True))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_reweighted_solve_vs_oracle(dtype):
+    """Two reweights (eq:weights-l21, eq:weights-n) between three runs of 6 PD
+    iterations each, warm-started, gamma factor 0.8."""
+    cfg, inp, op, prob = _fresh("t1", dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op))
+    ost, oprm, hist = pd.solve(op, prm, (1.0, 1.0 / 9.0, prm.kappa3), n_reweights=2, iters_per=6, factor=0.8,
+                               st=_oracle_state(st, op))
+    _set(prob, st)
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0)
+    X, rep = prob.solve(2, 6, gamma_factor=0.8)
+    assert rep["iterations"] == 18 and rep["reweights"] == 2
+    tol = 1e-11 if dtype == "f64" else 10 * TOL["f32"]
+    check_rel(host(X), ost.X, tol, "X")
+    assert abs(rep["final_beta"] - hist[-1]) <= tol * 10 * hist[-1]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adaptive_bounds_vs_oracle(dtype):
+    """Steps 13-19 with lam1 large enough and vartheta_bar = 1 so that the bounds
+    move within a few iterations: eps, rho and X follow the oracle."""
+    cfg, inp, op, prob = _fresh("t2", dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), adaptive_eps=True, lam1=10.0, lam2=0.01, lam3=0.618,
+                    vartheta_bar=1)
+    ost = _oracle_state(st, op)
+    for _ in range(5):
+        ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    eps_ref = np.concatenate(ost.eps)
+    eps0 = np.concatenate(op.eps)
+    assert np.any(eps_ref != eps0)              # the bounds did move
+    _set(prob, st)
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0, adaptive_eps=True, lam1=10.0,
+                 lam2=0.01, lam3=0.618, vartheta_bar=1)
+    prob.iterate(5)
+    beta, rho, eps = prob.stats()
+    tol = TOL[dtype] * (1 if dtype == "f64" else 10)
+    check_rel(eps, eps_ref, tol, "eps")
+    check_rel(rho, np.concatenate(ost.extra["rho"]), tol, "rho")
+    check_rel(host(prob.get_state()["X"]), ost.X, tol, "X")
+    # set_state restarts the bookkeeping: the bounds are the data's again
+    _set(prob, st)
+    _, _, eps_again = prob.stats()
+    assert np.array_equal(eps_again, eps0)
