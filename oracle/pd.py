@@ -2,7 +2,7 @@
 
 Readings taken (paper silent or ambiguous):
 * one iteration consumes (X^{t-1}, X~^{t-1}, P, A_d, v_l^b) and returns the next
-  state; dual updates use only iterate t-1 ("simultaneously", Algorithm 2);
+  state; dual updates use only iterate t-1 (Algorithm 2 runs them side by side);
 * Step 20's data term: channel l's adjoint lands in column l (the selection
   k_l^dagger of the adjoint in the dual problem is implied);
 * kappa1 = 1, kappa2 = 1/||Psi^dagger||_S^2 = 1/D, kappa3 = 1/||U^{1/2} Phi||_S^2
