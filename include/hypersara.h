@@ -61,7 +61,7 @@ typedef struct hs_ctx hs_ctx;
  * levels: wavelet depth (1..6), n_db: number of Daubechies bases (0..8),
  *   the dictionary is Dirac + db1..db{n_db} (D = 1 + n_db bases).
  * dtype: HS_F32 or HS_F64.  tile: gridding tile edge (0 = automatic; else a
- *   power of two in 8..64 with 2*nx/tile >= 3 and 2*ny/tile >= 3).
+ *   power of two in 8..32 with 2*nx/tile >= 3 and 2*ny/tile >= 3).
  * device: HIP device ordinal; stream: hipStream_t (NULL = default stream). */
 typedef struct {
     int32_t nx, ny, L;

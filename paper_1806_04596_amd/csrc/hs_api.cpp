@@ -52,7 +52,7 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.dunits, c->dunits.size() * sizeof(DegridUnit), base);
     k.take(d.gunits, c->gunits.size() * sizeof(GridUnit), base);
     k.take(d.splits, c->splits.size() * sizeof(SplitTile), base);
-    k.take(d.granges, c->h_granges.size() * 4, base);
+    k.take(d.glist, c->h_glist.size() * 4, base);
     k.take(d.gpartial, (size_t)c->npartial * c->T * c->T * cx, base);
     k.take(d.bin_u, (size_t)c->nbins * 8, base);
     k.take(d.bin_block, (size_t)c->nbins * 4, base);
@@ -132,7 +132,7 @@ static hs_status bind_impl(hs_ctx* c) {
     upload(d.dunits, c->dunits);
     upload(d.gunits, c->gunits);
     upload(d.splits, c->splits);
-    upload(d.granges, c->h_granges);
+    upload(d.glist, c->h_glist);
     upload(d.bin_u, c->h_bin_u);
     upload(d.bin_block, c->h_bin_block);
     upload(d.blk_bin_ptr, c->h_blk_bin_ptr);

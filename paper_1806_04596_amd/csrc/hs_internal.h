@@ -29,12 +29,13 @@ struct DegridUnit {
     int32_t run_base, pad0, pad1, pad2;
 };
 
-// One gridding work unit: part `split` of `nsplit` of the visibilities that
-// reach the core of `tile` of channel l.  nsplit > 1 writes a partial tile to
-// slot partial + split; nsplit == 1 writes the grid directly.
+// One gridding work unit: entries [g0, g0 + gn) of the sorted entry list of
+// `tile` of channel l (its own visibilities and its neighbours' border ones, by
+// first-tap cell), part `split` of `nsplit`.  nsplit > 1 writes a partial tile
+// to slot partial + split; nsplit == 1 writes the grid directly.
 struct GridUnit {
     int32_t l, tile, split, nsplit;
-    int32_t partial, pad0, pad1, pad2;
+    int32_t partial, g0, gn, pad;
 };
 
 // A tile whose gridding was split: the partials are summed in order.
@@ -54,7 +55,7 @@ struct KBPoly {                 // phi(d) = sum_k c[k] s^k, s = 1 - d^2/8 = 2(1 
 };
 
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {   // aligned to its size: one 64/128-bit access
     T re, im;
 };
 
@@ -75,7 +76,7 @@ struct Dev {
     DegridUnit* dunits = nullptr;
     GridUnit* gunits = nullptr;
     SplitTile* splits = nullptr;
-    int32_t* granges = nullptr;    // [L*ntiles][13][2]
+    int32_t* glist = nullptr;      // gridding entries: plan positions, per tile sorted by first-tap cell
     void* gpartial = nullptr;      // [npartial][T*T] complex
     // bins / blocks
     double* bin_u = nullptr;       // [nbins]
@@ -156,7 +157,7 @@ struct hs_ctx {
     int kb_terms = 0;
     std::vector<double> kb_c;          // power-series coefficients
     // host staging of the plan (uploaded at bind)
-    std::vector<int32_t> h_cell, h_bin, h_perm, h_granges, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_bin_runs;
+    std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_bin_runs;
     std::vector<double> h_frac, h_y, h_theta, h_u, h_bin_u, h_blk_eps;
     std::vector<int64_t> h_pos_of;     // caller global index -> grid position
     size_t ws_bytes = 0;

@@ -302,8 +302,8 @@ hs_status build_plan(hs_ctx* c) {
         T = 32;
         while (T > 8 && (c->Kx / T < 3 || c->Ky / T < 3 || c->Kx % T || c->Ky % T)) T /= 2;
     }
-    if (T < 8 || T > 64 || (T & (T - 1)) || c->Kx % T || c->Ky % T || c->Kx / T < 3 || c->Ky / T < 3)
-        return fail(c, HS_ERR_SHAPE, "hs_plan: tile must be a power of two in 8..64 with >= 3 tiles per dimension");
+    if (T < 8 || T > 32 || (T & (T - 1)) || c->Kx % T || c->Ky % T || c->Kx / T < 3 || c->Ky / T < 3)
+        return fail(c, HS_ERR_SHAPE, "hs_plan: tile must be a power of two in 8..32 with >= 3 tiles per dimension");
     c->T = T;
     c->tiles_x = c->Kx / T;
     c->tiles_y = c->Ky / T;
@@ -334,7 +334,8 @@ hs_status build_plan(hs_ctx* c) {
     c->dunits.clear();
     c->gunits.clear();
     c->splits.clear();
-    c->h_granges.assign((size_t)L * c->ntiles * 2 * N_GRANGES, 0);
+    c->h_glist.clear();
+    std::vector<int32_t> kcount((size_t)(T + 7) * (T + 7) + 1);
     std::vector<std::pair<int32_t, int32_t>> run_bin;  // (bin, run)
     int64_t nruns = 0, npartial = 0;
     int64_t bin_base = 0;
@@ -393,14 +394,43 @@ hs_status build_plan(hs_ctx* c) {
                 c->dunits.push_back(du);
             }
         }
-        // gridding units (every tile gets at least one: empty tiles write zeros)
+        // gridding units (every tile gets at least one: empty tiles write zeros).
+        // The entries meeting a tile -- its own visibilities and the border
+        // regions of its 8 neighbours -- are listed sorted by first-tap cell
+        // relative to the tile (counting sort, stable), so that the kernel sees
+        // runs of visibilities sharing a footprint.
         for (int tyi = 0; tyi < c->tiles_y; ++tyi) {
             for (int txi = 0; txi < c->tiles_x; ++txi) {
                 const int t = tyi * c->tiles_x + txi;
-                int32_t* rg = &c->h_granges[((size_t)l * c->ntiles + t) * 2 * N_GRANGES];
+                const int ox = txi * T, oy = tyi * T, W7 = T + 7;
+                int32_t rg[2 * N_GRANGES];
                 tile_ranges(o.region_ptr, base, c->tiles_x, c->tiles_y, txi, tyi, rg);
+                auto key_of = [&](int64_t g) -> int {
+                    const int32_t cl = c->h_cell[g];
+                    int relx = (cl & 0xFFFF) - ox, rely = (cl >> 16) - oy;
+                    if (relx < -T) relx += c->Kx;
+                    if (relx >= 2 * T) relx -= c->Kx;
+                    if (rely < -T) rely += c->Ky;
+                    if (rely >= 2 * T) rely -= c->Ky;
+                    const int rx0 = relx - 3, ry0 = rely - 3;
+                    if (rx0 < -7 || rx0 >= T || ry0 < -7 || ry0 >= T) return -1;
+                    return (ry0 + 7) * W7 + (rx0 + 7);
+                };
+                std::fill(kcount.begin(), kcount.end(), 0);
                 int64_t E = 0;
-                for (int r = 0; r < N_GRANGES; ++r) E += rg[2 * r + 1] - rg[2 * r];
+                for (int r = 0; r < N_GRANGES; ++r)
+                    for (int64_t g = rg[2 * r]; g < rg[2 * r + 1]; ++g) {
+                        const int k = key_of(g);
+                        if (k < 0) return fail(c, HS_ERR_INVALID_ARG, "hs_plan: internal error in tile ranges");
+                        ++kcount[k + 1];
+                        ++E;
+                    }
+                for (int k = 0; k < W7 * W7; ++k) kcount[k + 1] += kcount[k];
+                const int64_t g0 = (int64_t)c->h_glist.size();
+                if (g0 + E > INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: too many gridding entries");
+                c->h_glist.resize(g0 + E);
+                for (int r = 0; r < N_GRANGES; ++r)
+                    for (int64_t g = rg[2 * r]; g < rg[2 * r + 1]; ++g) c->h_glist[g0 + kcount[key_of(g)]++] = (int32_t)g;
                 const int nsplit = (int)std::max<int64_t>(1, (E + GRID_SPLIT - 1) / GRID_SPLIT);
                 for (int sp = 0; sp < nsplit; ++sp) {
                     GridUnit gu{};
@@ -409,6 +439,9 @@ hs_status build_plan(hs_ctx* c) {
                     gu.split = sp;
                     gu.nsplit = nsplit;
                     gu.partial = (int32_t)npartial;
+                    const int64_t a = (sp * E) / nsplit, b = ((sp + 1) * E) / nsplit;
+                    gu.g0 = (int32_t)(g0 + a);
+                    gu.gn = (int32_t)(b - a);
                     c->gunits.push_back(gu);
                 }
                 if (nsplit > 1) {

@@ -603,89 +603,151 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 }
 
 // ---------------------------------------------------------- gridding (pull)
-// One wave owns the T x T core of a tile (accumulator in LDS, rows padded to
-// T + GR_PAD cells so the 8 rows of a footprint fall in different banks).
-// Visibilities are consumed in batches of 64: first lane i computes the 8 + 8
-// kernel values of visibility i into LDS; then the wave walks the batch one
-// visibility at a time with lane (jx, jy) owning tap (jx, jy).  The 64 taps of
-// one visibility are 64 distinct cells, so each lane does a plain LDS
-// read-modify-write: no atomics, and the summation order is fixed.
-constexpr int GR_PAD = 8;
+// Output-stationary gridding, one wave per (tile, split) unit.  The plan lists
+// the entries meeting each tile (its own visibilities and its neighbours'
+// border ones) sorted by first-tap cell, so visibilities sharing a footprint
+// arrive in runs.  Lane (jx, jy) owns tap (jx, jy) of the current footprint:
+// within a run every lane adds phi_x(jx) phi_y(jy) val into one register; at
+// the end of a run the 64 sums are added into the tile accumulator in LDS (a
+// plain read-modify-write: the 64 taps are 64 distinct cells).  No atomics;
+// the summation order is fixed by the list.
+// Entries come in batches of 64: lane i stages the 8 + 8 kernel values and
+// the value of entry i in LDS; a ballot marks where runs start; the walk over
+// the batch is unrolled, so every LDS address in it is an immediate offset.
+constexpr int GR_PAD = 8;   // accumulator row stride T + 8: a footprint's 8 rows fall in distinct banks
+constexpr int GW = 17;      // staged kernel values per entry (8 + 8, odd stride: bank-free staging)
+
+// Accumulator slot of this lane's tap for the footprint whose first tap is
+// key = (cy, cx) (tile-relative), or -1 when the tap falls outside the tile
+// core; lane_off = jy * TS + jx.  Interior footprints (the usual case) need no
+// per-lane bounds test.
+__device__ __forceinline__ int grid_slot(int key, int TS, int TT, int jx, int jy, int lane_off) {
+    const int cx = (int)(short)(key & 0xFFFF), cy = key >> 16;
+    const bool inside = cx >= 0 && cx <= TT - 8 && cy >= 0 && cy <= TT - 8;
+    return (inside || (cx + jx >= 0 && cx + jx < TT && cy + jy >= 0 && cy + jy < TT)) ? cy * TS + cx + lane_off : -1;
+}
+
+// Add a run's sum into its accumulator cell (a plain read-modify-write: the
+// 64 taps of a footprint are 64 distinct cells; LDS float atomics measured
+// several times slower).
+template <typename T>
+__device__ __forceinline__ void grid_flush(cplx<T>* acc, int slot, const cplx<T>& r) {
+    if (slot >= 0) {
+        cplx<T> a = acc[slot];
+        a.re += r.re;
+        a.im += r.im;
+        acc[slot] = a;
+    }
+}
+
+template <typename T>
+struct GridFetch {
+    int cc;
+    cplx<T> f, val;
+};
+
+template <typename T>
+__device__ __forceinline__ void grid_fetch(GridFetch<T>& g, int pos, const int32_t* __restrict__ cell,
+                                           const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals,
+                                           const T* __restrict__ weight) {
+    if (pos >= 0) {
+        g.cc = cell[pos];
+        g.f = frac[pos];
+        g.val = vals[pos];
+        if (weight) {
+            const T w = weight[pos];
+            g.val.re *= w;
+            g.val.im *= w;
+        }
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
-    const GridUnit* __restrict__ units, const int32_t* __restrict__ granges, const int32_t* __restrict__ cell,
+    const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
     const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
-    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x, int ntiles,
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x,
     KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     const int TS = TT + GR_PAD;
-    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);        // [TT][TS]
-    T* wts = reinterpret_cast<T*>(acc + TT * TS);                // [64][16]
-    cplx<T>* vv = reinterpret_cast<cplx<T>*>(wts + 64 * 16);     // [64]
-    int* rel = reinterpret_cast<int*>(vv + 64);                  // [64] packed tap origin
+    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TT][TS]
+    cplx<T>* vv = acc + TT * TS;                                   // [64]
+    T* wts = reinterpret_cast<T*>(vv + 64);                        // [64][GW]
     const GridUnit u = units[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, jx = lane & 7, jy = lane >> 3, lane_off = jy * TS + jx;
+    const int32_t* gl = glist + u.g0;
+    const int n = u.gn;
+    // global loads run one batch ahead (entry data) and two batches ahead (list positions)
+    const int pos0 = lane < n ? gl[lane] : -1;
+    int posn = 64 + lane < n ? gl[64 + lane] : -1;
+    GridFetch<T> nxt;
+    grid_fetch<T>(nxt, pos0, cell, frac, vals, weight);
     for (int e = lane; e < TT * TS; e += 64) acc[e] = {T(0), T(0)};
-    const int32_t* rg = granges + ((size_t)u.l * ntiles + u.tile) * (2 * N_GRANGES);
-    int pref[N_GRANGES + 1];
-    pref[0] = 0;
-#pragma unroll
-    for (int r = 0; r < N_GRANGES; ++r) pref[r + 1] = pref[r] + (rg[2 * r + 1] - rg[2 * r]);
-    const int E = pref[N_GRANGES];
-    const int e0 = (int)(((int64_t)u.split * E) / u.nsplit);
-    const int e1 = (int)(((int64_t)(u.split + 1) * E) / u.nsplit);
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    const int jx = lane & 7, jy = lane >> 3;
-    for (int base = e0; base < e1; base += 64) {
+    // no run is open before the first entry: a key far outside the tile
+    constexpr int NOKEY = (0x4000 << 16) | 0x4000;
+    int prev = NOKEY, slot = -1;                 // slot: this lane's cell of the open run (-1: none)
+    cplx<T> racc{T(0), T(0)};
+    for (int base = 0; base < n; base += 64) {
         const int e = base + lane;
-        int packed = (int)(0x8000u << 16);   // sentinel: every tap falls outside the core
-        if (e < e1) {
-            int r = 0;
-#pragma unroll
-            for (int q = 1; q < N_GRANGES; ++q) r += (e >= pref[q]) ? 1 : 0;
-            const int pos = rg[2 * r] + (e - pref[r]);
-            const int cc = cell[pos];
-            int relx = (cc & 0xFFFF) - ox, rely = (cc >> 16) - oy;
+        const GridFetch<T> g = nxt;
+        if (base + 64 < n) {
+            grid_fetch<T>(nxt, posn, cell, frac, vals, weight);
+            posn = base + 128 + lane < n ? gl[base + 128 + lane] : -1;
+        }
+        int key = NOKEY;
+        T* wv = wts + lane * GW;
+        if (e < n) {
+            int relx = (g.cc & 0xFFFF) - ox, rely = (g.cc >> 16) - oy;
             if (relx < -TT) relx += Kx;
             if (relx >= 2 * TT) relx -= Kx;
             if (rely < -TT) rely += Ky;
             if (rely >= 2 * TT) rely -= Ky;
-            const cplx<T> f = frac[pos];
-            cplx<T> val = vals[pos];
-            if (weight) {
-                const T w = weight[pos];
-                val.re *= w;
-                val.im *= w;
-            }
+            key = ((rely - 3) << 16) | ((relx - 3) & 0xFFFF);
             T w8[KB_J];
-            kb_weights(f.re, kb, w8);
+            kb_weights(g.f.re, kb, w8);
 #pragma unroll
-            for (int j = 0; j < KB_J; ++j) wts[lane * 16 + j] = w8[j];
-            kb_weights(f.im, kb, w8);
+            for (int j = 0; j < KB_J; ++j) wv[j] = w8[j];
+            kb_weights(g.f.im, kb, w8);
 #pragma unroll
-            for (int j = 0; j < KB_J; ++j) wts[lane * 16 + 8 + j] = w8[j];
-            vv[lane] = val;
-            packed = ((rely - 3) << 16) | ((relx - 3) & 0xFFFF);
+            for (int j = 0; j < KB_J; ++j) wv[8 + j] = w8[j];
+            vv[lane] = g.val;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) wv[j] = T(0);
+            vv[lane] = {T(0), T(0)};
         }
-        rel[lane] = packed;
+        // a run starts where the key changes (the previous batch's last key carries over)
+        int before = __shfl_up(key, 1);
+        if (lane == 0) before = prev;
+        const unsigned long long starts = __ballot(e < n && key != before);
+        prev = __shfl(key, 63);
         __syncthreads();
-        const int nv = min(64, e1 - base);
-        for (int v = 0; v < nv; ++v) {
-            const int pk = rel[v];
-            const int ry = (pk >> 16) + jy;
-            const int rx = (int)(short)(pk & 0xFFFF) + jx;
-            if (ry >= 0 && ry < TT && rx >= 0 && rx < TT) {
-                const T w = wts[v * 16 + jx] * wts[v * 16 + 8 + jy];
-                const cplx<T> val = vv[v];
-                cplx<T> a = acc[ry * TS + rx];
-                a.re += w * val.re;
-                a.im += w * val.im;
-                acc[ry * TS + rx] = a;
+        // walk the batch; entry v + 1's staged values are loaded while entry v is added
+        T wxn = wts[jx], wyn = wts[8 + jy];
+        cplx<T> valn = vv[0];
+#pragma unroll
+        for (int v = 0; v < 64; ++v) {
+            const T wx = wxn, wy = wyn;
+            const cplx<T> val = valn;
+            if (v < 63) {
+                wxn = wts[(v + 1) * GW + jx];
+                wyn = wts[(v + 1) * GW + 8 + jy];
+                valn = vv[v + 1];
             }
+            if ((starts >> v) & 1ull) {
+                grid_flush<T>(acc, slot, racc);
+                racc = {T(0), T(0)};
+                slot = grid_slot(__builtin_amdgcn_readlane(key, v), TS, TT, jx, jy, lane_off);
+            }
+            const T w = wx * wy;
+            racc.re += w * val.re;
+            racc.im += w * val.im;
         }
         __syncthreads();
     }
+    grid_flush<T>(acc, slot, racc);
+    __syncthreads();
     if (u.nsplit == 1) {
         cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
         for (int e = lane; e < TT * TT; e += 64) {
@@ -871,11 +933,10 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
 
 template <typename T>
 void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    const size_t lds = (size_t)c->T * (c->T + GR_PAD) * sizeof(cplx<T>) + 64 * 16 * sizeof(T) +
-                       64 * sizeof(cplx<T>) + 64 * sizeof(int);
+    const size_t lds = (size_t)c->T * (c->T + GR_PAD) * sizeof(cplx<T>) + 64 * sizeof(cplx<T>) + 64 * GW * sizeof(T);
     k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
-        c->d.gunits, c->d.granges, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
-        (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, c->ntiles, kbpoly<T>(c));
+        c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
+        (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
     if (!c->splits.empty())
         k_grid_merge<T><<<(unsigned)c->splits.size(), 256, 0, c->stream>>>(
             c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Kx, c->Ky, c->T, c->tiles_x);
