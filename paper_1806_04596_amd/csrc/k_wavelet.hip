@@ -22,14 +22,95 @@ namespace hs {
 constexpr int WV_TB = 16;   // analysis output tile per subband
 constexpr int WV_TO = 32;   // synthesis output tile
 constexpr int WV_HALO = 14; // 2 * 8 - 2
+constexpr int WV_W = WV_TO / 2 + 8;   // synthesis coefficient window per subband
+
+// k mod n for 0 <= k < 2n + W (one subtraction in the usual case; small
+// coarse levels fall back to the remainder).
+__device__ __forceinline__ int wrap_idx(int k, int n) {
+    if (k >= n) k -= n;
+    if (k >= n) k %= n;
+    return k;
+}
+
+// Filter taps of basis b (db(b+1): NT = 2(b+1) taps); the loops below are
+// unrolled per NT, so the coefficients are uniform (scalar) operands.
+#define WV_DISPATCH(b, FN, ...)                         \
+    switch (b) {                                        \
+        case 0: FN<T, 2>(__VA_ARGS__); break;           \
+        case 1: FN<T, 4>(__VA_ARGS__); break;           \
+        case 2: FN<T, 6>(__VA_ARGS__); break;           \
+        case 3: FN<T, 8>(__VA_ARGS__); break;           \
+        case 4: FN<T, 10>(__VA_ARGS__); break;          \
+        case 5: FN<T, 12>(__VA_ARGS__); break;          \
+        case 6: FN<T, 14>(__VA_ARGS__); break;          \
+        default: FN<T, 16>(__VA_ARGS__); break;         \
+    }
+
+constexpr int WV_WI = 2 * WV_TB + WV_HALO;   // analysis input window edge
+
+// Analysis rows: a | d for every needed input row (2 TB + NT - 2 rows).
+template <typename T, int NT>
+__device__ __forceinline__ void dwt_rows(const T* __restrict__ f, const T (*inS)[WV_WI + 1], T (*tmpS)[2 * WV_TB + 1]) {
+    constexpr int TB = WV_TB, NR = 2 * TB + NT - 2;
+    T h[NT], g[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        h[j] = f[j];
+        g[j] = f[16 + j];
+    }
+    for (int e = threadIdx.x; e < NR * TB; e += blockDim.x) {
+        const int r = e / TB, kx = e - r * TB;
+        T a = T(0), d = T(0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const T x = inS[r][2 * kx + j];
+            a += h[j] * x;
+            d += g[j] * x;
+        }
+        tmpS[r][kx] = a;
+        tmpS[r][TB + kx] = d;
+    }
+}
+
+// Analysis columns: the four subbands of output (ky, kx), written to their places.
+template <typename T, int NT>
+__device__ __forceinline__ void dwt_cols(const T* __restrict__ f, const T (*tmpS)[2 * WV_TB + 1], T* __restrict__ cb,
+                                         T* __restrict__ llb, int ky0, int kx0, int hx, int hy, int nx, int last) {
+    constexpr int TB = WV_TB;
+    T h[NT], g[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        h[j] = f[j];
+        g[j] = f[16 + j];
+    }
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+        const int ky = e / TB, kx = e - ky * TB;
+        T aa = T(0), da = T(0), ad = T(0), dd = T(0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const T lo = tmpS[2 * ky + j][kx], hi = tmpS[2 * ky + j][TB + kx];
+            aa += h[j] * lo;
+            da += g[j] * lo;
+            ad += h[j] * hi;
+            dd += g[j] * hi;
+        }
+        const int gy = ky0 + ky, gx = kx0 + kx;
+        if (gy < hy && gx < hx) {
+            cb[(size_t)gy * nx + hx + gx] = ad;
+            cb[(size_t)(hy + gy) * nx + gx] = da;
+            cb[(size_t)(hy + gy) * nx + hx + gx] = dd;
+            if (last) cb[(size_t)gy * nx + gx] = aa;
+            else llb[(size_t)gy * hx + gx] = aa;
+        }
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, const T* __restrict__ llin,
                                                    T* __restrict__ coef, T* __restrict__ llout,
                                                    const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                    int lev0, int last, int n_db) {
-    constexpr int TB = WV_TB;
-    constexpr int WI = 2 * TB + WV_HALO;   // input window edge
+    constexpr int TB = WV_TB, WI = WV_WI;
     __shared__ T inS[WI][WI + 1];
     __shared__ T tmpS[WI][2 * TB + 1];
     const int hx = mx >> 1, hy = my >> 1;
@@ -47,52 +128,19 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
             const int stride = lev0 ? nx : mx;
             for (int e = tid; e < WI * WI; e += 256) {
                 const int r = e / WI, cc = e - r * WI;
-                const int gy = (2 * ky0 + r) % my, gx = (2 * kx0 + cc) % mx;
+                const int gy = wrap_idx(2 * ky0 + r, my), gx = wrap_idx(2 * kx0 + cc, mx);
                 inS[r][cc] = src[(size_t)gy * stride + gx];
             }
             __syncthreads();
-        } else if (!lev0) {
+        } else {
             __syncthreads();
         }
-        const T* h = filt + b * 32;
-        const T* g = h + 16;
-        const int nt = 2 * (b + 1);
-        const int nrows = 2 * TB + nt - 2;
-        // rows (x): a | d for every needed input row
-        for (int e = tid; e < nrows * TB; e += 256) {
-            const int r = e / TB, kx = e - r * TB;
-            T a = T(0), d = T(0);
-            for (int j = 0; j < nt; ++j) {
-                const T x = inS[r][2 * kx + j];
-                a += h[j] * x;
-                d += g[j] * x;
-            }
-            tmpS[r][kx] = a;
-            tmpS[r][TB + kx] = d;
-        }
+        const T* f = filt + b * 32;
+        WV_DISPATCH(b, dwt_rows, f, inS, tmpS)
         __syncthreads();
-        // columns (y): four subbands
-        for (int e = tid; e < TB * TB; e += 256) {
-            const int ky = e / TB, kx = e - ky * TB;
-            T aa = T(0), da = T(0), ad = T(0), dd = T(0);
-            for (int j = 0; j < nt; ++j) {
-                const T lo = tmpS[2 * ky + j][kx], hi = tmpS[2 * ky + j][TB + kx];
-                aa += h[j] * lo;
-                da += g[j] * lo;
-                ad += h[j] * hi;
-                dd += g[j] * hi;
-            }
-            const int gy = ky0 + ky, gx = kx0 + kx;
-            if (gy < hy && gx < hx) {
-                T* cb = coef + ((size_t)b * L + l) * N;
-                cb[(size_t)gy * nx + hx + gx] = ad;
-                cb[(size_t)(hy + gy) * nx + gx] = da;
-                cb[(size_t)(hy + gy) * nx + hx + gx] = dd;
-                if (last) cb[(size_t)gy * nx + gx] = aa;
-                else llout[((size_t)b * L + l) * (size_t)hy * hx + (size_t)gy * hx + gx] = aa;
-            }
-        }
-        __syncthreads();
+        T* cb = coef + ((size_t)b * L + l) * N;
+        T* llb = llout + ((size_t)b * L + l) * (size_t)hy * hx;
+        WV_DISPATCH(b, dwt_cols, f, tmpS, cb, llb, ky0, kx0, hx, hy, nx, last)
     }
 }
 
@@ -101,14 +149,69 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
 // (approximation from the coarser synthesis, or from C at the coarsest level),
 // inverts along y then x in LDS, and writes a compact approximation for the
 // next finer level.  At level 0 it loops over the bases and writes
-// Xout = C0 + sum_b Psi_b C_b once.
+// Xout = C0 + sum_b Psi_b C_b once.  Outputs 2p and 2p + 1 of a filter pass
+// read the same coefficients (even taps for the first, odd for the second), so
+// each thread produces such a pair.
+template <typename T, int NT>
+__device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T (*S)[WV_W][WV_W + 1],
+                                       T (*Tm)[WV_TO][WV_W + 1]) {
+    constexpr int TO = WV_TO, W = WV_W;
+    T h[NT], g[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        h[j] = f[j];
+        g[j] = f[16 + j];
+    }
+    for (int e = threadIdx.x; e < 2 * (TO / 2) * W; e += blockDim.x) {
+        const int wx = e % W, t = e / W;
+        const int p = t % (TO / 2), sx = t / (TO / 2);
+        T xe = T(0), xo = T(0);
+#pragma unroll
+        for (int i = 0; i < NT / 2; ++i) {
+            const int w = p - i + 8;
+            const T a = S[sx][w][wx], d = S[2 + sx][w][wx];
+            xe += h[2 * i] * a + g[2 * i] * d;
+            xo += h[2 * i + 1] * a + g[2 * i + 1] * d;
+        }
+        Tm[sx][2 * p][wx] = xe;
+        Tm[sx][2 * p + 1][wx] = xo;
+    }
+}
+
+// x pass: thread item k covers row m = e / (TO/2), columns 2q, 2q + 1.
+template <typename T, int NT>
+__device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV_TO][WV_W + 1], T (&res)[2][2]) {
+    constexpr int TO = WV_TO;
+    T h[NT], g[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        h[j] = f[j];
+        g[j] = f[16 + j];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = threadIdx.x + k * 256;
+        const int m = e / (TO / 2), q = e % (TO / 2);
+        T xe = T(0), xo = T(0);
+#pragma unroll
+        for (int i = 0; i < NT / 2; ++i) {
+            const int w = q - i + 8;
+            const T a = Tm[0][m][w], d = Tm[1][m][w];
+            xe += h[2 * i] * a + g[2 * i] * d;
+            xo += h[2 * i + 1] * a + g[2 * i + 1] * d;
+        }
+        res[k][0] = xe;
+        res[k][1] = xo;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
                                                     T* __restrict__ out, const T* __restrict__ C0,
                                                     const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                     int coarsest, int final_level, int n_db) {
-    constexpr int TO = WV_TO;
-    constexpr int W = TO / 2 + 8;          // coefficient window per subband
+    constexpr int TO = WV_TO, W = WV_W;
+    static_assert(TO * TO / 2 == 2 * 256, "two output pairs per thread");
     __shared__ T S[4][W][W + 1];           // subband (sy*2 + sx)
     __shared__ T Tm[2][TO][W + 1];         // after the column inverse, per x-subband
     const int hx = mx >> 1, hy = my >> 1;
@@ -121,74 +224,58 @@ __global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, con
     if (kylo < 0) kylo += hy;
     int kxlo = (m0x / 2 - 8) % hx;
     if (kxlo < 0) kxlo += hx;
-    constexpr int PER = (TO * TO + 255) / 256;
-    T accv[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) accv[k] = T(0);
+    T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
     const int b_first = final_level ? 0 : (int)blockIdx.z;
     const int b_last = final_level ? n_db : (int)blockIdx.z + 1;
     for (int b = b_first; b < b_last; ++b) {
         const T* Cb = C + ((size_t)b * L + l) * N;
         const T* LLb = coarsest ? nullptr : llin + ((size_t)b * L + l) * (size_t)hy * hx;
         for (int e = tid; e < 4 * W * W; e += 256) {
-            const int sb = e / (W * W), r = (e / W) % W, cc = e % W;
+            const int sb = e / (W * W), rem = e - sb * (W * W);
+            const int r = rem / W, cc = rem - r * W;
             const int sy = sb >> 1, sx = sb & 1;
-            int ky = kylo + r, kx = kxlo + cc;
-            while (ky >= hy) ky -= hy;
-            while (kx >= hx) kx -= hx;
+            const int ky = wrap_idx(kylo + r, hy), kx = wrap_idx(kxlo + cc, hx);
             T v;
             if (sb == 0 && !coarsest) v = LLb[(size_t)ky * hx + kx];
             else v = Cb[(size_t)(sy * hy + ky) * nx + sx * hx + kx];
             S[sb][r][cc] = v;
         }
         __syncthreads();
-        const T* h = filt + b * 32;
-        const T* g = h + 16;
-        const int nt = 2 * (b + 1);
-        // inverse along y: Tm[sx][m][wx]
-        for (int e = tid; e < 2 * TO * W; e += 256) {
-            const int sx = e / (TO * W), m = (e / W) % TO, wx = e % W;
-            const int gm = m0y + m;
-            T x = T(0);
-            // window row r holds coefficient (m0y/2 - 8 + r) mod hy, so tap j of
-            // output row m0y + m reads row (m - j)/2 + 8 (m0y even, j = m mod 2)
-            for (int j = (m & 1); j < nt; j += 2) {
-                const int w = ((m - j) >> 1) + 8;
-                x += h[j] * S[sx][w][wx] + g[j] * S[2 + sx][w][wx];
-            }
-            Tm[sx][m][wx] = x;
-        }
+        const T* f = filt + b * 32;
+        WV_DISPATCH(b, idwt_y, f, S, Tm)
         __syncthreads();
-        // inverse along x
+        T res[2][2];
+        WV_DISPATCH(b, idwt_x, f, Tm, res)
+        if (final_level) {
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = tid + k * 256;
-            if (e < TO * TO) {
-                const int m = e / TO, n = e % TO;
-                const int gn = m0x + n;
-                T x = T(0);
-                for (int j = (n & 1); j < nt; j += 2) {
-                    const int w = ((n - j) >> 1) + 8;
-                    x += h[j] * Tm[0][m][w] + g[j] * Tm[1][m][w];
+            for (int k = 0; k < 2; ++k) {
+                acc[k][0] += res[k][0];
+                acc[k][1] += res[k][1];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int e = tid + k * 256;
+                const int m = e / (TO / 2), n = 2 * (e % (TO / 2));
+                if (m0y + m < my && m0x + n < mx) {
+                    T* o = out + ((size_t)b * L + l) * (size_t)my * mx + (size_t)(m0y + m) * mx + m0x + n;
+                    o[0] = res[k][0];
+                    o[1] = res[k][1];
                 }
-                if (final_level) accv[k] += x;
-                else if (m0y + m < my && gn < mx)
-                    out[((size_t)b * L + l) * (size_t)my * mx + (size_t)(m0y + m) * mx + gn] = x;
             }
         }
         __syncthreads();
     }
     if (final_level) {
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
+        for (int k = 0; k < 2; ++k) {
             const int e = tid + k * 256;
-            if (e < TO * TO) {
-                const int m = e / TO, n = e % TO;
-                const int gy = m0y + m, gx = m0x + n;
-                if (gy < my && gx < mx) {
-                    const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
-                    out[idx] = (C0 ? C0[idx] : T(0)) + accv[k];
-                }
+            const int m = e / (TO / 2), n = 2 * (e % (TO / 2));
+            const int gy = m0y + m, gx = m0x + n;
+            if (gy < my && gx < mx) {
+                const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
+                out[idx] = (C0 ? C0[idx] : T(0)) + acc[k][0];
+                out[idx + 1] = (C0 ? C0[idx + 1] : T(0)) + acc[k][1];
             }
         }
     }
