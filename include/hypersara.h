@@ -54,7 +54,7 @@ enum { HS_NORM_PHI_PRECOND = 0, HS_NORM_PSI = 1 };
 typedef struct hs_ctx hs_ctx;
 
 /* Problem description (Sec. 2.1 data model, Sec. 2.3 dictionary).
- * nx, ny: image size; powers of two in 16..16384 (and >= 2^levels).
+ * nx, ny: image size; powers of two in 16..2048 (and >= 2^levels).
  * L: number of channels (1..64).
  * oversamp: grid oversampling per dimension; must be 2.
  * J: Kaiser-Bessel support per dimension; must be 8.

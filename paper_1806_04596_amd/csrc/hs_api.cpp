@@ -402,10 +402,10 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
     if (d.levels < 1 || d.levels > 6 || d.n_db < 0 || d.n_db > MAX_DB)
         return fail(nullptr, HS_ERR_INVALID_ARG, "levels in 1..6 and n_db in 0..8");
     const int q = 1 << d.levels;
-    if (d.nx < 16 || d.ny < 16 || d.nx % q || d.ny % q || d.nx > 16384 || d.ny > 16384 || (d.nx & (d.nx - 1)) ||
+    // one FFT line of the 2x oversampled grid (<= 4096 points) lives in one workgroup's LDS
+    if (d.nx < 16 || d.ny < 16 || d.nx % q || d.ny % q || d.nx > 2048 || d.ny > 2048 || (d.nx & (d.nx - 1)) ||
         (d.ny & (d.ny - 1)))
-        return fail(nullptr, HS_ERR_SHAPE, "nx, ny must be powers of two in 16..16384 and multiples of 2^levels");
-    if (2 * d.nx > 4096 * 8 || 2 * d.ny > 4096 * 8) return fail(nullptr, HS_ERR_SHAPE, "grid too large");
+        return fail(nullptr, HS_ERR_SHAPE, "nx, ny must be powers of two in 16..2048 and multiples of 2^levels");
     int dev_count = 0;
     const hipError_t derr = hipGetDeviceCount(&dev_count);
     if (derr != hipSuccess || d.device < 0 || d.device >= dev_count)

@@ -32,213 +32,245 @@ template <typename T>
 __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
 
 // ------------------------------------------------------------------ FFT core
-// In-place Stockham autosort FFT over `nseq` sequences of length n held in
-// LDS; element k of sequence s lives at buf[k*es + s*ss].  Each stage loads its
-// butterflies into registers, synchronises, and stores them at their
-// autosorted positions.  tw[k] = exp(-2 pi i k / n); INV uses the conjugate.
-template <typename T, bool INV, int KPT>
-__device__ __forceinline__ void fft_lds(cplx<T>* buf, int n, int nseq, int es, int ss, bool seq_fast,
-                        const cplx<T>* __restrict__ tw) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int lgseq = __builtin_ctz(nseq);
-    cplx<T> r[4 * KPT];
-    for (int Ns = 1; Ns < n;) {
-        if (n / Ns >= 4) {
-            // radix-4 stage: KPT butterflies per thread
-            const int nb = n >> 2;
-            const int lgnb = __builtin_ctz(nb);
-            const int total = nb * nseq;
-            const int tstride = n / (Ns * 4);
+// Stockham autosort FFT of length n (a power of two, 2..4096) with 16 elements
+// per thread.  Each pass has radix R = min(16, n / Ns) (Ns: product of the
+// radices before it); a thread owns 16 / R butterflies.  Butterfly j reads
+// in[j + k n/R] (k < R), multiplies by w^(k jm) (jm = j mod Ns, w = e^(-2 pi i/(Ns R))),
+// takes the R-point DFT in registers and writes out[(j - jm) R + jm + k Ns].
+// The first pass reads its inputs from global memory and the last pass writes
+// to global memory; LDS only carries data between passes (n = 1024: 3 passes).
+// tw[m] = exp(-2 pi i m / n); INV uses the conjugate.
+
+// e^(-2 pi i k / 16) for k < 8 (cos, sin): compile-time twiddles of the register DFTs.
+__device__ constexpr double kW16c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+__device__ constexpr double kW16s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                        1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+
+// t * e^(-+2 pi i k / R) for a compile-time k (after unrolling).
+template <typename T, bool INV, int R>
+__device__ __forceinline__ cplx<T> tw_const(cplx<T> t, int k) {
+    if (k == 0) return t;
+    if (4 * k == R) return INV ? cplx<T>{-t.im, t.re} : cplx<T>{t.im, -t.re};
+    const T c = (T)kW16c[k * (16 / R)], sn = (T)kW16s[k * (16 / R)];
+    return INV ? cplx<T>{t.re * c - t.im * sn, t.im * c + t.re * sn} : cplx<T>{t.re * c + t.im * sn, t.im * c - t.re * sn};
+}
+
+// In-register DFT of a[0..R-1] (natural order in and out), decimation in time.
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void dft_reg(cplx<T>* a) {
+    if constexpr (R > 1) {
+        cplx<T> e[R / 2], o[R / 2];
 #pragma unroll
-            for (int k = 0; k < KPT; ++k) {
-                const int b = tid + k * nth;
-                if (b < total) {
-                    int s, j;
-                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
-                    const int jm = j & (Ns - 1);
-                    cplx<T>* base = buf + s * ss;
-                    cplx<T> a0 = base[j * es];
-                    cplx<T> a1 = base[(j + nb) * es];
-                    cplx<T> a2 = base[(j + 2 * nb) * es];
-                    cplx<T> a3 = base[(j + 3 * nb) * es];
-                    if (Ns > 1) {
-                        cplx<T> w1 = tw[jm * tstride], w2 = tw[2 * jm * tstride], w3 = tw[3 * jm * tstride];
-                        if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
-                        a1 = cmul(a1, w1); a2 = cmul(a2, w2); a3 = cmul(a3, w3);
-                    }
-                    const cplx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
-                    const cplx<T> s13 = cadd(a1, a3), d13 = csub(a1, a3);
-                    // d13 times -i (forward) or +i (inverse)
-                    const cplx<T> jd13 = INV ? cplx<T>{-d13.im, d13.re} : cplx<T>{d13.im, -d13.re};
-                    r[4 * k + 0] = cadd(s02, s13);
-                    r[4 * k + 1] = cadd(d02, jd13);
-                    r[4 * k + 2] = csub(s02, s13);
-                    r[4 * k + 3] = csub(d02, jd13);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < KPT; ++k) {
-                const int b = tid + k * nth;
-                if (b < total) {
-                    int s, j;
-                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
-                    const int jm = j & (Ns - 1);
-                    const int idxD = (j - jm) * 4 + jm;
-                    cplx<T>* base = buf + s * ss;
-                    base[idxD * es] = r[4 * k + 0];
-                    base[(idxD + Ns) * es] = r[4 * k + 1];
-                    base[(idxD + 2 * Ns) * es] = r[4 * k + 2];
-                    base[(idxD + 3 * Ns) * es] = r[4 * k + 3];
-                }
-            }
-            __syncthreads();
-            Ns <<= 2;
-        } else {
-            // radix-2 stage: 2*KPT butterflies per thread
-            const int nb = n >> 1;
-            const int lgnb = __builtin_ctz(nb);
-            const int total = nb * nseq;
-            const int tstride = n / (Ns * 2);
-#pragma unroll
-            for (int k = 0; k < 2 * KPT; ++k) {
-                const int b = tid + k * nth;
-                if (b < total) {
-                    int s, j;
-                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
-                    const int jm = j & (Ns - 1);
-                    cplx<T>* base = buf + s * ss;
-                    cplx<T> a0 = base[j * es];
-                    cplx<T> a1 = base[(j + nb) * es];
-                    if (Ns > 1) {
-                        cplx<T> w1 = tw[jm * tstride];
-                        if (INV) w1.im = -w1.im;
-                        a1 = cmul(a1, w1);
-                    }
-                    r[2 * k + 0] = cadd(a0, a1);
-                    r[2 * k + 1] = csub(a0, a1);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 2 * KPT; ++k) {
-                const int b = tid + k * nth;
-                if (b < total) {
-                    int s, j;
-                    if (seq_fast) { s = b & (nseq - 1); j = b >> lgseq; } else { j = b & (nb - 1); s = b >> lgnb; }
-                    const int jm = j & (Ns - 1);
-                    const int idxD = (j - jm) * 2 + jm;
-                    cplx<T>* base = buf + s * ss;
-                    base[idxD * es] = r[2 * k + 0];
-                    base[(idxD + Ns) * es] = r[2 * k + 1];
-                }
-            }
-            __syncthreads();
-            Ns <<= 1;
+        for (int k = 0; k < R / 2; ++k) {
+            e[k] = a[2 * k];
+            o[k] = a[2 * k + 1];
         }
+        dft_reg<T, INV, R / 2>(e);
+        dft_reg<T, INV, R / 2>(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            const cplx<T> t = tw_const<T, INV, R>(o[k], k);
+            a[k] = cadd(e[k], t);
+            a[k + R / 2] = csub(e[k], t);
+        }
+    }
+}
+
+// Butterfly m of this thread: j = u + m n/16.
+__device__ __forceinline__ int fft_bj(int u, int m, int n) { return u + m * (n >> 4); }
+
+// Twiddles and DFTs of the 16/R butterflies held in a (butterfly m at a[m R ..]).
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void fft_compute(cplx<T>* a, int u, int n, int Ns, const cplx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int j = fft_bj(u, m, n);
+        const int jm = j & (Ns - 1);
+        if (Ns > 1) {
+            const int step = jm * (n / (Ns * R));
+#pragma unroll
+            for (int k = 1; k < R; ++k) {
+                cplx<T> w = tw[k * step];
+                if (INV) w.im = -w.im;
+                a[m * R + k] = cmul(a[m * R + k], w);
+            }
+        }
+        dft_reg<T, INV, R>(a + m * R);
+    }
+}
+
+// LDS slot of element q of sequence s: column layout (es = CT, ss = 1) or
+// row layout (one pad slot per 16 elements, against stride-R bank conflicts).
+template <bool ROWS>
+__device__ __forceinline__ int fft_slot(int q, int s, int n, int CT) {
+    return ROWS ? s * (n + (n >> 4)) + q + (q >> 4) : q * CT + s;
+}
+
+template <typename T, bool ROWS, int R>
+__device__ __forceinline__ void fft_load_lds(cplx<T>* a, const cplx<T>* buf, int u, int s, int n, int CT) {
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int j = fft_bj(u, m, n);
+#pragma unroll
+        for (int k = 0; k < R; ++k) a[m * R + k] = buf[fft_slot<ROWS>(j + k * (n / R), s, n, CT)];
+    }
+}
+template <typename T, bool ROWS, int R>
+__device__ __forceinline__ void fft_store_lds(const cplx<T>* a, cplx<T>* buf, int u, int s, int n, int Ns, int CT) {
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int j = fft_bj(u, m, n);
+        const int jm = j & (Ns - 1);
+        const int o = (j - jm) * R + jm;
+#pragma unroll
+        for (int k = 0; k < R; ++k) buf[fft_slot<ROWS>(o + k * Ns, s, n, CT)] = a[m * R + k];
+    }
+}
+
+// First pass inputs from global: ld(q) gives element q of this thread's sequence.
+template <typename T, int R, typename LD>
+__device__ __forceinline__ void fft_load_glb(cplx<T>* a, int u, int n, LD ld) {
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int j = fft_bj(u, m, n);
+#pragma unroll
+        for (int k = 0; k < R; ++k) a[m * R + k] = ld(j + k * (n / R));
+    }
+}
+template <typename T, int R, typename ST>
+__device__ __forceinline__ void fft_store_glb(const cplx<T>* a, int u, int n, int Ns, ST st) {
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+        const int j = fft_bj(u, m, n);
+        const int jm = j & (Ns - 1);
+        const int o = (j - jm) * R + jm;
+#pragma unroll
+        for (int k = 0; k < R; ++k) st(o + k * Ns, a[m * R + k]);
+    }
+}
+
+#define HS_RADIX_SWITCH(R, BODY)                              \
+    switch (R) {                                              \
+        case 16: { constexpr int RR = 16; BODY; } break;      \
+        case 8: { constexpr int RR = 8; BODY; } break;        \
+        case 4: { constexpr int RR = 4; BODY; } break;        \
+        default: { constexpr int RR = 2; BODY; } break;       \
+    }
+
+// The whole transform of this thread's part of sequence s (u: thread index
+// within the sequence, n/16 threads per sequence).
+template <typename T, bool INV, bool ROWS, typename LD, typename ST>
+__device__ __forceinline__ void fft_run(cplx<T>* buf, int u, int s, int n, int CT, const cplx<T>* __restrict__ tw,
+                                        LD ld, ST st) {
+    cplx<T> a[16];
+    int Ns = 1;
+    int R = n < 16 ? n : 16;
+    HS_RADIX_SWITCH(R, (fft_load_glb<T, RR>(a, u, n, ld)))
+    for (;;) {
+        HS_RADIX_SWITCH(R, (fft_compute<T, INV, RR>(a, u, n, Ns, tw)))
+        if (Ns * R == n) {
+            HS_RADIX_SWITCH(R, (fft_store_glb<T, RR>(a, u, n, Ns, st)))
+            break;
+        }
+        HS_RADIX_SWITCH(R, (fft_store_lds<T, ROWS, RR>(a, buf, u, s, n, Ns, CT)))
+        __syncthreads();
+        Ns *= R;
+        R = (n / Ns) < 16 ? (n / Ns) : 16;
+        HS_RADIX_SWITCH(R, (fft_load_lds<T, ROWS, RR>(a, buf, u, s, n, CT)))
+        __syncthreads();
     }
 }
 
 // Row pass of F Z: rows j of image l are deapodised, placed at (i - nx/2) mod Kx
 // and transformed; H[l][j][:] holds the transformed row (only the ny rows Z fills).
-template <typename T, int KPT>
-__global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, cplx<T>* __restrict__ H, const T* __restrict__ sx,
-                               const T* __restrict__ sy, const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
-                               int rows) {
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, cplx<T>* __restrict__ H,
+                                                       const T* __restrict__ sx, const T* __restrict__ sy,
+                                                       const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                                                       int rows) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
-    const int j0 = blockIdx.x * rows;
-    const T* Xl = X + (size_t)l * nx * ny;
-    const int E = Kx * rows;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        const int s = e / Kx, q = e - s * Kx;
-        const int j = j0 + s;
-        int i = q + nx / 2;
-        if (i >= Kx) i -= Kx;
-        T v = (i < nx) ? Xl[(size_t)j * nx + i] * sx[i] * sy[j] : T(0);
-        buf[e] = {v, T(0)};
-    }
-    __syncthreads();
-    fft_lds<T, false, KPT>(buf, Kx, rows, 1, Kx, false, tw);
-    cplx<T>* Hl = H + ((size_t)l * ny + j0) * Kx;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) Hl[e] = buf[e];
+    const int tps = Kx >> 4;                        // threads per sequence
+    const int u = threadIdx.x % tps, s = threadIdx.x / tps;
+    const int j = blockIdx.x * rows + s;
+    const T* Xr = X + ((size_t)l * ny + j) * nx;
+    const T syj = sy[j];
+    cplx<T>* Hr = H + ((size_t)l * ny + j) * Kx;
+    fft_run<T, false, true>(buf, u, s, Kx, 0, tw,
+        [&](int q) {
+            int i = q + (nx >> 1);
+            if (i >= Kx) i -= Kx;
+            return cplx<T>{i < nx ? Xr[i] * sx[i] * syj : T(0), T(0)};
+        },
+        [&](int q, const cplx<T>& v) { Hr[q] = v; });
 }
 
 // Column pass of F: CT adjacent columns, rows placed at (j - ny/2) mod Ky.
-template <typename T, int KPT>
-__global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G, const cplx<T>* __restrict__ tw,
-                               int ny, int Kx, int Ky, int CT) {
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kx, int Ky,
+                                                       int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
-    const int c0 = blockIdx.x * CT;
-    const cplx<T>* Hl = H + (size_t)l * ny * Kx;
-    const int E = Ky * CT;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        const int q = e / CT, c = e - q * CT;
-        int j = q + ny / 2;
-        if (j >= Ky) j -= Ky;
-        buf[e] = (j < ny) ? Hl[(size_t)j * Kx + c0 + c] : cplx<T>{T(0), T(0)};
-    }
-    __syncthreads();
-    fft_lds<T, false, KPT>(buf, Ky, CT, CT, 1, true, tw);
-    cplx<T>* Gl = G + (size_t)l * Ky * Kx;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        const int k = e / CT, c = e - k * CT;
-        Gl[(size_t)k * Kx + c0 + c] = buf[e];
-    }
+    const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
+    const int c = blockIdx.x * CT + s;
+    const cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
+    cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
+    fft_run<T, false, false>(buf, u, s, Ky, CT, tw,
+        [&](int q) {
+            int j = q + (ny >> 1);
+            if (j >= Ky) j -= Ky;
+            return j < ny ? Hl[(size_t)j * Kx] : cplx<T>{T(0), T(0)};
+        },
+        [&](int q, const cplx<T>& v) { Gl[(size_t)q * Kx] = v; });
 }
 
 // Adjoint column pass: inverse (unnormalised) DFT along y, keep the rows Z^T reads.
-template <typename T, int KPT>
-__global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H, const cplx<T>* __restrict__ tw,
-                               int ny, int Kx, int Ky, int CT) {
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H,
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kx, int Ky,
+                                                       int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
-    const int c0 = blockIdx.x * CT;
-    const cplx<T>* Gl = G + (size_t)l * Ky * Kx;
-    const int E = Ky * CT;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        const int k = e / CT, c = e - k * CT;
-        buf[e] = Gl[(size_t)k * Kx + c0 + c];
-    }
-    __syncthreads();
-    fft_lds<T, true, KPT>(buf, Ky, CT, CT, 1, true, tw);
-    cplx<T>* Hl = H + (size_t)l * ny * Kx;
-    const int E2 = ny * CT;
-    for (int e = threadIdx.x; e < E2; e += blockDim.x) {
-        const int j = e / CT, c = e - j * CT;
-        int q = j - ny / 2;
-        if (q < 0) q += Ky;
-        Hl[(size_t)j * Kx + c0 + c] = buf[q * CT + c];
-    }
+    const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
+    const int c = blockIdx.x * CT + s;
+    const cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
+    cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
+    fft_run<T, true, false>(buf, u, s, Ky, CT, tw,
+        [&](int q) { return Gl[(size_t)q * Kx]; },
+        [&](int q, const cplx<T>& v) {
+            int j = q + (ny >> 1);
+            if (j >= Ky) j -= Ky;
+            if (j < ny) Hl[(size_t)j * Kx] = v;
+        });
 }
 
 // Adjoint row pass: inverse DFT along x, crop, deapodise, real part.
-template <typename T, int KPT>
-__global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict__ H, T* __restrict__ X, const T* __restrict__ sx,
-                               const T* __restrict__ sy, const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
-                               int rows) {
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict__ H, T* __restrict__ X,
+                                                       const T* __restrict__ sx, const T* __restrict__ sy,
+                                                       const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                                                       int rows) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
-    const int j0 = blockIdx.x * rows;
-    const cplx<T>* Hl = H + ((size_t)l * ny + j0) * Kx;
-    const int E = Kx * rows;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) buf[e] = Hl[e];
-    __syncthreads();
-    fft_lds<T, true, KPT>(buf, Kx, rows, 1, Kx, false, tw);
-    T* Xl = X + (size_t)l * nx * ny;
-    const int E2 = nx * rows;
-    for (int e = threadIdx.x; e < E2; e += blockDim.x) {
-        const int s = e / nx, i = e - s * nx;
-        const int j = j0 + s;
-        int q = i - nx / 2;
-        if (q < 0) q += Kx;
-        Xl[(size_t)j * nx + i] = buf[s * Kx + q].re * sx[i] * sy[j];
-    }
+    const int tps = Kx >> 4;
+    const int u = threadIdx.x % tps, s = threadIdx.x / tps;
+    const int j = blockIdx.x * rows + s;
+    const cplx<T>* Hr = H + ((size_t)l * ny + j) * Kx;
+    T* Xr = X + ((size_t)l * ny + j) * nx;
+    const T syj = sy[j];
+    fft_run<T, true, true>(buf, u, s, Kx, 0, tw,
+        [&](int q) { return Hr[q]; },
+        [&](int q, const cplx<T>& v) {
+            int i = q + (nx >> 1);
+            if (i >= Kx) i -= Kx;
+            if (i < nx) Xr[i] = v.re * sx[i] * syj;
+        });
 }
 
 template <typename KF>
@@ -246,48 +278,40 @@ static void set_lds(KF kern, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Rows per workgroup for the row passes (power of two dividing ny, Kx*rows <= 4096).
+// Rows per workgroup for the row passes (power of two dividing ny, Kx * rows <= 8192: <= 512 threads).
 static int row_group(const hs_ctx* c) {
     int rows = 1;
-    while (rows * 2 <= c->ny && (c->ny % (rows * 2)) == 0 && c->Kx * rows * 2 <= 4096) rows *= 2;
+    while (rows * 2 <= c->ny && (c->ny % (rows * 2)) == 0 && c->Kx * rows * 2 <= 8192) rows *= 2;
     return rows;
 }
-// Columns per tile for the column passes (LDS <= 128 KiB).
+// Columns per tile for the column passes (16 elements per thread, <= 512 threads, LDS <= 128 KiB).
 template <typename T>
 static int col_group(const hs_ctx* c) {
     const int maxE = (int)(131072 / sizeof(cplx<T>));
     int ct = 1;
-    while (ct * 2 <= c->Kx && c->Kx % (ct * 2) == 0 && c->Ky * ct * 2 <= maxE && ct < 32) ct *= 2;
+    while (ct * 2 <= c->Kx && c->Kx % (ct * 2) == 0 && c->Ky * ct * 2 <= maxE && c->Ky * ct * 2 <= 8192 && ct < 16)
+        ct *= 2;
     return ct;
 }
-
-// Launch one of the FFT kernels with KPT chosen so that nth = E / (4 KPT) <= 256.
-#define HS_FFT_DISPATCH(KERN, T, E, GRID, STREAM, ...)                                          \
-    do {                                                                                         \
-        const int E_ = (E);                                                                      \
-        const size_t lds_ = (size_t)E_ * sizeof(cplx<T>);                                        \
-        if (sizeof(T) == 4 && E_ >= 8192) {                                                      \
-            KERN<T, 8><<<GRID, E_ / 32, lds_, STREAM>>>(__VA_ARGS__);                            \
-        } else {                                                                                 \
-            KERN<T, 4><<<GRID, (E_ / 16 > 0 ? E_ / 16 : 1), lds_, STREAM>>>(__VA_ARGS__);       \
-        }                                                                                        \
-    } while (0)
+static size_t row_lds(const hs_ctx* c, int rows, size_t csz) {
+    return (size_t)rows * (c->Kx + (c->Kx >> 4)) * csz;
+}
 
 // Allow up to 160 KiB of dynamic LDS for every FFT instantiation (set once,
 // outside any stream capture).
-template <typename T, int KPT>
+template <typename T>
 static void fft_attrs_one() {
     const size_t b = 160 * 1024;
-    set_lds(k_fft_rows_fwd<T, KPT>, b);
-    set_lds(k_fft_cols_fwd<T, KPT>, b);
-    set_lds(k_fft_cols_adj<T, KPT>, b);
-    set_lds(k_fft_rows_adj<T, KPT>, b);
+    set_lds(k_fft_rows_fwd<T>, b);
+    set_lds(k_fft_cols_fwd<T>, b);
+    set_lds(k_fft_cols_adj<T>, b);
+    set_lds(k_fft_rows_adj<T>, b);
 }
 void fft_init_attrs() {
     static bool done = false;
     if (done) return;
-    fft_attrs_one<float, 4>(); fft_attrs_one<float, 8>();
-    fft_attrs_one<double, 4>();
+    fft_attrs_one<float>();
+    fft_attrs_one<double>();
     done = true;
 }
 
@@ -295,29 +319,35 @@ template <typename T>
 void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L) {
     const int rows = row_group(c);
     dim3 grid(c->ny / rows, L);
-    HS_FFT_DISPATCH(k_fft_rows_fwd, T, c->Kx * rows, grid, c->stream, X, (cplx<T>*)c->d.H, (const T*)c->d.sx,
-                    (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx, rows);
+    const int nth = std::max(1, c->Kx * rows / 16);
+    k_fft_rows_fwd<T><<<grid, nth, row_lds(c, rows, sizeof(cplx<T>)), c->stream>>>(
+        X, (cplx<T>*)c->d.H, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx,
+        rows);
 }
 template <typename T>
 void launch_fft_cols_fwd(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
     dim3 grid(c->Kx / ct, L);
-    HS_FFT_DISPATCH(k_fft_cols_fwd, T, c->Ky * ct, grid, c->stream, (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid,
-                    (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+    const int nth = std::max(1, c->Ky * ct / 16);
+    k_fft_cols_fwd<T><<<grid, nth, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
 }
 template <typename T>
 void launch_fft_cols_adj(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
     dim3 grid(c->Kx / ct, L);
-    HS_FFT_DISPATCH(k_fft_cols_adj, T, c->Ky * ct, grid, c->stream, (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H,
-                    (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+    const int nth = std::max(1, c->Ky * ct / 16);
+    k_fft_cols_adj<T><<<grid, nth, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
 }
 template <typename T>
 void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
     const int rows = row_group(c);
     dim3 grid(c->ny / rows, L);
-    HS_FFT_DISPATCH(k_fft_rows_adj, T, c->Kx * rows, grid, c->stream, (const cplx<T>*)c->d.H, Xout,
-                    (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx, rows);
+    const int nth = std::max(1, c->Kx * rows / 16);
+    k_fft_rows_adj<T><<<grid, nth, row_lds(c, rows, sizeof(cplx<T>)), c->stream>>>(
+        (const cplx<T>*)c->d.H, Xout, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
+        c->Kx, rows);
 }
 
 // ------------------------------------------------------------- KB kernel
