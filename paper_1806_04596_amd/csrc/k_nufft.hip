@@ -639,35 +639,29 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 // arrive in runs.  Lane (jx, jy) owns tap (jx, jy) of the current footprint:
 // within a run every lane adds phi_x(jx) phi_y(jy) val into one register; at
 // the end of a run the 64 sums are added into the tile accumulator in LDS (a
-// plain read-modify-write: the 64 taps are 64 distinct cells).  No atomics;
-// the summation order is fixed by the list.
-// Entries come in batches of 64: lane i stages the 8 + 8 kernel values and
-// the value of entry i in LDS; a ballot marks where runs start; the walk over
-// the batch is unrolled, so every LDS address in it is an immediate offset.
-constexpr int GR_PAD = 8;   // accumulator row stride T + 8: a footprint's 8 rows fall in distinct banks
+// plain read-modify-write: the 64 taps are 64 distinct cells).  The
+// accumulator has a 7-cell apron on every side, so every tap of every listed
+// footprint lands in it without a bounds test; the apron is discarded (the
+// neighbouring tiles grid those cells themselves).  No atomics; the summation
+// order is fixed by the list.
+// Entries come in batches of 64: lane i stages the 8 + 8 kernel values, the
+// value and the accumulator offset of entry i; a ballot marks where runs
+// start; the walk over the batch is unrolled, so every LDS address in it is an
+// immediate offset.
+constexpr int GR_APRON = 7;
 constexpr int GW = 17;      // staged kernel values per entry (8 + 8, odd stride: bank-free staging)
 
-// Accumulator slot of this lane's tap for the footprint whose first tap is
-// key = (cy, cx) (tile-relative), or -1 when the tap falls outside the tile
-// core; lane_off = jy * TS + jx.  Interior footprints (the usual case) need no
-// per-lane bounds test.
-__device__ __forceinline__ int grid_slot(int key, int TS, int TT, int jx, int jy, int lane_off) {
-    const int cx = (int)(short)(key & 0xFFFF), cy = key >> 16;
-    const bool inside = cx >= 0 && cx <= TT - 8 && cy >= 0 && cy <= TT - 8;
-    return (inside || (cx + jx >= 0 && cx + jx < TT && cy + jy >= 0 && cy + jy < TT)) ? cy * TS + cx + lane_off : -1;
-}
+// Accumulator row stride for a T-cell tile with its aprons: at least T + 14
+// cells, = 8 (mod 16) so that the two footprint rows a 16-lane group touches
+// fall in disjoint banks.
+__host__ __device__ constexpr int grid_stride(int TT) { return ((TT + 2 * GR_APRON - 8 + 15) / 16) * 16 + 8; }
 
-// Add a run's sum into its accumulator cell (a plain read-modify-write: the
-// 64 taps of a footprint are 64 distinct cells; LDS float atomics measured
-// several times slower).
 template <typename T>
 __device__ __forceinline__ void grid_flush(cplx<T>* acc, int slot, const cplx<T>& r) {
-    if (slot >= 0) {
-        cplx<T> a = acc[slot];
-        a.re += r.re;
-        a.im += r.im;
-        acc[slot] = a;
-    }
+    cplx<T> a = acc[slot];
+    a.re += r.re;
+    a.im += r.im;
+    acc[slot] = a;
 }
 
 template <typename T>
@@ -699,9 +693,9 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x,
     KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
-    const int TS = TT + GR_PAD;
-    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TT][TS]
-    cplx<T>* vv = acc + TT * TS;                                   // [64]
+    const int TS = grid_stride(TT), TA = TT + 2 * GR_APRON;
+    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TA][TS]: rows/cols -7 .. T+6
+    cplx<T>* vv = acc + TA * TS;                                   // [64]
     T* wts = reinterpret_cast<T*>(vv + 64);                        // [64][GW]
     const GridUnit u = units[blockIdx.x];
     const int lane = threadIdx.x, jx = lane & 7, jy = lane >> 3, lane_off = jy * TS + jx;
@@ -712,11 +706,11 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     int posn = 64 + lane < n ? gl[64 + lane] : -1;
     GridFetch<T> nxt;
     grid_fetch<T>(nxt, pos0, cell, frac, vals, weight);
-    for (int e = lane; e < TT * TS; e += 64) acc[e] = {T(0), T(0)};
+    for (int e = lane; e < TA * TS; e += 64) acc[e] = {T(0), T(0)};
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    // no run is open before the first entry: a key far outside the tile
-    constexpr int NOKEY = (0x4000 << 16) | 0x4000;
-    int prev = NOKEY, slot = -1;                 // slot: this lane's cell of the open run (-1: none)
+    // key of an entry: accumulator offset of its first tap (a bijection with the
+    // first-tap cell); before the first entry the open "run" adds zeros at 0
+    int prev = -1, slot = lane_off;
     cplx<T> racc{T(0), T(0)};
     for (int base = 0; base < n; base += 64) {
         const int e = base + lane;
@@ -725,7 +719,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             grid_fetch<T>(nxt, posn, cell, frac, vals, weight);
             posn = base + 128 + lane < n ? gl[base + 128 + lane] : -1;
         }
-        int key = NOKEY;
+        int key = -1;
         T* wv = wts + lane * GW;
         if (e < n) {
             int relx = (g.cc & 0xFFFF) - ox, rely = (g.cc >> 16) - oy;
@@ -733,7 +727,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             if (relx >= 2 * TT) relx -= Kx;
             if (rely < -TT) rely += Ky;
             if (rely >= 2 * TT) rely -= Ky;
-            key = ((rely - 3) << 16) | ((relx - 3) & 0xFFFF);
+            key = (rely - 3 + GR_APRON) * TS + (relx - 3 + GR_APRON);
             T w8[KB_J];
             kb_weights(g.f.re, kb, w8);
 #pragma unroll
@@ -768,7 +762,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             if ((starts >> v) & 1ull) {
                 grid_flush<T>(acc, slot, racc);
                 racc = {T(0), T(0)};
-                slot = grid_slot(__builtin_amdgcn_readlane(key, v), TS, TT, jx, jy, lane_off);
+                slot = __builtin_amdgcn_readlane(key, v) + lane_off;
             }
             const T w = wx * wy;
             racc.re += w * val.re;
@@ -782,13 +776,13 @@ __global__ __launch_bounds__(64) void k_grid_pull(
         cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
         for (int e = lane; e < TT * TT; e += 64) {
             const int ry = e / TT, rx = e - ry * TT;
-            g[(size_t)(oy + ry) * Kx + ox + rx] = acc[ry * TS + rx];
+            g[(size_t)(oy + ry) * Kx + ox + rx] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
         }
     } else {
         cplx<T>* p = partial + (size_t)(u.partial + u.split) * TT * TT;
         for (int e = lane; e < TT * TT; e += 64) {
             const int ry = e / TT, rx = e - ry * TT;
-            p[e] = acc[ry * TS + rx];
+            p[e] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
         }
     }
 }
@@ -963,7 +957,8 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
 
 template <typename T>
 void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    const size_t lds = (size_t)c->T * (c->T + GR_PAD) * sizeof(cplx<T>) + 64 * sizeof(cplx<T>) + 64 * GW * sizeof(T);
+    const size_t lds = (size_t)(c->T + 2 * GR_APRON) * grid_stride(c->T) * sizeof(cplx<T>) + 64 * sizeof(cplx<T>) +
+                       64 * GW * sizeof(T);
     k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
         c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
         (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
