@@ -33,6 +33,13 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-channels", type=int, default=3, help="channels of the oracle's CPU sample")
     p.add_argument("--phase-iters", type=int, default=5)
+    p.add_argument("--phases-only", action="store_true",
+                   help="only the eager per-phase timing (for rocprofv3 kernel traces and counters)")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run a 1 GiB device-to-device copy: the counter reference of known size")
+    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="offline: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into "
+                        "profiles/traffic.json and exit")
     return p.parse_args()
 
 
@@ -79,6 +86,52 @@ def source_hash(*names) -> str:
     return h.hexdigest()[:16]
 
 
+# kernel that dominates each phase (the one the counters are read for)
+PHASE_KERNEL = {"grid": "k_grid_pull", "degrid": "k_degrid_dual", "fft_fwd": "k_fft_cols_fwd",
+                "fft_adj": "k_fft_cols_adj", "psi": "k_idwt_level", "psi_adj": "k_dwt_level", "eig": "k_eig",
+                "l21": "k_l21", "primal": "k_primal", "gram": "k_gram", "backproject": "k_backproject"}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+CALIB_BYTES = 1 << 30
+
+
+def _counter_means(path: str, counter: str):
+    """Mean counter value (KiB) per dispatch, by kernel (short name), from a rocprofv3 counter CSV."""
+    import csv
+    sums, counts = {}, {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].replace("void ", "").split("(")[0].split("<")[0].split("::")[-1]
+            sums[name] = sums.get(name, 0.0) + float(r["Counter_Value"])
+            counts[name] = counts.get(name, 0) + 1
+    return {k: sums[k] / counts[k] for k in sums}, counts
+
+
+def write_traffic(fetch_csv: str, write_csv: str):
+    """profiles/traffic.json: HBM bytes per launch of each phase's kernel, each counter
+    scaled by what it reads for a device-to-device copy of CALIB_BYTES (read once, write once)."""
+    fm, fc = _counter_means(fetch_csv, "FETCH_SIZE")
+    wm, wc = _counter_means(write_csv, "WRITE_SIZE")
+    if COPY_KERNEL not in fm or COPY_KERNEL not in wm:
+        raise SystemExit("the counter runs must include the copy reference (bench.py --calib-copy)")
+    # the copy may be split over several dispatches: the reference is the total over one copy
+    f_scale = CALIB_BYTES / (fm[COPY_KERNEL] * 1024 * fc[COPY_KERNEL] / 3)
+    w_scale = CALIB_BYTES / (wm[COPY_KERNEL] * 1024 * wc[COPY_KERNEL] / 3)
+    out = {"_reference": {"kernel": COPY_KERNEL, "bytes": CALIB_BYTES, "fetch_scale": f_scale, "write_scale": w_scale,
+                          "note": "counter KiB per dispatch x 1024 x scale = HBM bytes per dispatch"}}
+    for phase, kern in PHASE_KERNEL.items():
+        if kern in fm and kern in wm:
+            fb, wb = fm[kern] * 1024 * f_scale, wm[kern] * 1024 * w_scale
+            out[phase] = {"kernel": kern, "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                          "bytes_per_launch": round(fb + wb), "dispatches_per_phase": fc[kern] / max(1, fc.get("k_primal", 1)),
+                          "src_hash": source_hash(PHASE_SRC[phase])}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path)
+
+
 def traffic_from_profiles(kernel_phase: str, src_file: str):
     """Measured HBM bytes per iteration for a phase from committed rocprofv3
     counter summaries (profiles/traffic.json); None if absent or stale."""
@@ -89,7 +142,7 @@ def traffic_from_profiles(kernel_phase: str, src_file: str):
         ent = t.get(kernel_phase)
         if not ent or ent.get("src_hash") != source_hash(src_file):
             return None
-        return ent["bytes_per_iteration"]
+        return ent["bytes_per_launch"]
     except Exception:
         return None
 
@@ -134,8 +187,23 @@ def cpu_baseline(cfg, inputs, n_ch: int):
                       f"{dt:.2f} s, scaled by L/{n_ch} = {scale:.0f} to the full cube"}
 
 
+def calib_copy():
+    """Three device-to-device copies of CALIB_BYTES (the counter reference)."""
+    import torch
+    src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
                                    "(see DESIGN.md for how the path would shard)"}))
@@ -158,6 +226,14 @@ def main():
     prob.pd_init(mu=mu, tau=tau, kappa3=kappa3)
     setup_s = time.perf_counter() - t_setup
     stream = prob.stream
+    if args.phases_only:
+        prob.profile_phases(1)
+        phases = prob.profile_phases(args.phase_iters)
+        torch.cuda.synchronize()
+        if args.calib_copy:
+            calib_copy()
+        print(json.dumps({"phases_ms": {k: round(v, 4) for k, v in phases.items()}, "workload": cfg.name}), flush=True)
+        return
 
     # warm-up (the first call captures one iteration into a HIP graph)
     prob.iterate(args.warmup)
@@ -205,7 +281,7 @@ def main():
     dom = max(phases, key=lambda k: phases[k])
     ach = ab[dom] / (phases[dom] * 1e-3) / 1e9 if ab[dom] > 0 else 0.0
     traffic = traffic_from_profiles(dom, PHASE_SRC[dom])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+    roofline = {"bound": "hbm", "kernel": f"{PHASE_KERNEL.get(dom, dom)} ({dom} phase)", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(ab[dom]), "avg_ms": round(phases[dom], 4)}
     iter_bytes = sum(ab.values())
@@ -235,6 +311,8 @@ def main():
         fp64 = {"iters_per_s": round(v64, 3), "fp32_speedup": round(value / v64, 3),
                 "one_iter_rel_err_fp32_vs_fp64": rel}
         del p64
+    if args.calib_copy:
+        calib_copy()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, inputs, args.cpu_channels)
