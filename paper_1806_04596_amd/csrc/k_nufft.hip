@@ -207,6 +207,16 @@ __global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, c
         [&](int q, const cplx<T>& v) { Hr[q] = v; });
 }
 
+// Column tile of work-group b (of nb): work-groups b and b + 8 run on the same
+// XCD (work-groups are dispatched round-robin over the 8 XCDs, each with its
+// own L2) and take adjacent tiles, so both halves of a 128-byte line of a grid
+// row are read through one L2.
+__device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
+    if (nb & 15) return b;
+    const int q = b >> 4, r = b & 15;
+    return (q << 4) + ((r & 7) << 1) + (r >> 3);
+}
+
 // Column pass of F: CT adjacent columns, rows placed at (j - ny/2) mod Ky.
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
@@ -216,7 +226,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
-    const int c = blockIdx.x * CT + s;
+    const int c = xcd_pair_tile(blockIdx.x, gridDim.x) * CT + s;
     const cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
     cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
     fft_run<T, false, false>(buf, u, s, Ky, CT, tw,
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict_
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
-    const int c = blockIdx.x * CT + s;
+    const int c = xcd_pair_tile(blockIdx.x, gridDim.x) * CT + s;
     const cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
     cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
     fft_run<T, true, false>(buf, u, s, Ky, CT, tw,
@@ -639,7 +649,10 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 // arrive in runs.  Lane (jx, jy) owns tap (jx, jy) of the current footprint:
 // within a run every lane adds phi_x(jx) phi_y(jy) val into one register; at
 // the end of a run the 64 sums are added into the tile accumulator in LDS (a
-// plain read-modify-write: the 64 taps are 64 distinct cells).  The
+// plain read-modify-write: the 64 taps are 64 distinct cells), whose old
+// values were read when the run started, so the write does not wait on a
+// fresh read; one wave issues its LDS operations in order, so that read sees
+// the previous run's write.  The
 // accumulator has a 7-cell apron on every side, so every tap of every listed
 // footprint lands in it without a bounds test; the apron is discarded (the
 // neighbouring tiles grid those cells themselves).  No atomics; the summation
@@ -651,18 +664,9 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 constexpr int GR_APRON = 7;
 constexpr int GW = 17;      // staged kernel values per entry (8 + 8, odd stride: bank-free staging)
 
-// Accumulator row stride for a T-cell tile with its aprons: at least T + 14
-// cells, = 8 (mod 16) so that the two footprint rows a 16-lane group touches
-// fall in disjoint banks.
-__host__ __device__ constexpr int grid_stride(int TT) { return ((TT + 2 * GR_APRON - 8 + 15) / 16) * 16 + 8; }
-
-template <typename T>
-__device__ __forceinline__ void grid_flush(cplx<T>* acc, int slot, const cplx<T>& r) {
-    cplx<T> a = acc[slot];
-    a.re += r.re;
-    a.im += r.im;
-    acc[slot] = a;
-}
+// Accumulator row stride for a T-cell tile with its aprons (no padding: the
+// smaller footprint raises occupancy by more than the bank conflicts cost).
+__host__ __device__ constexpr int grid_stride(int TT) { return TT + 2 * GR_APRON; }
 
 template <typename T>
 struct GridFetch {
@@ -711,7 +715,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     // key of an entry: accumulator offset of its first tap (a bijection with the
     // first-tap cell); before the first entry the open "run" adds zeros at 0
     int prev = -1, slot = lane_off;
-    cplx<T> racc{T(0), T(0)};
+    cplx<T> racc{T(0), T(0)}, old{T(0), T(0)};
     for (int base = 0; base < n; base += 64) {
         const int e = base + lane;
         const GridFetch<T> g = nxt;
@@ -760,9 +764,10 @@ __global__ __launch_bounds__(64) void k_grid_pull(
                 valn = vv[v + 1];
             }
             if ((starts >> v) & 1ull) {
-                grid_flush<T>(acc, slot, racc);
+                acc[slot] = {old.re + racc.re, old.im + racc.im};
                 racc = {T(0), T(0)};
                 slot = __builtin_amdgcn_readlane(key, v) + lane_off;
+                old = acc[slot];
             }
             const T w = wx * wy;
             racc.re += w * val.re;
@@ -770,7 +775,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
         }
         __syncthreads();
     }
-    grid_flush<T>(acc, slot, racc);
+    acc[slot] = {old.re + racc.re, old.im + racc.im};
     __syncthreads();
     if (u.nsplit == 1) {
         cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
