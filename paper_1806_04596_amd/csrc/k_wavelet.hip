@@ -227,20 +227,52 @@ __global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, con
     T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
     const int b_first = final_level ? 0 : (int)blockIdx.z;
     const int b_last = final_level ? n_db : (int)blockIdx.z + 1;
-    for (int b = b_first; b < b_last; ++b) {
-        const T* Cb = C + ((size_t)b * L + l) * N;
-        const T* LLb = coarsest ? nullptr : llin + ((size_t)b * L + l) * (size_t)hy * hx;
-        for (int e = tid; e < 4 * W * W; e += 256) {
+    // This thread's window elements: the same offsets in every basis, computed once.
+    // Element i comes from the coarser approximation (llin) when it is in subband 0
+    // below the coarsest level, else from the coefficient image.
+    constexpr int NE = (4 * W * W + 255) / 256;
+    int off[NE];
+    unsigned from_ll = 0u, live = 0u;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = tid + 256 * i;
+        off[i] = 0;
+        if (e < 4 * W * W) {
             const int sb = e / (W * W), rem = e - sb * (W * W);
             const int r = rem / W, cc = rem - r * W;
             const int sy = sb >> 1, sx = sb & 1;
             const int ky = wrap_idx(kylo + r, hy), kx = wrap_idx(kxlo + cc, hx);
-            T v;
-            if (sb == 0 && !coarsest) v = LLb[(size_t)ky * hx + kx];
-            else v = Cb[(size_t)(sy * hy + ky) * nx + sx * hx + kx];
-            S[sb][r][cc] = v;
+            live |= 1u << i;
+            if (sb == 0 && !coarsest) {
+                from_ll |= 1u << i;
+                off[i] = ky * hx + kx;
+            } else {
+                off[i] = (sy * hy + ky) * nx + sx * hx + kx;
+            }
+        }
+    }
+    // the window of the next basis is loaded into registers while this one is filtered
+    T nxt[NE];
+    auto fetch = [&](int b) {
+        const T* Cb = C + ((size_t)b * L + l) * N;
+        const T* LLb = coarsest ? Cb : llin + ((size_t)b * L + l) * (size_t)hy * hx;
+#pragma unroll
+        for (int i = 0; i < NE; ++i)
+            if ((live >> i) & 1u) nxt[i] = ((from_ll >> i) & 1u) ? LLb[off[i]] : Cb[off[i]];
+    };
+    fetch(b_first);
+    for (int b = b_first; b < b_last; ++b) {
+        T* Sf = &S[0][0][0];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int e = tid + 256 * i;
+            if ((live >> i) & 1u) {
+                const int sb = e / (W * W), rem = e - sb * (W * W);
+                Sf[(sb * W + rem / W) * (W + 1) + rem % W] = nxt[i];
+            }
         }
         __syncthreads();
+        if (b + 1 < b_last) fetch(b + 1);
         const T* f = filt + b * 32;
         WV_DISPATCH(b, idwt_y, f, S, Tm)
         __syncthreads();
