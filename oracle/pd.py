@@ -66,6 +66,10 @@ class Params:
     lam2: float = 0.01
     lam3: float = 0.618
     vartheta_bar: int = 100
+    # prior of the minimisation task: "lrjas" (low rankness + joint average sparsity,
+    # eq:min; with reweighting this is HyperSARA), "lr" (nuclear norm only, eq:min-lr),
+    # "jas" (l2,1 only, eq:min-js) or "sara" (weighted l1 per channel, eq:min-sara)
+    prior: str = "lrjas"
 
 
 @dataclass
@@ -131,11 +135,20 @@ def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_par
     Xt = st.Xt
     t = st.t + 1
 
+    use_nuc = prm.prior in ("lrjas", "lr")
+    use_sp = prm.prior in ("lrjas", "jas", "sara")
     # Step 5: low rankness dual
-    P = prox.dual_nuclear(st.P, Xt, w, method="svd")
-    # Steps 6-8: joint average sparsity duals and their synthesis
-    A = prox.dual_l21(st.A, wavelets.psi_adj(Xt, prob.levels, prob.n_db), wbar, prm.mu, float(prob.D))
-    At_sum = wavelets.psi(A, prob.levels)
+    P = prox.dual_nuclear(st.P, Xt, w, method="svd") if use_nuc else st.P
+    # Steps 6-8: joint average sparsity duals (or per-channel l1 for SARA) and their synthesis
+    if use_sp:
+        PsiXt = wavelets.psi_adj(Xt, prob.levels, prob.n_db)
+        if prm.prior == "sara":
+            A = prox.dual_l1(st.A, PsiXt, wbar, prm.mu, float(prob.D))
+        else:
+            A = prox.dual_l21(st.A, PsiXt, wbar, prm.mu, float(prob.D))
+        At_sum = wavelets.psi(A, prob.levels)
+    else:
+        A, At_sum = st.A, np.zeros_like(Xt)
     # Steps 3-4 and 9-12: data fidelity duals, per (l, b)
     v_new, lams, rho = [], [], []
     eps_new = [e.copy() for e in st.eps] if st.eps is not None else [np.array(e) for e in prob.eps]
@@ -163,7 +176,7 @@ def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_par
         rho.append(np.array(rho_l))
         data_adj[l] = nufft.phi_adj(vl, prob.uv[l], prob.theta[l], prob.ny, prob.nx)   # Steps 12, 20
     # Steps 20-23: primal update
-    G = k1 * P + k2 * At_sum + k3 * data_adj
+    G = (k1 * P if use_nuc else 0.0) + k2 * At_sum + k3 * data_adj
     X = prox.proj_pos(st.X - prm.tau * G)
     Xt_new = 2.0 * X - st.X
     nx_ = np.linalg.norm(X)
@@ -225,6 +238,8 @@ def reweight(X: np.ndarray, prob: Problem, gamma: float, gamma_bar: float):
 def solve(prob: Problem, prm: Params, kappa: tuple, n_reweights: int, iters_per: int,
           factor: float = 0.8, st: State | None = None):
     """Algorithm 1: reweighted sequence of Algorithm 2 solves with warm starts."""
+    if prm.prior == "sara" and n_reweights > 0:
+        raise ValueError("reweighting the SARA variant needs per-channel l1 weights, which are not modelled")
     st = zero_state(prob) if st is None else st
     gamma = gamma_bar = 1.0
     prm = Params(**{**prm.__dict__})

@@ -49,6 +49,20 @@ def dual_l21(A: np.ndarray, PsiXt: np.ndarray, wbar: np.ndarray, mu: float, psi_
     return Z - prox_l21(Z, mu * wbar * psi_norm2, axis=1)
 
 
+def soft_threshold(Z: np.ndarray, t) -> np.ndarray:
+    """Proximity operator of t * |.| (elementwise l1, the single-channel SARA prior)."""
+    return np.sign(Z) * np.maximum(np.abs(Z) - t, 0.0)
+
+
+def dual_l1(A: np.ndarray, PsiXt: np.ndarray, wbar: np.ndarray, mu: float, psi_norm2: float) -> np.ndarray:
+    """Step 7 for the SARA variant: the weighted l1 norm of each channel's
+    coefficients in place of the l2,1 norm (Sec. 4.2).  A, PsiXt: [D][L][ny][nx];
+    wbar: [D][ny][nx] (shared by the channels).  Returns Z - soft(Z) with
+    Z = A + PsiXt and threshold mu * wbar * psi_norm2, element by element."""
+    Z = A + PsiXt
+    return Z - soft_threshold(Z, mu * wbar[:, None] * psi_norm2)
+
+
 def _as_matrix(X: np.ndarray) -> np.ndarray:
     """Cube [L][ny][nx] -> N x L matrix (column l = channel l), as in Sec. 2.1."""
     L = X.shape[0]

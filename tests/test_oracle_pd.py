@@ -175,3 +175,33 @@ def test_workload_measurements_and_bounds():
         y0 = nufft.phi(inp["X0"][l], prob.uv[l], np.ones(m))
         wn = prob.theta[l] * (y_raw[l] - y0)
         assert np.linalg.norm(wn) ** 2 == pytest.approx(m, rel=0.2)
+
+
+def _variant_state(prob, seed):
+    rng = np.random.default_rng(seed)
+    L, ny, nx = prob.L, prob.ny, prob.nx
+    X = np.abs(rng.standard_normal((L, ny, nx)))
+    return pd.State(X=X, Xt=X + 0.1 * rng.standard_normal(X.shape), P=0.1 * rng.standard_normal(X.shape),
+                    A=0.1 * rng.standard_normal((prob.D, L, ny, nx)),
+                    v=[0.1 * (rng.standard_normal(len(u)) + 1j * rng.standard_normal(len(u))) for u in prob.uv])
+
+
+def test_prior_variants_reduce_to_special_cases():
+    """LR = LRJAS with mu = 0 and JAS = LRJAS with zero nuclear weights (eq:min-lr,
+    eq:min-js, Sec. 4.2), for the primal update; SARA = JAS for a single channel."""
+    prob, _ = _tiny_problem(2)
+    st = _variant_state(prob, 5)
+    k = (1.0, 1.0 / 9.0, 1e-3)
+    lr = pd.pd_iteration(st, prob, pd.Params(mu=0.3, prior="lr"), k)
+    ref = pd.pd_iteration(st, prob, pd.Params(mu=0.0, prior="lrjas"), k)
+    assert np.allclose(lr.X, ref.X, rtol=0, atol=1e-14) and np.array_equal(lr.A, st.A)
+    jas = pd.pd_iteration(st, prob, pd.Params(mu=0.3, prior="jas"), k)
+    ref = pd.pd_iteration(st, prob, pd.Params(mu=0.3, w=np.zeros(prob.L), prior="lrjas"), k)
+    assert np.allclose(jas.X, ref.X, rtol=0, atol=1e-14) and np.array_equal(jas.P, st.P)
+    prob1, _ = _tiny_problem(1, L=1)
+    st1 = _variant_state(prob1, 6)
+    sara = pd.pd_iteration(st1, prob1, pd.Params(mu=0.3, prior="sara"), k)
+    jas1 = pd.pd_iteration(st1, prob1, pd.Params(mu=0.3, prior="jas"), k)
+    assert np.allclose(sara.X, jas1.X, rtol=0, atol=1e-14) and np.allclose(sara.A, jas1.A, rtol=0, atol=1e-14)
+    with pytest.raises(ValueError):
+        pd.solve(prob, pd.Params(mu=0.3, prior="sara"), k, 1, 1)

@@ -179,3 +179,18 @@ def test_dual_data_block_is_moreau_of_projection():
 def test_positivity_projection():
     x = np.array([-1.0, 0.0, 2.0]) + 1j * np.array([5.0, -1.0, 3.0])
     assert np.array_equal(prox.proj_pos(x), [0.0, 0.0, 2.0])
+
+
+def test_l1_dual_is_projection_onto_linf_ball():
+    # Moreau: Z - soft_t(Z) is the projection of Z onto the l_inf ball of radius t
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((3, 2, 8, 8))
+    S = rng.standard_normal((3, 2, 8, 8))
+    wbar = rng.uniform(0.1, 1.0, (3, 8, 8))
+    mu, D = 0.2, 3.0
+    out = prox.dual_l1(A, S, wbar, mu, D)
+    t = mu * wbar[:, None] * D
+    assert np.allclose(out, np.clip(A + S, -t, t), rtol=0, atol=1e-15)
+    # and soft thresholding by hand on one element
+    z, tt = 1.7, 0.5
+    assert prox.soft_threshold(np.array([z, -z, 0.2]), tt).tolist() == [1.2, -1.2, 0.0]
