@@ -96,7 +96,17 @@ typedef struct {
  * w: host double [L] nuclear weights paired with singular values in
  *    decreasing order (NULL = ones), copied.
  * adaptive_eps: nonzero enables Steps 13-19 with lam1..lam3, vartheta_bar
- *    (Appendix A: 5e-4, 0.01, 0.618, 100). */
+ *    (Appendix A: 5e-4, 0.01, 0.618, 100).
+ * prior: the regularisation of the minimisation task (Sec. 2.3, Sec. 4.2):
+ *    HS_PRIOR_LRJAS  low rankness + joint average sparsity (eq:min; reweighted by
+ *                    hs_solve this is HyperSARA),
+ *    HS_PRIOR_LR     nuclear norm only (eq:min-lr),
+ *    HS_PRIOR_JAS    l2,1 norm only (eq:min-js),
+ *    HS_PRIOR_SARA   weighted l1 norm of each channel's coefficients, no
+ *                    nuclear norm (eq:min-sara; weights wbar shared by the
+ *                    channels, so hs_solve does not reweight it).
+ *    A prior that is off leaves its dual (P or A) untouched. */
+enum { HS_PRIOR_LRJAS = 0, HS_PRIOR_LR = 1, HS_PRIOR_JAS = 2, HS_PRIOR_SARA = 3 };
 typedef struct {
     double mu, tau, kappa1, kappa2, kappa3;
     const void* wbar;
@@ -104,6 +114,7 @@ typedef struct {
     int32_t adaptive_eps;
     double lam1, lam2, lam3;
     int32_t vartheta_bar;
+    int32_t prior;
 } hs_pd_params;
 
 /* Device pointers to a primal-dual state, ctx dtype.  X, Xt, P: [L][ny][nx];
@@ -250,6 +261,15 @@ hs_status hs_proj_ellipsoid(hs_ctx* ctx, int32_t l, int32_t b, void* z);
  * *iters receives the iterations used (may be NULL).  Synchronising. */
 hs_status hs_op_norm(hs_ctx* ctx, int32_t which, int32_t max_it, double tol, const void* x0,
                      double* out, double* per_channel, int32_t* iters);
+
+/* Dirty cube and the trade-off estimate of Sec. 2.3 (normalisation of Sec. 4.3):
+ *   PSF_l = Re Phi_l^dagger Phi_l delta, delta a unit source at the phase centre;
+ *   X_dirty[l] = Re Phi_l^dagger y_l / max_p PSF_l(p)  (y = theta * y_raw of hs_set_data);
+ *   mu_hat = ||X_dirty||_* / ||Psi^dagger X_dirty||_{2,1}.
+ * Xd: device real [L][ny][nx] receiving X_dirty (may be NULL); mu: host double
+ * (may be NULL; one of the two is required).  FP64 reductions; synchronising
+ * when mu is requested. */
+hs_status hs_dirty_mu(hs_ctx* ctx, void* Xd, double* mu);
 
 /* -------------------------------------------------------------- PD solver */
 /* Sets parameters of Algorithm 2 (does not reset the state). */

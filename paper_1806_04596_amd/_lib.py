@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhypersara.so")
 HS_OK = 0
 HS_F32, HS_F64 = 0, 1
 HS_NORM_PHI_PRECOND, HS_NORM_PSI = 0, 1
+PRIORS = {"lrjas": 0, "lr": 1, "jas": 2, "sara": 3}
 
 STATUS = {0: "HS_OK", -1: "HS_ERR_INVALID_ARG", -2: "HS_ERR_SHAPE", -3: "HS_ERR_DTYPE", -4: "HS_ERR_NOT_PLANNED",
           -5: "HS_ERR_NO_WORKSPACE", -6: "HS_ERR_NONFINITE", -7: "HS_ERR_HIP", -8: "HS_ERR_NOT_CONVERGED"}
@@ -36,7 +37,7 @@ class PDParams(C.Structure):
     _fields_ = [("mu", C.c_double), ("tau", C.c_double), ("kappa1", C.c_double), ("kappa2", C.c_double),
                 ("kappa3", C.c_double), ("wbar", C.c_void_p), ("w", C.POINTER(C.c_double)),
                 ("adaptive_eps", C.c_int32), ("lam1", C.c_double), ("lam2", C.c_double), ("lam3", C.c_double),
-                ("vartheta_bar", C.c_int32)]
+                ("vartheta_bar", C.c_int32), ("prior", C.c_int32)]
 
 
 class StatePtrs(C.Structure):
@@ -82,6 +83,7 @@ SIGNATURES = {
     "hs_dual_data": (C.c_int32, [ctxp, P, P, P]),
     "hs_proj_ellipsoid": (C.c_int32, [ctxp, C.c_int32, C.c_int32, P]),
     "hs_op_norm": (C.c_int32, [ctxp, C.c_int32, C.c_int32, C.c_double, P, dptr, dptr, C.POINTER(C.c_int32)]),
+    "hs_dirty_mu": (C.c_int32, [ctxp, P, dptr]),
     "hs_pd_init": (C.c_int32, [ctxp, C.POINTER(PDParams)]),
     "hs_pd_set_state": (C.c_int32, [ctxp, C.POINTER(StatePtrs)]),
     "hs_pd_get_state": (C.c_int32, [ctxp, C.POINTER(StatePtrs)]),

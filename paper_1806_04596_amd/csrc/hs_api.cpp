@@ -250,12 +250,16 @@ static void dual_nuclear_impl(hs_ctx* c, T* P, const T* Xt, const PhaseMarks& pm
     pm.mark(c, HS_PH_BACKPROJ + 1);
 }
 
+// Prior terms the iteration carries.
+static bool use_nuclear(const hs_ctx* c) { return c->prior == HS_PRIOR_LRJAS || c->prior == HS_PRIOR_LR; }
+static bool use_sparsity(const hs_ctx* c) { return c->prior != HS_PRIOR_LR; }
+
 template <typename T>
 static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu, T* At_sum,
                           const PhaseMarks& pm = PhaseMarks()) {
     launch_psi_adj<T>(c, Xt, nullptr);
     pm.mark(c, HS_PH_PSI_ADJ + 1);
-    launch_l21_dual<T>(c, A, Xt, (const T*)c->d.coef, wbar, mu * (double)c->D, 0);
+    launch_l21_dual<T>(c, A, Xt, (const T*)c->d.coef, wbar, mu * (double)c->D, c->prior == HS_PRIOR_SARA ? 2 : 0);
     pm.mark(c, HS_PH_L21 + 1);
     if (At_sum) launch_psi_sum<T>(c, A + (size_t)c->L * c->N, A, At_sum);
     pm.mark(c, HS_PH_PSI + 1);
@@ -269,20 +273,25 @@ static void pd_iter_forked(hs_ctx* c) {
     Dev& d = c->d;
     T* Xt = (T*)d.Xt;
     hipStream_t main = c->stream;
+    const bool nuc = use_nuclear(c), sp = use_sparsity(c);
     (void)hipEventRecord(c->ev_fork, main);
-    (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0);
-    (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0);
-    c->stream = c->side[0];
-    dual_nuclear_impl<T>(c, (T*)d.P, Xt);
-    (void)hipEventRecord(c->ev_join[0], c->side[0]);
-    c->stream = c->side[1];
-    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
-    (void)hipEventRecord(c->ev_join[1], c->side[1]);
+    if (nuc) {
+        (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0);
+        c->stream = c->side[0];
+        dual_nuclear_impl<T>(c, (T*)d.P, Xt);
+        (void)hipEventRecord(c->ev_join[0], c->side[0]);
+    }
+    if (sp) {
+        (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0);
+        c->stream = c->side[1];
+        dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
+        (void)hipEventRecord(c->ev_join[1], c->side[1]);
+    }
     c->stream = main;
     dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0);
-    (void)hipStreamWaitEvent(main, c->ev_join[0], 0);
-    (void)hipStreamWaitEvent(main, c->ev_join[1], 0);
-    launch_primal<T>(c, (const T*)d.img1, (const T*)d.img0);
+    if (nuc) (void)hipStreamWaitEvent(main, c->ev_join[0], 0);
+    if (sp) (void)hipStreamWaitEvent(main, c->ev_join[1], 0);
+    launch_primal<T>(c, sp ? (const T*)d.img1 : nullptr, (const T*)d.img0, nuc);
 }
 
 // One iteration of Algorithm 2 on the context state.
@@ -293,12 +302,15 @@ static void pd_iter_impl(hs_ctx* c, const PhaseMarks& pm = PhaseMarks()) {
     pm.mark(c, 0);
     // data fidelity (Steps 3-4, 9-12) -> img0 = Re Phi^dag v
     dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0, pm);
-    // low rankness (Step 5)
-    dual_nuclear_impl<T>(c, (T*)d.P, Xt, pm);
+    // low rankness (Step 5); a prior that is off still records its phase marks
+    const bool nuc = use_nuclear(c), sp = use_sparsity(c);
+    if (nuc) dual_nuclear_impl<T>(c, (T*)d.P, Xt, pm);
+    else for (int k = HS_PH_GRAM; k <= HS_PH_BACKPROJ; ++k) pm.mark(c, k + 1);
     // joint average sparsity (Steps 6-8) -> img1 = sum_d Psi_d A_d
-    dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1, pm);
+    if (sp) dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1, pm);
+    else for (int k = HS_PH_PSI_ADJ; k <= HS_PH_PSI; ++k) pm.mark(c, k + 1);
     // primal (Steps 20-23)
-    launch_primal<T>(c, (const T*)d.img1, (const T*)d.img0);
+    launch_primal<T>(c, sp ? (const T*)d.img1 : nullptr, (const T*)d.img0, nuc);
     pm.mark(c, HS_PH_PRIMAL + 1);
 }
 
@@ -336,6 +348,45 @@ static hs_status op_norm_impl(hs_ctx* c, int max_it, double tol, const T* x0, do
     *out = mx;
     if (per) std::copy(lam.begin(), lam.end(), per);
     if (iters) *iters = it;
+    return HS_OK;
+}
+
+// Dirty cube and trade-off estimate (Sec. 2.3, normalisation of Sec. 4.3):
+// PSF_l = Re Phi_l^dag Phi_l delta (delta at the phase centre), X_l = Re Phi_l^dag y_l / max PSF_l,
+// mu = ||X||_* / ||Psi^dag X||_{2,1}.
+template <typename T>
+static hs_status dirty_mu_impl(hs_ctx* c, T* Xd, double* mu) {
+    Dev& d = c->d;
+    const int64_t LN = (int64_t)c->L * c->N;
+    T* delta = (T*)d.img1;
+    T* psf = (T*)d.img0;
+    T* X = Xd ? Xd : (T*)d.img0;
+    launch_fill<T>(c->stream, delta, T(0), LN);
+    launch_set_center<T>(c, delta);
+    launch_fft_rows_fwd<T>(c, delta, c->L);
+    launch_fft_cols_fwd<T>(c, c->L);
+    launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)nullptr);
+    adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, psf);
+    launch_chan_max<T>(c, psf, d.chan_nrm);
+    adj_from_grid_order<T>(c, (const cplx<T>*)d.vis_y, (const T*)d.vis_theta, X);
+    launch_chan_scale<T>(c, X, d.chan_nrm);
+    if (!mu) return HS_OK;
+    // nuclear norm from the FP64 eigen-decomposition of the L x L Gram matrix
+    launch_gram<T>(c, X, (const T*)nullptr);
+    launch_eig(c, 0);
+    std::vector<double> sg(MAX_L);
+    hipMemcpyAsync(sg.data(), d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
+    launch_psi_adj<T>(c, X, nullptr);
+    const int np = launch_l21_norm<T>(c, X, (const T*)d.coef);
+    std::vector<double> part(np);
+    hipMemcpyAsync(part.data(), d.red_part, np * 8, hipMemcpyDeviceToHost, c->stream);
+    launch_eig_reset(c);   // the eigen-solver warm start belongs to the PD iteration
+    hs_status s = hip_check(c, hipStreamSynchronize(c->stream), "hs_dirty_mu");
+    if (s) return s;
+    double nuc = 0.0, l21 = 0.0;
+    for (int l = 0; l < c->L; ++l) nuc += sg[l];
+    for (int k = 0; k < np; ++k) l21 += part[k];
+    *mu = l21 > 0.0 ? nuc / l21 : 0.0;
     return HS_OK;
 }
 
@@ -719,6 +770,15 @@ hs_status hs_op_norm(hs_ctx* c, int32_t which, int32_t max_it, double tol, const
     return launched(c, "hs_op_norm");
 }
 
+hs_status hs_dirty_mu(hs_ctx* c, void* Xd, double* mu) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!Xd && !mu) return fail(c, HS_ERR_INVALID_ARG, "nothing requested");
+    HS_DISPATCH(c, s = dirty_mu_impl<T>(c, (T*)Xd, mu));
+    if (s) return s;
+    return launched(c, "hs_dirty_mu");
+}
+
 hs_status hs_pd_init(hs_ctx* c, const hs_pd_params* p) {
     hs_status s = ready(c);
     if (s) return s;
@@ -735,6 +795,8 @@ hs_status hs_pd_init(hs_ctx* c, const hs_pd_params* p) {
     c->lam2 = p->lam2 > 0 ? p->lam2 : 0.01;
     c->lam3 = p->lam3 > 0 ? p->lam3 : 0.618;
     c->vartheta_bar = p->vartheta_bar > 0 ? p->vartheta_bar : 100;
+    if (p->prior < HS_PRIOR_LRJAS || p->prior > HS_PRIOR_SARA) return fail(c, HS_ERR_INVALID_ARG, "unknown prior");
+    c->prior = p->prior;
     s = upload_w(c, p->w);
     if (s) return s;
     if (p->wbar) hipMemcpyAsync(c->d.wbar, p->wbar, (size_t)c->D * c->N * c->rsz, hipMemcpyDeviceToDevice, c->stream);
@@ -887,6 +949,8 @@ hs_status hs_solve(hs_ctx* c, const hs_solve_params* p, void* X_out, hs_report* 
     if (!p || p->iters_per_reweight < 1 || p->n_reweights < 0 || !(p->gamma_factor > 0))
         return fail(c, HS_ERR_INVALID_ARG, "bad solve parameters");
     if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
+    if (c->prior == HS_PRIOR_SARA && p->n_reweights > 0)
+        return fail(c, HS_ERR_INVALID_ARG, "reweighting the SARA prior needs per-channel weights (not modelled)");
     double gamma = 1.0, gamma_bar = 1.0, beta = 0.0;
     int64_t total = 0;
     const int check = p->check_every > 0 ? p->check_every : p->iters_per_reweight;

@@ -169,6 +169,7 @@ struct hs_ctx {
     bool adaptive = false;
     double lam1 = 5e-4, lam2 = 0.01, lam3 = 0.618;
     int vartheta_bar = 100;
+    int prior = HS_PRIOR_LRJAS;        // which prior terms the iteration carries
     int64_t t_iter = 0;
     std::vector<double> w_host;
     hipGraph_t graph = nullptr;
@@ -221,8 +222,11 @@ void launch_eig_reset(hs_ctx* c);
 template <typename T> void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2);
 
 // primal and helpers (k_misc.hip)
-template <typename T> void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg);
+template <typename T> void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg, bool use_p);
 template <typename T> void launch_chan_norms(hs_ctx* c, const T* X, double* out);
+template <typename T> void launch_chan_max(hs_ctx* c, const T* X, double* out);
+template <typename T> void launch_set_center(hs_ctx* c, T* X);
+template <typename T> int launch_l21_norm(hs_ctx* c, const T* X, const T* coef);
 template <typename T> void launch_chan_scale(hs_ctx* c, T* X, const double* nrm);
 template <typename T> void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);
 

@@ -30,7 +30,8 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
     return s;
 }
 
-// Steps 20-23: G = k1 P + k2 At + k3 D; X <- max(X - tau G, 0); Xt <- 2X_new - X_old;
+// Steps 20-23: G = k1 P + k2 At + k3 D (P or At null: that prior is off);
+// X <- max(X - tau G, 0); Xt <- 2X_new - X_old;
 // FP64 partial sums of ||X_new - X_old||^2 and ||X_new||^2 per block (fixed grid).
 template <typename T>
 __global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict__ Xt, const T* __restrict__ P,
@@ -39,7 +40,9 @@ __global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict
     __shared__ double sh[4];
     double dd = 0.0, xx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const T g = k1 * P[i] + k2 * At[i] + k3 * D[i];
+        T g = k3 * D[i];
+        if (P) g += k1 * P[i];
+        if (At) g += k2 * At[i];
         const T xo = X[i];
         T xn = xo - tau * g;
         xn = xn > T(0) ? xn : T(0);
@@ -111,6 +114,57 @@ __global__ void k_chan_scale(T* __restrict__ X, const double* __restrict__ nrm, 
     if (s > 0.0) X[(size_t)l * N + i] = (T)((double)X[(size_t)l * N + i] / s);
 }
 
+// Per-channel maximum of X: block partials, then out[l] = max over the partials.
+template <typename T>
+__global__ __launch_bounds__(256) void k_chan_max(const T* __restrict__ X, int64_t N, double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int l = blockIdx.y;
+    const T* x = X + (size_t)l * N;
+    double m = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, (double)x[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(size_t)l * gridDim.x + blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ void k_chan_max_finish(const double* __restrict__ part, double* __restrict__ out, int L, int nch) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    double m = -INFINITY;
+    for (int k = 0; k < nch; ++k) m = fmax(m, part[(size_t)l * nch + k]);
+    out[l] = m;
+}
+
+// X[l][center] = 1 for every channel (a unit source at the phase centre; X zeroed before).
+template <typename T>
+__global__ void k_set_center(T* __restrict__ X, int L, int64_t N, int64_t center) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < L) X[(size_t)l * N + center] = T(1);
+}
+
+// ||Psi^dag X||_{2,1} partials: basis d = blockIdx.y (0: Dirac = X itself, else coef[d-1]);
+// sum over pixels of the l2 norm over the L channels, FP64, fixed reduction order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_l21_norm(const T* __restrict__ X, const T* __restrict__ coef, int L,
+                                                  int64_t N, double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int d = blockIdx.y;
+    const T* S = (d == 0) ? X : coef + (size_t)(d - 1) * L * N;
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        double n2 = 0.0;
+        for (int l = 0; l < L; ++l) {
+            const double v = (double)S[(size_t)l * N + p];
+            n2 += v * v;
+        }
+        acc += sqrt(n2);
+    }
+    acc = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)d * gridDim.x + blockIdx.x] = acc;
+}
+
 // eq:weights-l21: wbar[d][p] = gb / (gb + ||(Psi^dag X)_{d,p}||) over the L channels.
 template <typename T>
 __global__ void k_reweight_l21(const T* __restrict__ X, const T* __restrict__ coef, T* __restrict__ wbar, double gb,
@@ -137,11 +191,12 @@ void launch_axpby(hipStream_t s, T* y, const T* x, T a, T b, int64_t n) {
 }
 
 template <typename T>
-void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg) {
+void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg, bool use_p) {
     const int64_t n = (int64_t)c->L * c->N;
     int grid = (int)std::min<int64_t>(NRED, (n + 255) / 256);
     if (grid < 1) grid = 1;
-    k_primal<T><<<grid, 256, 0, c->stream>>>((T*)c->d.X, (T*)c->d.Xt, (const T*)c->d.P, Atsum, Dimg, (T)c->k1,
+    k_primal<T><<<grid, 256, 0, c->stream>>>((T*)c->d.X, (T*)c->d.Xt, use_p ? (const T*)c->d.P : nullptr, Atsum,
+                                              Dimg, (T)c->k1,
                                               (T)c->k2, (T)c->k3, (T)c->tau, n, c->d.red_part);
     k_finish_beta<<<1, 64, 0, c->stream>>>(c->d.red_part, c->d.scal, grid);
 }
@@ -162,6 +217,29 @@ void launch_chan_scale(hs_ctx* c, T* X, const double* nrm) {
 }
 
 template <typename T>
+void launch_chan_max(hs_ctx* c, const T* X, double* out) {
+    const int nch = 64;
+    dim3 g(nch, c->L);
+    k_chan_max<T><<<g, 256, 0, c->stream>>>(X, c->N, c->d.red_part);
+    k_chan_max_finish<<<1, 64, 0, c->stream>>>(c->d.red_part, out, c->L, nch);
+}
+
+template <typename T>
+void launch_set_center(hs_ctx* c, T* X) {
+    k_set_center<T><<<1, 64, 0, c->stream>>>(X, c->L, c->N, (int64_t)(c->ny / 2) * c->nx + c->nx / 2);
+}
+
+// Partials of ||Psi^dag X||_{2,1} (X: Dirac basis, coef: the n_db wavelet bases) into
+// red_part[0 .. D * 64); returns the number of partials.
+template <typename T>
+int launch_l21_norm(hs_ctx* c, const T* X, const T* coef) {
+    const int nch = 64;
+    dim3 g(nch, c->D);
+    k_l21_norm<T><<<g, 256, 0, c->stream>>>(X, coef, c->L, c->N, c->d.red_part);
+    return nch * c->D;
+}
+
+template <typename T>
 void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb) {
     dim3 g(nb(c->N, 256), c->D);
     k_reweight_l21<T><<<g, 256, 0, c->stream>>>(X, coef, wbar, gb, c->L, c->N);
@@ -170,9 +248,12 @@ void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double g
 #define HS_INST(T)                                                                 \
     template void launch_fill<T>(hipStream_t, T*, T, int64_t);                     \
     template void launch_axpby<T>(hipStream_t, T*, const T*, T, T, int64_t);       \
-    template void launch_primal<T>(hs_ctx*, const T*, const T*);                   \
+    template void launch_primal<T>(hs_ctx*, const T*, const T*, bool);             \
     template void launch_chan_norms<T>(hs_ctx*, const T*, double*);                \
     template void launch_chan_scale<T>(hs_ctx*, T*, const double*);                \
+    template void launch_chan_max<T>(hs_ctx*, const T*, double*);                  \
+    template void launch_set_center<T>(hs_ctx*, T*);                               \
+    template int launch_l21_norm<T>(hs_ctx*, const T*, const T*);                  \
     template void launch_reweight_l21<T>(hs_ctx*, const T*, const T*, T*, double);
 HS_INST(float)
 HS_INST(double)

@@ -325,7 +325,9 @@ __global__ void k_psi_sum(const T* __restrict__ Y, const T* __restrict__ C0, T* 
 
 // l2,1 on rows of length L at fixed (d, pixel):
 //  mode 0 (dual, Step 7): Z = A + Psi_d^dag Xt, A <- Z min(1, thr*wbar/||Z||);
-//  mode 1 (prox, eq:prox-L21): Z = A, A <- Z max(||Z|| - thr*wbar, 0)/||Z||.
+//  mode 1 (prox, eq:prox-L21): Z = A, A <- Z max(||Z|| - thr*wbar, 0)/||Z||;
+//  mode 2 (dual of the per-channel weighted l1 of the SARA variant, eq:min-sara):
+//         Z = A + Psi_d^dag Xt, A <- clip(Z, -thr*wbar, thr*wbar) element by element.
 template <typename T>
 __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restrict__ Xt, const T* __restrict__ coef,
                       const T* __restrict__ wbar, double thr, int L, int64_t N, int mode) {
@@ -333,7 +335,16 @@ __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restr
     if (p >= N) return;
     const int d = blockIdx.y;
     T* Ad = A + (size_t)d * L * N + p;
-    const T* Sd = (mode == 0) ? ((d == 0) ? Xt + p : coef + (size_t)(d - 1) * L * N + p) : nullptr;
+    const T* Sd = (mode != 1) ? ((d == 0) ? Xt + p : coef + (size_t)(d - 1) * L * N + p) : nullptr;
+    if (mode == 2) {
+        // SARA variant: weighted l1 per channel, Z - soft(Z) = clip(Z, -t, t) element by element
+        const T t = (T)(thr * (wbar ? (double)wbar[(size_t)d * N + p] : 1.0));
+        for (int l = 0; l < L; ++l) {
+            const T v = Ad[(size_t)l * N] + Sd[(size_t)l * N];
+            Ad[(size_t)l * N] = v > t ? t : (v < -t ? -t : v);
+        }
+        return;
+    }
     T z[MAX_L];
     double n2 = 0.0;
 #pragma unroll

@@ -213,15 +213,22 @@ class Problem:
                                       C.byref(out), L.as_dptr(per), C.byref(it))
         return out.value, per, it.value
 
+    def dirty_mu(self, want_cube=True):
+        """(mu_hat, X_dirty or None): the dirty cube and mu_hat of Sec. 2.3."""
+        Xd = self.empty_cube() if want_cube else None
+        mu = C.c_double()
+        self._call("hs_dirty_mu", self.lib.hs_dirty_mu, self._p(Xd), C.byref(mu))
+        return mu.value, Xd
+
     # ----------------------------------------------------------------- PD
     def pd_init(self, mu, tau, kappa3, kappa1=1.0, kappa2=0.0, wbar=None, w=None, adaptive_eps=False,
-                lam1=5e-4, lam2=0.01, lam3=0.618, vartheta_bar=100):
+                lam1=5e-4, lam2=0.01, lam3=0.618, vartheta_bar=100, prior="lrjas"):
         self._wkeep = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
         prm = L.PDParams(mu=mu, tau=tau, kappa1=kappa1, kappa2=kappa2, kappa3=kappa3,
                          wbar=None if wbar is None else wbar.data_ptr(),
                          w=None if self._wkeep is None else L.as_dptr(self._wkeep),
                          adaptive_eps=1 if adaptive_eps else 0, lam1=lam1, lam2=lam2, lam3=lam3,
-                         vartheta_bar=vartheta_bar)
+                         vartheta_bar=vartheta_bar, prior=L.PRIORS[prior])
         self._call("hs_pd_init", self.lib.hs_pd_init, C.byref(prm))
 
     def _state(self, X=None, Xt=None, P=None, A=None, v=None):

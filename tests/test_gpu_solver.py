@@ -77,3 +77,36 @@ def test_adaptive_bounds_vs_oracle(dtype):
     _set(prob, st)
     _, _, eps_again = prob.stats()
     assert np.array_equal(eps_again, eps0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dirty_cube_and_mu_hat_vs_oracle(dtype):
+    """X_dirty = Re Phi^dag y normalised by the PSF peak and mu_hat = ||X_dirty||_* /
+    ||Psi^dag X_dirty||_{2,1} (Sec. 2.3)."""
+    cfg, inp, op, prob = _fresh("t2", dtype)
+    mu, Xd = prob.dirty_mu()
+    check_rel(host(Xd), pd.dirty_cube(op), TOL[dtype], "X_dirty")
+    ref = pd.mu_hat(op)
+    assert abs(mu - ref) <= TOL[dtype] * ref, (mu, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("prior", ["lr", "jas", "sara"])
+def test_prior_variants_one_iteration_vs_oracle(prior, dtype):
+    """LR, JAS and SARA (Sec. 4.2) through the graph-replayed iteration, three iterations."""
+    cfg, inp, op = oracle_case("t2")
+    from gpu_cases import gpu_case
+    prob, _, _ = gpu_case("t2", dtype)
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), prior=prior)
+    ost = _oracle_state(st, op)
+    for _ in range(3):
+        ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    _set(prob, st)
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0, prior=prior)
+    prob.iterate(3)
+    g = {k: host(v) for k, v in prob.get_state().items()}
+    tol = TOL[dtype] * (1 if dtype == "f64" else 10)
+    for k in ("X", "Xt", "P", "A"):
+        check_rel(g[k], getattr(ost, k), tol, k)
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0)   # back to the default prior
