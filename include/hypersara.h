@@ -200,7 +200,10 @@ hs_status hs_density_precond(int64_t M, const double* uv, int32_t nx, int32_t ny
 /* The library's visibility order for one channel: perm[k] = input index of the
  * k-th visibility in tile-major order, sorted by (tile, region, bin) with ties
  * in input order; region_ptr[t*9 + r] = first position of region r of tile t,
- * region_ptr has (2nx/tile)(2ny/tile)*9 + 1 entries.  precond may be NULL. */
+ * region_ptr has (nx/tile + 1)(2ny/tile)*9 + 1 entries.  Cells are those of the
+ * Hermitian half plane: a visibility with (u Kx) mod Kx > Kx/2 is binned at -t
+ * (the transform of a real image is conjugate-symmetric), so tiles cover
+ * kx in [0, Kx/2] only.  precond may be NULL. */
 hs_status hs_visibility_order(int64_t M, const double* uv, const double* precond, int32_t nblocks,
                               const int64_t* block_ptr, int32_t nx, int32_t ny, int32_t tile,
                               int64_t* perm, int64_t* region_ptr);

@@ -65,8 +65,8 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.bin_run_ptr, (size_t)(c->nbins + 1) * 4, base);
     k.take(d.bin_runs, (size_t)c->nruns * 4, base);
     k.take(d.bin_S, (size_t)c->nbins * 16, base);
-    k.take(d.grid, (size_t)c->L * c->Kx * c->Ky * cx, base);
-    k.take(d.H, (size_t)c->L * c->ny * c->Kx * cx, base);
+    k.take(d.grid, (size_t)c->L * c->Ky * c->Wg * cx, base);
+    k.take(d.H, (size_t)c->L * c->ny * c->Hs * cx, base);
     k.take(d.tw_x, (size_t)c->Kx * cx, base);
     k.take(d.tw_y, (size_t)c->Ky * cx, base);
     k.take(d.sx, (size_t)c->nx * r, base);

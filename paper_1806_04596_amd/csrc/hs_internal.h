@@ -62,7 +62,7 @@ struct alignas(2 * sizeof(T)) cplx {   // aligned to its size: one 64/128-bit ac
 // Device pointers carved from the caller's workspace.
 struct Dev {
     // per visibility, tile-major order
-    int32_t* vis_cell = nullptr;   // (cy << 16) | cx
+    int32_t* vis_cell = nullptr;   // (cy << 16) | (reflected << 15) | cx, half-plane cell
     void* vis_frac = nullptr;      // [M][2] real, t - floor(t)
     void* vis_y = nullptr;         // [M] complex, theta * y_raw
     void* vis_theta = nullptr;     // [M] real
@@ -146,7 +146,12 @@ struct hs_ctx {
     std::vector<hs::Channel> ch;
     // plan
     bool planned = false, bound = false;
-    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0;
+    // Hermitian half plane: visibilities live at kx in [0, Kx/2] (those at
+    // negative kx are reflected); visibility tiles cover [0, Kx/2 + T), gridding
+    // tiles [-T, Kx/2 + T) = the Wg columns of a grid row (column = kx + T).
+    int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0;   // visibility tiles
+    int gtiles_x = 0, ngtiles = 0;                      // gridding tiles
+    int Kh = 0, Wh = 0, Wg = 0, Hs = 0;                 // Kx/2, Kx/2 + 1, Kx/2 + 2T, Kx/2 + 16
     int64_t Mtot = 0;
     std::vector<int64_t> chan_off;     // [L+1]
     std::vector<int32_t> blk_off;      // [L+1]

@@ -193,35 +193,63 @@ struct ChanOrder {
     std::vector<int64_t> perm;        // position -> input index
     std::vector<int64_t> region_ptr;  // [ntiles*9 + 1]
     std::vector<int32_t> bin_local;   // per input index
-    std::vector<int32_t> cx, cy;      // per input index
+    std::vector<int32_t> cx, cy;      // per input index (half-plane cell)
+    std::vector<int32_t> refl;        // per input index: reflected to -t
     std::vector<double> fx, fy;       // per input index
     std::vector<double> class_val;    // distinct preconditioner values (ascending)
     int C = 1;
 };
 
+// Cell, fraction and reflection of one visibility in the Hermitian half plane:
+// t = (u Kx, v Ky) reduced mod K (exact: K is a power of two and u is
+// float32-representable); when t_x mod Kx > Kx/2 the visibility is reflected
+// to -t (phi is even, so its model value is the conjugate of the value at -t).
+// The taps of t are floor(t) - 3 .. floor(t) + 4; their mirror images are the
+// taps of cell -floor(t) - 1 = ceil(-t) - 1 with fraction 1 - f in (0, 1], so a
+// reflected visibility sees exactly the mirrored cells, also on a grid node.
+struct HalfCell {
+    int32_t cx, cy, refl;
+    double fx, fy;
+};
+static inline HalfCell half_cell(double u, double v, int Kx, int Ky) {
+    const double tX = u * (double)Kx;   // one correctly rounded product, as the definition
+    const double tY = v * (double)Ky;
+    const double flx = std::floor(tX), fly = std::floor(tY);
+    int64_t ix = (int64_t)flx % Kx, iy = (int64_t)fly % Ky;
+    if (ix < 0) ix += Kx;
+    if (iy < 0) iy += Ky;
+    const double fx = tX - flx, fy = tY - fly;
+    HalfCell h{(int32_t)ix, (int32_t)iy, 0, fx, fy};
+    if (ix > Kx / 2 || (ix == Kx / 2 && fx > 0.0)) {
+        h.refl = 1;
+        h.cx = (int32_t)(Kx - 1 - ix);
+        h.cy = (int32_t)(Ky - 1 - iy);
+        h.fx = 1.0 - fx;   // exact: fx is a multiple of ulp(tX)
+        h.fy = 1.0 - fy;
+    }
+    return h;
+}
+
 static void order_channel(int64_t M, const double* uv, const double* u, int nb, const int64_t* bp, int nx, int ny,
                           int T, ChanOrder& o) {
     const int Kx = 2 * nx, Ky = 2 * ny;
-    const int tx = Kx / T, ty = Ky / T;
+    const int tx = nx / T + 1, ty = Ky / T;   // visibility tiles over kx in [0, Kx/2 + T)
     const int64_t ntr = (int64_t)tx * ty * 9;
     o.cx.resize(M);
     o.cy.resize(M);
     o.fx.resize(M);
     o.fy.resize(M);
+    o.refl.resize(M);
     std::vector<int64_t> key(M);
     for (int64_t m = 0; m < M; ++m) {
-        const double tX = uv[2 * m] * (double)Kx;   // one correctly rounded product, as the definition
-        const double tY = uv[2 * m + 1] * (double)Ky;
-        const double flx = std::floor(tX), fly = std::floor(tY);
-        int64_t ix = (int64_t)flx % Kx, iy = (int64_t)fly % Ky;
-        if (ix < 0) ix += Kx;
-        if (iy < 0) iy += Ky;
-        o.cx[m] = (int32_t)ix;
-        o.cy[m] = (int32_t)iy;
-        o.fx[m] = tX - flx;
-        o.fy[m] = tY - fly;
-        const int64_t tile = (iy / T) * tx + (ix / T);
-        const int reg = 3 * region_class((int)(iy % T), T) + region_class((int)(ix % T), T);
+        const HalfCell h = half_cell(uv[2 * m], uv[2 * m + 1], Kx, Ky);
+        o.cx[m] = h.cx;
+        o.cy[m] = h.cy;
+        o.fx[m] = h.fx;
+        o.fy[m] = h.fy;
+        o.refl[m] = h.refl;
+        const int64_t tile = (h.cy / T) * tx + (h.cx / T);
+        const int reg = 3 * region_class(h.cy % T, T) + region_class(h.cx % T, T);
         key[m] = tile * 9 + reg;
     }
     // bins: block * C + rank of the preconditioner value
@@ -263,9 +291,12 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
     }
 }
 
-// The 13 source ranges feeding the core of tile (txi, tyi): own tile, and the
-// border regions of the 8 neighbours whose kernel footprints reach into it.
-static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_x, int tiles_y, int txi, int tyi,
+// The source ranges feeding the core of gridding tile (gtx, tyi) (origin
+// ((gtx - 1) T, tyi T)): the visibility tile with the same origin and the
+// border regions of its neighbours whose kernel footprints reach into it.
+// Periodic in y; in x the half plane has no wrap (the margins beyond kx = 0
+// and kx = Kx/2 are folded after gridding).  Empty ranges fill the rest.
+static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_x, int tiles_y, int gtx, int tyi,
                         int32_t* out) {
     int k = 0;
     auto push = [&](int64_t s, int64_t e) {
@@ -273,9 +304,11 @@ static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_
         out[2 * k + 1] = (int32_t)(base + e);
         ++k;
     };
+    const int txi = gtx - 1;   // visibility tile of the same origin (may be -1 or tiles_x)
     for (int dy = -1; dy <= 1; ++dy) {
         for (int dx = -1; dx <= 1; ++dx) {
-            const int sx = (txi - dx + tiles_x) % tiles_x, sy = (tyi - dy + tiles_y) % tiles_y;
+            const int sx = txi - dx, sy = (tyi - dy + tiles_y) % tiles_y;
+            if (sx < 0 || sx >= tiles_x) continue;
             const int64_t t = (int64_t)sy * tiles_x + sx;
             // source at target - (dx,dy): dx = +1 -> source right border (class 2)
             const int rc = (dy == 1) ? 2 : 0;   // row class when dy != 0
@@ -291,6 +324,7 @@ static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_
             }
         }
     }
+    while (k < N_GRANGES) push(0, 0);
 }
 
 hs_status build_plan(hs_ctx* c) {
@@ -305,9 +339,15 @@ hs_status build_plan(hs_ctx* c) {
     if (T < 8 || T > 32 || (T & (T - 1)) || c->Kx % T || c->Ky % T || c->Kx / T < 3 || c->Ky / T < 3)
         return fail(c, HS_ERR_SHAPE, "hs_plan: tile must be a power of two in 8..32 with >= 3 tiles per dimension");
     c->T = T;
-    c->tiles_x = c->Kx / T;
+    c->Kh = c->Kx / 2;
+    c->Wh = c->Kh + 1;
+    c->Wg = c->Kh + 2 * T;
+    c->Hs = c->Kh + 16;
+    c->tiles_x = c->Kh / T + 1;
     c->tiles_y = c->Ky / T;
     c->ntiles = c->tiles_x * c->tiles_y;
+    c->gtiles_x = c->tiles_x + 1;
+    c->ngtiles = c->gtiles_x * c->tiles_y;
     // offsets
     c->chan_off.assign(L + 1, 0);
     c->blk_off.assign(L + 1, 0);
@@ -348,7 +388,7 @@ hs_status build_plan(hs_ctx* c) {
         for (int64_t k = 0; k < ch.M; ++k) {
             const int64_t m = o.perm[k];
             const int64_t g = base + k;
-            c->h_cell[g] = (o.cy[m] << 16) | o.cx[m];
+            c->h_cell[g] = (o.cy[m] << 16) | (o.refl[m] << 15) | o.cx[m];
             c->h_frac[2 * g] = o.fx[m];
             c->h_frac[2 * g + 1] = o.fy[m];
             c->h_theta[g] = ch.theta[m];
@@ -400,16 +440,15 @@ hs_status build_plan(hs_ctx* c) {
         // relative to the tile (counting sort, stable), so that the kernel sees
         // runs of visibilities sharing a footprint.
         for (int tyi = 0; tyi < c->tiles_y; ++tyi) {
-            for (int txi = 0; txi < c->tiles_x; ++txi) {
-                const int t = tyi * c->tiles_x + txi;
-                const int ox = txi * T, oy = tyi * T, W7 = T + 7;
+            for (int gtx = 0; gtx < c->gtiles_x; ++gtx) {
+                const int t = tyi * c->gtiles_x + gtx;
+                const int ox = (gtx - 1) * T, oy = tyi * T, W7 = T + 7;
                 int32_t rg[2 * N_GRANGES];
-                tile_ranges(o.region_ptr, base, c->tiles_x, c->tiles_y, txi, tyi, rg);
+                tile_ranges(o.region_ptr, base, c->tiles_x, c->tiles_y, gtx, tyi, rg);
                 auto key_of = [&](int64_t g) -> int {
                     const int32_t cl = c->h_cell[g];
-                    int relx = (cl & 0xFFFF) - ox, rely = (cl >> 16) - oy;
-                    if (relx < -T) relx += c->Kx;
-                    if (relx >= 2 * T) relx -= c->Kx;
+                    const int relx = (cl & 0x7FFF) - ox;
+                    int rely = (cl >> 16) - oy;
                     if (rely < -T) rely += c->Ky;
                     if (rely >= 2 * T) rely -= c->Ky;
                     const int rx0 = relx - 3, ry0 = rely - 3;

@@ -2,10 +2,14 @@
 // and the data-fidelity dual update (Algorithm 2, Steps 4 and 10-12, eq:md).
 //
 // Design (gfx950):
-//  * F Z: two LDS Stockham radix-4/2 passes.  The row pass transforms only the
-//    ny rows that Z fills (zero-padding is implicit); the column pass works on
-//    tiles of CT adjacent columns so every HBM access is a CT-wide contiguous
-//    segment.  The adjoint mirrors it and only writes the rows Z^T keeps.
+//  * Hermitian half plane: the image is real, so its transform at -k is the
+//    conjugate of that at k.  Only kx in [0, Kx/2] is transformed and stored;
+//    a visibility at negative kx is handled at -t with conjugated value.
+//  * F Z: register/LDS Stockham passes.  The row pass transforms only the ny
+//    rows that Z fills (zero-padding is implicit), two real rows per complex
+//    transform; the column pass works on tiles of CT adjacent columns of the
+//    half plane so every HBM access is a CT-wide contiguous segment.  The
+//    adjoint mirrors it and only writes the rows Z^T keeps.
 //  * G (degridding): visibilities are stored tile-major; a work unit stages the
 //    (T+8)^2 grid neighbourhood of its tile in LDS and each thread interpolates
 //    one visibility (8 + 8 kernel values, 64 taps from LDS).
@@ -14,6 +18,8 @@
 //    it (its own tile plus the border regions of the 8 neighbours, 13 ranges),
 //    accumulating in LDS; each grid cell is written exactly once.  Tiles with
 //    many visibilities are split and their partial cores summed in fixed order.
+//    Gridding tiles also cover one tile-wide margin beyond kx = 0 and kx = Kx/2;
+//    the adjoint column pass folds the margins back (conjugate mirror cells).
 //  * Per-block FP64 sums for the ellipsoid projection are produced by a
 //    deterministic segmented scan in the degridding pass and reduced per
 //    (block, preconditioner value) bin, so the secular equation of the exact
@@ -182,104 +188,167 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, int u, int s, int n, int C
     }
 }
 
-// Row pass of F Z: rows j of image l are deapodised, placed at (i - nx/2) mod Kx
-// and transformed; H[l][j][:] holds the transformed row (only the ny rows Z fills).
+// Real-to-complex row pass of F Z.  Rows ja = 2p and jb = 2p + 1 of image l are
+// deapodised, placed at (i - nx/2) mod Kx and transformed together as
+// z = x_a + i x_b; the halves are separated by the Hermitian symmetry of the
+// transform of a real sequence, X_a[k] = (Z[k] + conj Z[-k]) / 2 and
+// X_b[k] = -i (Z[k] - conj Z[-k]) / 2, and only k in [0, Kx/2] is kept
+// (row stride Hs).  The last FFT pass writes Z to LDS for the separation.
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, cplx<T>* __restrict__ H,
                                                        const T* __restrict__ sx, const T* __restrict__ sy,
                                                        const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
-                                                       int rows) {
+                                                       int Hs, int pairs) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int tps = Kx >> 4;                        // threads per sequence
     const int u = threadIdx.x % tps, s = threadIdx.x / tps;
-    const int j = blockIdx.x * rows + s;
-    const T* Xr = X + ((size_t)l * ny + j) * nx;
-    const T syj = sy[j];
-    cplx<T>* Hr = H + ((size_t)l * ny + j) * Kx;
+    const int ja = 2 * (blockIdx.x * pairs + s);
+    const T* Xa = X + ((size_t)l * ny + ja) * nx;
+    const T* Xb = Xa + nx;
+    const T sya = sy[ja], syb = sy[ja + 1];
     fft_run<T, false, true>(buf, u, s, Kx, 0, tw,
         [&](int q) {
             int i = q + (nx >> 1);
             if (i >= Kx) i -= Kx;
-            return cplx<T>{i < nx ? Xr[i] * sx[i] * syj : T(0), T(0)};
+            if (i >= nx) return cplx<T>{T(0), T(0)};
+            const T w = sx[i];
+            return cplx<T>{Xa[i] * w * sya, Xb[i] * w * syb};
         },
-        [&](int q, const cplx<T>& v) { Hr[q] = v; });
+        [&](int q, const cplx<T>& v) { buf[fft_slot<true>(q, s, Kx, 0)] = v; });
+    __syncthreads();
+    const int Kh = Kx >> 1;
+    cplx<T>* Ha = H + ((size_t)l * ny + ja) * Hs;
+    cplx<T>* Hb = Ha + Hs;
+    for (int k = u; k <= Kh; k += tps) {
+        const cplx<T> zk = buf[fft_slot<true>(k, s, Kx, 0)];
+        const cplx<T> zm = buf[fft_slot<true>((Kx - k) & (Kx - 1), s, Kx, 0)];
+        Ha[k] = {(zk.re + zm.re) * T(0.5), (zk.im - zm.im) * T(0.5)};
+        Hb[k] = {(zk.im + zm.im) * T(0.5), (zm.re - zk.re) * T(0.5)};
+    }
 }
 
 // Column tile of work-group b (of nb): work-groups b and b + 8 run on the same
 // XCD (work-groups are dispatched round-robin over the 8 XCDs, each with its
 // own L2) and take adjacent tiles, so both halves of a 128-byte line of a grid
-// row are read through one L2.
+// row are read through one L2.  Tiles past the last full group of 16 keep
+// their index.
 __device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
-    if (nb & 15) return b;
+    if (b >= (nb & ~15)) return b;
     const int q = b >> 4, r = b & 15;
     return (q << 4) + ((r & 7) << 1) + (r >> 3);
 }
 
-// Column pass of F: CT adjacent columns, rows placed at (j - ny/2) mod Ky.
+// Column pass of F over the half plane: columns kx in [0, Kx/2] in tiles of CT
+// adjacent columns (the last tile is partly idle), rows placed at
+// (j - ny/2) mod Ky.  The grid row has Wg cells, kx = 0 at cell T.
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
-                                                       const cplx<T>* __restrict__ tw, int ny, int Kx, int Ky,
-                                                       int CT) {
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
+                                                       int Hs, int Wg, int TT, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
     const int c = xcd_pair_tile(blockIdx.x, gridDim.x) * CT + s;
-    const cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
-    cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
+    const bool live = c <= Kh;
+    const cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
+    cplx<T>* Gl = G + (size_t)l * Ky * Wg + TT + c;
     fft_run<T, false, false>(buf, u, s, Ky, CT, tw,
         [&](int q) {
             int j = q + (ny >> 1);
             if (j >= Ky) j -= Ky;
-            return j < ny ? Hl[(size_t)j * Kx] : cplx<T>{T(0), T(0)};
+            return (live && j < ny) ? Hl[(size_t)j * Hs] : cplx<T>{T(0), T(0)};
         },
-        [&](int q, const cplx<T>& v) { Gl[(size_t)q * Kx] = v; });
+        [&](int q, const cplx<T>& v) {
+            if (live) Gl[(size_t)q * Wg] = v;
+        });
 }
 
-// Adjoint column pass: inverse (unnormalised) DFT along y, keep the rows Z^T reads.
+// Adjoint column pass over the half plane: inverse (unnormalised) DFT along y
+// of the folded grid, keeping the rows Z^T reads.  Gridding leaves the
+// contributions that fall beyond kx = 0 or kx = Kx/2 in the margins of the
+// grid row; the Hermitian part of the full-plane grid is (g[k] + conj g[-k]) / 2,
+// so columns within GR_FOLD of either edge add the conjugate of their mirror
+// cell as they are loaded (the factor 1/2 is applied by the row pass).
+constexpr int GR_FOLD = 4;
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H,
-                                                       const cplx<T>* __restrict__ tw, int ny, int Kx, int Ky,
-                                                       int CT) {
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
+                                                       int Hs, int Wg, int TT, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int s = threadIdx.x & (CT - 1), u = threadIdx.x / CT;
     const int c = xcd_pair_tile(blockIdx.x, gridDim.x) * CT + s;
-    const cplx<T>* Gl = G + (size_t)l * Ky * Kx + c;
-    cplx<T>* Hl = H + (size_t)l * ny * Kx + c;
+    const bool live = c <= Kh;
+    const bool fold = c <= GR_FOLD || (c >= Kh - GR_FOLD && live);
+    const int mx = c <= GR_FOLD ? -c : 2 * Kh - c;
+    const cplx<T>* G0 = G + (size_t)l * Ky * Wg + TT;   // kx = 0
+    cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
     fft_run<T, true, false>(buf, u, s, Ky, CT, tw,
-        [&](int q) { return Gl[(size_t)q * Kx]; },
+        [&](int q) {
+            if (!live) return cplx<T>{T(0), T(0)};
+            cplx<T> g = G0[(size_t)q * Wg + c];
+            if (fold) {
+                const cplx<T> h = G0[(size_t)(q == 0 ? 0 : Ky - q) * Wg + mx];
+                g.re += h.re;
+                g.im -= h.im;
+            }
+            return g;
+        },
         [&](int q, const cplx<T>& v) {
             int j = q + (ny >> 1);
             if (j >= Ky) j -= Ky;
-            if (j < ny) Hl[(size_t)j * Kx] = v;
+            if (live && j < ny) Hl[(size_t)j * Hs] = v;
         });
 }
 
-// Adjoint row pass: inverse DFT along x, crop, deapodise, real part.
+// Complex-to-real adjoint row pass: rows ja = 2p and jb = 2p + 1 hold the half
+// spectra A, B (k in [0, Kx/2]) of two real rows; Z[k] = A[k] + i B[k] with
+// A[k] = conj A[Kx - k] beyond Kx/2 (and the real parts at k = 0 and Kx/2,
+// which is what the real part of the full inverse transform keeps) gives
+// x_a + i x_b in one inverse DFT.  Crop, deapodise, times 1/2.
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict__ H, T* __restrict__ X,
                                                        const T* __restrict__ sx, const T* __restrict__ sy,
                                                        const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
-                                                       int rows) {
+                                                       int Hs, int pairs) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
     const int tps = Kx >> 4;
     const int u = threadIdx.x % tps, s = threadIdx.x / tps;
-    const int j = blockIdx.x * rows + s;
-    const cplx<T>* Hr = H + ((size_t)l * ny + j) * Kx;
-    T* Xr = X + ((size_t)l * ny + j) * nx;
-    const T syj = sy[j];
+    const int ja = 2 * (blockIdx.x * pairs + s);
+    const int Kh = Kx >> 1;
+    const cplx<T>* Ha = H + ((size_t)l * ny + ja) * Hs;
+    const cplx<T>* Hb = Ha + Hs;
+    T* Xa = X + ((size_t)l * ny + ja) * nx;
+    T* Xb = Xa + nx;
+    const T sya = sy[ja] * T(0.5), syb = sy[ja + 1] * T(0.5);
     fft_run<T, true, true>(buf, u, s, Kx, 0, tw,
-        [&](int q) { return Hr[q]; },
+        [&](int q) {
+            const bool up = q > Kh;
+            const int k = up ? Kx - q : q;
+            cplx<T> a = Ha[k], b = Hb[k];
+            if (up) {
+                a.im = -a.im;
+                b.im = -b.im;
+            } else if (q == 0 || q == Kh) {
+                a.im = T(0);
+                b.im = T(0);
+            }
+            return cplx<T>{a.re - b.im, a.im + b.re};
+        },
         [&](int q, const cplx<T>& v) {
             int i = q + (nx >> 1);
             if (i >= Kx) i -= Kx;
-            if (i < nx) Xr[i] = v.re * sx[i] * syj;
+            if (i < nx) {
+                const T w = sx[i];
+                Xa[i] = v.re * w * sya;
+                Xb[i] = v.im * w * syb;
+            }
         });
 }
 
@@ -288,18 +357,19 @@ static void set_lds(KF kern, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Rows per workgroup for the row passes (power of two dividing ny, Kx * rows <= 8192: <= 512 threads).
+// Row pairs per workgroup for the row passes (power of two, 2 * pairs dividing
+// ny, Kx * pairs <= 8192: <= 512 threads).
 static int row_group(const hs_ctx* c) {
-    int rows = 1;
-    while (rows * 2 <= c->ny && (c->ny % (rows * 2)) == 0 && c->Kx * rows * 2 <= 8192) rows *= 2;
-    return rows;
+    int p = 1;
+    while (4 * p <= c->ny && (c->ny % (4 * p)) == 0 && c->Kx * p * 2 <= 8192) p *= 2;
+    return p;
 }
 // Columns per tile for the column passes (16 elements per thread, <= 512 threads, LDS <= 128 KiB).
 template <typename T>
 static int col_group(const hs_ctx* c) {
     const int maxE = (int)(131072 / sizeof(cplx<T>));
     int ct = 1;
-    while (ct * 2 <= c->Kx && c->Kx % (ct * 2) == 0 && c->Ky * ct * 2 <= maxE && c->Ky * ct * 2 <= 8192 && ct < 16)
+    while (ct * 2 <= c->Kh && c->Ky * ct * 2 <= maxE && c->Ky * ct * 2 <= 8192 && ct < 16)
         ct *= 2;
     return ct;
 }
@@ -327,37 +397,35 @@ void fft_init_attrs() {
 
 template <typename T>
 void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L) {
-    const int rows = row_group(c);
-    dim3 grid(c->ny / rows, L);
-    const int nth = std::max(1, c->Kx * rows / 16);
-    k_fft_rows_fwd<T><<<grid, nth, row_lds(c, rows, sizeof(cplx<T>)), c->stream>>>(
+    const int p = row_group(c);
+    dim3 grid(c->ny / (2 * p), L);
+    k_fft_rows_fwd<T><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
         X, (cplx<T>*)c->d.H, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx,
-        rows);
+        c->Hs, p);
 }
 template <typename T>
 void launch_fft_cols_fwd(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
-    dim3 grid(c->Kx / ct, L);
-    const int nth = std::max(1, c->Ky * ct / 16);
-    k_fft_cols_fwd<T><<<grid, nth, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+    dim3 grid((c->Wh + ct - 1) / ct, L);
+    k_fft_cols_fwd<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
+        c->T, ct);
 }
 template <typename T>
 void launch_fft_cols_adj(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
-    dim3 grid(c->Kx / ct, L);
-    const int nth = std::max(1, c->Ky * ct / 16);
-    k_fft_cols_adj<T><<<grid, nth, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kx, c->Ky, ct);
+    dim3 grid((c->Wh + ct - 1) / ct, L);
+    k_fft_cols_adj<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
+        c->T, ct);
 }
 template <typename T>
 void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
-    const int rows = row_group(c);
-    dim3 grid(c->ny / rows, L);
-    const int nth = std::max(1, c->Kx * rows / 16);
-    k_fft_rows_adj<T><<<grid, nth, row_lds(c, rows, sizeof(cplx<T>)), c->stream>>>(
+    const int p = row_group(c);
+    dim3 grid(c->ny / (2 * p), L);
+    k_fft_rows_adj<T><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
         (const cplx<T>*)c->d.H, Xout, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
-        c->Kx, rows);
+        c->Kx, c->Hs, p);
 }
 
 // ------------------------------------------------------------- KB kernel
@@ -382,18 +450,30 @@ __device__ __forceinline__ void kb_weights(T f, const KBPoly<T>& P, T* w) {
 }
 
 // ------------------------------------------------------------- degridding
+// Stage the (T+8)^2 window of the half-plane grid around tile origin (ox, oy):
+// g0 points at kx = 0 of the channel's grid (rows of Wg cells).  Cells beyond the
+// half plane (kx < 0 or kx > Kx/2) are the conjugates of their reflections
+// (Hermitian symmetry of the transform of a real image); y is periodic.
 template <typename T>
-__device__ __forceinline__ void stage_tile(cplx<T>* tileS, const cplx<T>* __restrict__ g, int ox, int oy, int TT,
-                                           int Kx, int Ky) {
+__device__ __forceinline__ void stage_tile(cplx<T>* tileS, const cplx<T>* g0, int ox, int oy, int TT, int Kh, int Ky,
+                                           int Wg) {
     const int W = TT + 8;
     for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
         const int ry = e / W, rx = e - ry * W;
-        int gy = oy - 3 + ry, gx = ox - 3 + rx;
+        int gy = oy - 3 + ry;
         if (gy < 0) gy += Ky;
         if (gy >= Ky) gy -= Ky;
-        if (gx < 0) gx += Kx;
-        if (gx >= Kx) gx -= Kx;
-        tileS[e] = g[(size_t)gy * Kx + gx];
+        const int gx = ox - 3 + rx;
+        cplx<T> v;
+        if (gx >= 0 && gx <= Kh) {
+            v = g0[(size_t)gy * Wg + gx];
+        } else {
+            const int mx = gx < 0 ? -gx : 2 * Kh - gx;
+            const int my = gy == 0 ? 0 : Ky - gy;
+            const cplx<T> w = g0[(size_t)my * Wg + mx];
+            v = {w.re, -w.im};
+        }
+        tileS[e] = v;
     }
 }
 
@@ -425,20 +505,22 @@ template <typename T>
 __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ mult,
-    const int32_t* __restrict__ perm, cplx<T>* __restrict__ out, int Kx, int Ky, int TT, int tiles_x, KBPoly<T> kb) {
+    const int32_t* __restrict__ perm, cplx<T>* __restrict__ out, int Kh, int Ky, int Wg, int TT, int tiles_x,
+    KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
     const DegridUnit u = units[blockIdx.x];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    stage_tile(tileS, grid + (size_t)u.l * Kx * Ky, ox, oy, TT, Kx, Ky);
+    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + TT, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
     for (int i = threadIdx.x; i < u.count; i += DEG_THREADS) {
         const int pos = u.start + i;
         const int cc = cell[pos];
-        const int cx = cc & 0xFFFF, cy = cc >> 16;
+        const int cx = cc & 0x7FFF, cy = cc >> 16;
         const cplx<T> f = frac[pos];
         cplx<T> a = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
+        if (cc & 0x8000) a.im = -a.im;   // reflected visibility: conjugate of the value at -t
         T s = theta[pos];
         if (mult) s *= mult[pos];
         a.re *= s;
@@ -454,14 +536,14 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ uprec,
     const cplx<T>* __restrict__ yv, const int32_t* __restrict__ vbin, cplx<T>* __restrict__ v,
-    double* __restrict__ run_sum, int Kx, int Ky, int TT, int tiles_x, KBPoly<T> kb) {
+    double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x, KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
     __shared__ double s0[DEG_THREADS], s1[DEG_THREADS];
     __shared__ int sb[DEG_THREADS], sh[DEG_THREADS], sf[DEG_THREADS];
     const DegridUnit u = units[blockIdx.x];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    stage_tile(tileS, grid + (size_t)u.l * Kx * Ky, ox, oy, TT, Kx, Ky);
+    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + TT, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
     const int tid = threadIdx.x;
@@ -474,9 +556,10 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
         if (act) {
             const int pos = u.start + i;
             const int cc = cell[pos];
-            const int cx = cc & 0xFFFF, cy = cc >> 16;
+            const int cx = cc & 0x7FFF, cy = cc >> 16;
             const cplx<T> f = frac[pos];
             cplx<T> g = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
+            if (cc & 0x8000) g.im = -g.im;   // reflected visibility
             const T th = theta[pos];
             g.re *= th;
             g.im *= th;
@@ -694,7 +777,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
     const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
     const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
-    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Kx, int Ky, int TT, int tiles_x,
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int TT, int gtiles_x,
     KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     const int TS = grid_stride(TT), TA = TT + 2 * GR_APRON;
@@ -711,7 +794,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     GridFetch<T> nxt;
     grid_fetch<T>(nxt, pos0, cell, frac, vals, weight);
     for (int e = lane; e < TA * TS; e += 64) acc[e] = {T(0), T(0)};
-    const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
+    const int ox = (u.tile % gtiles_x - 1) * TT, oy = (u.tile / gtiles_x) * TT;   // ox = -T for the margin tile
     // key of an entry: accumulator offset of its first tap (a bijection with the
     // first-tap cell); before the first entry the open "run" adds zeros at 0
     int prev = -1, slot = lane_off;
@@ -726,9 +809,8 @@ __global__ __launch_bounds__(64) void k_grid_pull(
         int key = -1;
         T* wv = wts + lane * GW;
         if (e < n) {
-            int relx = (g.cc & 0xFFFF) - ox, rely = (g.cc >> 16) - oy;
-            if (relx < -TT) relx += Kx;
-            if (relx >= 2 * TT) relx -= Kx;
+            const int relx = (g.cc & 0x7FFF) - ox;   // the half plane has no wrap in x
+            int rely = (g.cc >> 16) - oy;
             if (rely < -TT) rely += Ky;
             if (rely >= 2 * TT) rely -= Ky;
             key = (rely - 3 + GR_APRON) * TS + (relx - 3 + GR_APRON);
@@ -739,7 +821,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             kb_weights(g.f.im, kb, w8);
 #pragma unroll
             for (int j = 0; j < KB_J; ++j) wv[8 + j] = w8[j];
-            vv[lane] = g.val;
+            vv[lane] = (g.cc & 0x8000) ? cplx<T>{g.val.re, -g.val.im} : g.val;   // reflected: conjugate value
         } else {
 #pragma unroll
             for (int j = 0; j < 16; ++j) wv[j] = T(0);
@@ -778,10 +860,10 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     acc[slot] = {old.re + racc.re, old.im + racc.im};
     __syncthreads();
     if (u.nsplit == 1) {
-        cplx<T>* g = grid + (size_t)u.l * Kx * Ky;
+        cplx<T>* g = grid + (size_t)u.l * Ky * Wg + TT;   // column of kx = 0
         for (int e = lane; e < TT * TT; e += 64) {
             const int ry = e / TT, rx = e - ry * TT;
-            g[(size_t)(oy + ry) * Kx + ox + rx] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
+            g[(size_t)(oy + ry) * Wg + ox + rx] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
         }
     } else {
         cplx<T>* p = partial + (size_t)(u.partial + u.split) * TT * TT;
@@ -794,10 +876,10 @@ __global__ __launch_bounds__(64) void k_grid_pull(
 
 template <typename T>
 __global__ void k_grid_merge(const SplitTile* __restrict__ splits, const cplx<T>* __restrict__ partial,
-                             cplx<T>* __restrict__ grid, int Kx, int Ky, int TT, int tiles_x) {
+                             cplx<T>* __restrict__ grid, int Ky, int Wg, int TT, int gtiles_x) {
     const SplitTile s = splits[blockIdx.x];
-    const int ox = (s.tile % tiles_x) * TT, oy = (s.tile / tiles_x) * TT;
-    cplx<T>* g = grid + (size_t)s.l * Kx * Ky;
+    const int ox = (s.tile % gtiles_x - 1) * TT, oy = (s.tile / gtiles_x) * TT;
+    cplx<T>* g = grid + (size_t)s.l * Ky * Wg + TT;
     for (int e = threadIdx.x; e < TT * TT; e += blockDim.x) {
         cplx<T> acc{T(0), T(0)};
         for (int k = 0; k < s.nsplit; ++k) {
@@ -806,7 +888,7 @@ __global__ void k_grid_merge(const SplitTile* __restrict__ splits, const cplx<T>
             acc.im += p.im;
         }
         const int ry = e / TT, rx = e - ry * TT;
-        g[(size_t)(oy + ry) * Kx + ox + rx] = acc;
+        g[(size_t)(oy + ry) * Wg + ox + rx] = acc;
     }
 }
 
@@ -919,7 +1001,8 @@ void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user) {
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
     k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
-        (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+        (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x,
+        kbpoly<T>(c));
 }
 
 // Degrid into grid order with an extra per-visibility factor (used by the power iteration).
@@ -929,7 +1012,7 @@ void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult) {
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
     k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
-        (const T*)c->d.vis_theta, mult, nullptr, out, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+        (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
 }
 
 template <typename T>
@@ -939,7 +1022,7 @@ void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v) {
     k_degrid_dual<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
-        c->d.run_sum, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+        c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
 }
 
 template <typename T>
@@ -966,10 +1049,10 @@ void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
                        64 * GW * sizeof(T);
     k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
         c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
-        (cplx<T>*)c->d.gpartial, c->Kx, c->Ky, c->T, c->tiles_x, kbpoly<T>(c));
+        (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->T, c->gtiles_x, kbpoly<T>(c));
     if (!c->splits.empty())
         k_grid_merge<T><<<(unsigned)c->splits.size(), 256, 0, c->stream>>>(
-            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Kx, c->Ky, c->T, c->tiles_x);
+            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->T, c->gtiles_x);
 }
 
 template <typename T>

@@ -303,7 +303,7 @@ def visibility_order(uv, precond, block_ptr, nx, ny, tile):
     pre = None if precond is None else np.ascontiguousarray(precond, dtype=np.float64)
     bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
     perm = np.empty(M, dtype=np.int64)
-    ntr = (2 * nx // tile) * (2 * ny // tile) * 9
+    ntr = (nx // tile + 1) * (2 * ny // tile) * 9
     rp = np.empty(ntr + 1, dtype=np.int64)
     L.check(lib.hs_visibility_order(M, L.as_dptr(uv), L.as_dptr(pre), len(bp) - 1, L.as_i64p(bp), nx, ny, tile,
                                     L.as_i64p(perm), L.as_i64p(rp)), None, "hs_visibility_order")

@@ -317,3 +317,36 @@ def test_edge_cases_empty_channel_empty_block_zero_eps():
             check_rel(vg[l][s], r, 1e-12, "vg[l][s]")
     Xa = host(prob.phi_adj(to_dev(prob, v, complex_=True)))
     assert np.all(Xa[1] == 0)
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_half_plane_nodes_line_and_fold_band(tile):
+    """Visibilities on grid nodes (reflected and not), on and next to the line
+    kx = Kx/2, and next to kx = 0, where the half-plane reflection, the mirrored
+    staging and the fold of the gridding margins all act: Phi element by
+    element and Phi^T against the FP64 oracle."""
+    import paper_1806_04596_amd as H
+    nx = ny = 32
+    Kx = 2 * nx
+    rng = np.random.default_rng(17)
+    pts = [(k / Kx, j / Kx) for k in (0, 1, 3, 4, 5, 28, 31, 32, 33, 35, 36, 60, 63, -1, -3, 64, 97)
+           for j in (0, 1, 31, 32, 33, -2)]
+    eps_u = [2.0 ** -20, 2.0 ** -12, 1e-3]
+    pts += [(0.5 + s * e, v) for e in eps_u for s in (-1, 1) for v in (0.1, -0.3, 0.5)]
+    pts += [(s * e, v) for e in eps_u for s in (-1, 1) for v in (0.2, -0.45, 0.0)]
+    pts += [tuple(p) for p in rng.uniform(-0.6, 0.6, (200, 2))]
+    uv = np.array(pts).astype(np.float32).astype(np.float64)
+    m = len(uv)
+    y = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    th = rng.uniform(0.5, 2.0, m)
+    bp = np.array([0, m])
+    prob = H.Problem(nx, ny, [dict(uv=uv, y_raw=y, theta=th, block_ptr=bp, eps=np.array([1.0]), precond=None)],
+                     dtype="f64", tile=tile)
+    op = pd.Problem(nx=nx, ny=ny, uv=[uv], y=[y * th], theta=[th], u=[np.ones(m)], eps=[np.array([1.0])],
+                    block_ptr=[bp])
+    X = rng.uniform(0, 1, (1, ny, nx))
+    Y = host(prob.phi(to_dev(prob, X)))
+    ref = op.phi(X)[0]
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    v = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    check_rel(host(prob.phi_adj(to_dev(prob, v, complex_=True))), op.phi_adj([v]), 1e-12, "Phi^T v")

@@ -1,5 +1,7 @@
 """Pins of the preconditioner density and of the visibility-order definition."""
 from collections import Counter
+from fractions import Fraction
+import math
 
 import numpy as np
 
@@ -27,9 +29,8 @@ def test_order_definition_properties():
         perm, rptr = binning.order(uv, u, bp, cfg.nx, cfg.ny, T)
         M = len(uv)
         assert np.array_equal(np.sort(perm), np.arange(M))
-        cx, cy = binning.cells(uv, cfg.nx, cfg.ny)
-        Kx = 2 * cfg.nx
-        tile = (cy // T) * (Kx // T) + cx // T
+        cx, cy, _ = binning.cells(uv, cfg.nx, cfg.ny)
+        tile = (cy // T) * (cfg.nx // T + 1) + cx // T
         reg = 3 * binning.region_class(cy % T, T) + binning.region_class(cx % T, T)
         key = tile * 9 + reg
         assert np.all(np.diff(key[perm]) >= 0)
@@ -48,3 +49,35 @@ def test_region_reaches_neighbour_exactly():
     cls = binning.region_class(o, T)
     assert np.array_equal(cls == 0, o - 3 < 0)
     assert np.array_equal(cls == 2, o + 4 >= T)
+
+
+def test_half_plane_cells_by_exact_arithmetic():
+    """Each visibility's half-plane cell is floor(p) of p = t mod K if that has
+    kx <= Kx/2, else (the transform of a real image at -t is the conjugate of
+    that at t) the cell whose 8 taps are the mirror images of the taps of t,
+    ceil(p) - 1 of p = -t mod K; computed here in exact rational arithmetic."""
+    nx, ny = 16, 16
+    Kx, Ky = 2 * nx, 2 * ny
+    rng = np.random.default_rng(5)
+    uv = rng.uniform(-1.2, 1.2, (400, 2)).astype(np.float32).astype(np.float64)
+    # on nodes, on the reflection line kx = Kx/2 and next to it, at 0
+    uv = np.concatenate([uv, [[0.5, 0.25], [-0.5, -0.25], [0.5 + 2.0 ** -20, 0.1], [0.5 - 2.0 ** -20, 0.1],
+                              [0.0, 0.0], [0.0, 0.5], [1 / 32, -1 / 32], [-1 / 32, 1 / 32]]])
+    cx, cy, refl = binning.cells(uv, nx, ny)
+    for m, (a, b) in enumerate(uv):
+        px, py = (Fraction(a) * Kx) % Kx, (Fraction(b) * Ky) % Ky
+        r = px > nx
+        if r:
+            px, py = (-px) % Kx, (-py) % Ky
+        assert bool(refl[m]) == r, m
+        if r:
+            want = (math.ceil(px) - 1, math.ceil(py) - 1)
+            want = (want[0], want[1] % Ky)
+            # the taps of the mirror cell are the negated taps of t
+            t0x, t0y = math.floor(Fraction(a) * Kx), math.floor(Fraction(b) * Ky)
+            taps = {((-(t0x - 3 + i)) % Kx, (-(t0y - 3 + j)) % Ky) for i in range(8) for j in range(8)}
+            assert taps == {((want[0] - 3 + i) % Kx, (want[1] - 3 + j) % Ky) for i in range(8) for j in range(8)}
+        else:
+            want = (int(px // 1), int(py // 1))
+        assert (int(cx[m]), int(cy[m])) == want, m
+        assert 0 <= cx[m] <= nx
