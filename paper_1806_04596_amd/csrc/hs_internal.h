@@ -22,20 +22,28 @@ constexpr int MAX_DB = 8;
 constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
 
 // One degridding work unit: `count` (<= DEG_THREADS*DEG_BATCHES) visibilities of
-// one tile of channel l starting at global position `start`.  Its segmented
-// reduction runs are numbered from run_base.
+// one tile of channel l starting at global position `start`.  Runs of equal bin
+// are cut at every DEG_CHUNK visibilities of the unit (one wave's share);
+// chunk_run[chunk0 + j] is the number of the first run of chunk j.
+constexpr int DEG_CHUNK = 64;
 struct DegridUnit {
     int32_t l, tile, start, count;
-    int32_t run_base, pad0, pad1, pad2;
+    int32_t run_base, chunk0, pad1, pad2;
 };
 
 // One gridding work unit: entries [g0, g0 + gn) of the sorted entry list of
 // `tile` of channel l (its own visibilities and its neighbours' border ones, by
 // first-tap cell), part `split` of `nsplit`.  nsplit > 1 writes a partial tile
 // to slot partial + split; nsplit == 1 writes the grid directly.
+// One gridding work-group: a tile (or one split part of it) whose entries are
+// cut into GR_BANDS row bands of first-tap rows; bands 0, 2, 4 are gridded
+// together by the three waves, then bands 1, 3 (their footprints never share
+// a core cell with another band of the same pass).
+constexpr int GR_BANDS = 5;
 struct GridUnit {
     int32_t l, tile, split, nsplit;
-    int32_t partial, g0, gn, pad;
+    int32_t partial, pad;
+    int32_t bs[GR_BANDS], bn[GR_BANDS];   // glist start and length of each band
 };
 
 // A tile whose gridding was split: the partials are summed in order.
@@ -89,6 +97,7 @@ struct Dev {
     double* run_sum = nullptr;     // [nruns][2] (|d|^2, |y - Phi Xt|^2)
     int32_t* bin_run_ptr = nullptr;// [nbins+1]
     int32_t* bin_runs = nullptr;   // [nruns]
+    int32_t* chunk_run = nullptr;  // [chunks] first run of each DEG_CHUNK-visibility chunk
     double* bin_S = nullptr;       // [nbins][2]
     // FFT
     void* grid = nullptr;          // [L][Ky][Kx] complex
@@ -163,6 +172,7 @@ struct hs_ctx {
     std::vector<double> kb_c;          // power-series coefficients
     // host staging of the plan (uploaded at bind)
     std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_bin_runs;
+    std::vector<int32_t> h_chunk_run;
     std::vector<double> h_frac, h_y, h_theta, h_u, h_bin_u, h_blk_eps;
     std::vector<int64_t> h_pos_of;     // caller global index -> grid position
     size_t ws_bytes = 0;

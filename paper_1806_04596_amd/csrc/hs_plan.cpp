@@ -372,10 +372,28 @@ hs_status build_plan(hs_ctx* c) {
     c->h_blk_bin_ptr.assign(1, 0);
     c->h_blk_eps.clear();
     c->dunits.clear();
+    c->h_chunk_run.clear();
     c->gunits.clear();
     c->splits.clear();
     c->h_glist.clear();
     std::vector<int32_t> kcount((size_t)(T + 7) * (T + 7) + 1);
+    // Row bands of a gridding tile's entries by first-tap row r in 0 .. T+6 (an
+    // entry's footprint covers accumulator rows r .. r+7).  Bands 0, 2, 4 are
+    // gridded concurrently and bands 1, 3 afterwards; bands 1 and 3 are 7 rows
+    // high, so the footprints of one pass never share a row.
+    int band_row[GR_BANDS + 1];
+    {
+        const int R = T + 7;
+        if (R - 14 >= 21) {   // three bands of >= 7 rows in the first pass
+            const int na = (R - 14) / 3;
+            const int rows[GR_BANDS + 1] = {0, na, na + 7, 2 * na + 7, 2 * na + 14, R};
+            std::copy(rows, rows + GR_BANDS + 1, band_row);
+        } else {              // two bands in the first pass, one in the second
+            const int na = (R - 7) / 2;
+            const int rows[GR_BANDS + 1] = {0, na, na + 7, R, R, R};
+            std::copy(rows, rows + GR_BANDS + 1, band_row);
+        }
+    }
     std::vector<std::pair<int32_t, int32_t>> run_bin;  // (bin, run)
     int64_t nruns = 0, npartial = 0;
     int64_t bin_base = 0;
@@ -419,8 +437,10 @@ hs_status build_plan(hs_ctx* c) {
                 du.start = (int32_t)(base + p);
                 du.count = (int32_t)std::min<int64_t>(unit_max, e - p);
                 du.run_base = (int32_t)nruns;
-                for (int64_t b0 = 0; b0 < du.count; b0 += DEG_THREADS) {
-                    const int64_t b1 = std::min<int64_t>(du.count, b0 + DEG_THREADS);
+                du.chunk0 = (int32_t)c->h_chunk_run.size();
+                for (int64_t b0 = 0; b0 < du.count; b0 += DEG_CHUNK) {
+                    const int64_t b1 = std::min<int64_t>(du.count, b0 + DEG_CHUNK);
+                    c->h_chunk_run.push_back((int32_t)nruns);
                     int32_t prev = -1;
                     for (int64_t i = b0; i < b1; ++i) {
                         const int32_t bin = c->h_bin[base + p + i];
@@ -465,6 +485,9 @@ hs_status build_plan(hs_ctx* c) {
                         ++E;
                     }
                 for (int k = 0; k < W7 * W7; ++k) kcount[k + 1] += kcount[k];
+                // band boundaries (positions in the sorted list) from the first-tap rows
+                int64_t bpos[GR_BANDS + 1];
+                for (int b = 0; b <= GR_BANDS; ++b) bpos[b] = kcount[band_row[b] * W7];
                 const int64_t g0 = (int64_t)c->h_glist.size();
                 if (g0 + E > INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: too many gridding entries");
                 c->h_glist.resize(g0 + E);
@@ -478,9 +501,12 @@ hs_status build_plan(hs_ctx* c) {
                     gu.split = sp;
                     gu.nsplit = nsplit;
                     gu.partial = (int32_t)npartial;
-                    const int64_t a = (sp * E) / nsplit, b = ((sp + 1) * E) / nsplit;
-                    gu.g0 = (int32_t)(g0 + a);
-                    gu.gn = (int32_t)(b - a);
+                    for (int b = 0; b < GR_BANDS; ++b) {
+                        const int64_t len = bpos[b + 1] - bpos[b];
+                        const int64_t a = (sp * len) / nsplit, e = ((sp + 1) * len) / nsplit;
+                        gu.bs[b] = (int32_t)(g0 + bpos[b] + a);
+                        gu.bn[b] = (int32_t)(e - a);
+                    }
                     c->gunits.push_back(gu);
                 }
                 if (nsplit > 1) {

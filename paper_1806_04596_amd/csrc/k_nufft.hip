@@ -536,23 +536,23 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ uprec,
     const cplx<T>* __restrict__ yv, const int32_t* __restrict__ vbin, cplx<T>* __restrict__ v,
-    double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x, KBPoly<T> kb) {
+    const int32_t* __restrict__ chunk_run, double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x,
+    KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
-    __shared__ double s0[DEG_THREADS], s1[DEG_THREADS];
-    __shared__ int sb[DEG_THREADS], sh[DEG_THREADS], sf[DEG_THREADS];
     const DegridUnit u = units[blockIdx.x];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + TT, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
-    const int tid = threadIdx.x;
-    int run_off = u.run_base;
-    for (int b0 = 0; b0 < u.count; b0 += DEG_THREADS) {
-        const int i = b0 + tid;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // lanes <= this one
+    // chunk j of the unit (DEG_CHUNK visibilities) is walked by wave j mod 4
+    for (int j = wave; j * DEG_CHUNK < u.count; j += DEG_THREADS / DEG_CHUNK) {
+        const int i = j * DEG_CHUNK + lane;
         const bool act = i < u.count;
         double a0 = 0.0, a1 = 0.0;
-        int bin = -1 - tid;  // unique for inactive lanes
+        int bin = -1;
         if (act) {
             const int pos = u.start + i;
             const int cc = cell[pos];
@@ -573,46 +573,24 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
             a1 = (double)r.re * (double)r.re + (double)r.im * (double)r.im;
             bin = vbin[pos];
         }
-        s0[tid] = a0;
-        s1[tid] = a1;
-        sb[tid] = bin;
-        __syncthreads();
-        const int flag = (tid == 0 || sb[tid - 1] != bin) ? 1 : 0;
-        sh[tid] = flag ? tid : 0;   // segment head (max-scan)
-        sf[tid] = flag;             // run count (sum-scan)
-        __syncthreads();
-        for (int off = 1; off < DEG_THREADS; off <<= 1) {
-            int hh = sh[tid], ff = sf[tid];
-            if (tid >= off) {
-                hh = max(hh, sh[tid - off]);
-                ff += sf[tid - off];
+        // runs of equal bin within the chunk: segmented inclusive sums by shuffles
+        const int bprev = __shfl_up(bin, 1);
+        const unsigned long long heads = __ballot(act && (lane == 0 || bin != bprev));
+        const int head = 63 - __builtin_clzll(heads & le);   // first lane of this lane's run
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double y0 = __shfl_up(a0, off), y1 = __shfl_up(a1, off);
+            if (lane - off >= head) {
+                a0 += y0;
+                a1 += y1;
             }
-            __syncthreads();
-            sh[tid] = hh;
-            sf[tid] = ff;
-            __syncthreads();
         }
-        const int head = sh[tid];
-        for (int off = 1; off < DEG_THREADS; off <<= 1) {
-            double x0 = s0[tid], x1 = s1[tid];
-            if (tid - off >= head) {
-                x0 += s0[tid - off];
-                x1 += s1[tid - off];
-            }
-            __syncthreads();
-            s0[tid] = x0;
-            s1[tid] = x1;
-            __syncthreads();
+        const bool last = lane == 63 || !act || ((heads >> (lane + 1)) & 1ull) || (i + 1 >= u.count);
+        if (act && last) {
+            const int slot = chunk_run[u.chunk0 + j] + __popcll(heads & le) - 1;
+            run_sum[2 * (size_t)slot] = a0;
+            run_sum[2 * (size_t)slot + 1] = a1;
         }
-        const int nact = min(DEG_THREADS, u.count - b0);
-        const bool tail = act && (tid == nact - 1 || sb[tid + 1] != bin);
-        if (tail) {
-            const int slot = run_off + sf[tid] - 1;
-            run_sum[2 * (size_t)slot] = s0[tid];
-            run_sum[2 * (size_t)slot + 1] = s1[tid];
-        }
-        run_off += sf[nact - 1];
-        __syncthreads();
     }
 }
 
@@ -740,6 +718,11 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 // footprint lands in it without a bounds test; the apron is discarded (the
 // neighbouring tiles grid those cells themselves).  No atomics; the summation
 // order is fixed by the list.
+// Each wave waits on its run-start reads, so three waves share one tile: the
+// plan cuts the tile's sorted list into five bands of first-tap rows; bands
+// 0, 2, 4 are gridded by waves 0, 1, 2 at once, then bands 1 and 3 by waves
+// 0 and 1.  The footprints of one pass never share an accumulator row, so the
+// waves never touch the same cell at the same time.
 // Entries come in batches of 64: lane i stages the 8 + 8 kernel values, the
 // value and the accumulator offset of entry i; a ballot marks where runs
 // start; the walk over the batch is unrolled, so every LDS address in it is an
@@ -773,30 +756,31 @@ __device__ __forceinline__ void grid_fetch(GridFetch<T>& g, int pos, const int32
     }
 }
 
+// Orders this wave's LDS accesses around a wave-local exchange (the LDS
+// operations of one wave complete in issue order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave grids the n entries gl[0 .. n) of a band into the accumulator.
 template <typename T>
-__global__ __launch_bounds__(64) void k_grid_pull(
-    const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
-    const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
-    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int TT, int gtiles_x,
-    KBPoly<T> kb) {
-    extern __shared__ unsigned char smem_raw[];
-    const int TS = grid_stride(TT), TA = TT + 2 * GR_APRON;
-    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TA][TS]: rows/cols -7 .. T+6
-    cplx<T>* vv = acc + TA * TS;                                   // [64]
-    T* wts = reinterpret_cast<T*>(vv + 64);                        // [64][GW]
-    const GridUnit u = units[blockIdx.x];
-    const int lane = threadIdx.x, jx = lane & 7, jy = lane >> 3, lane_off = jy * TS + jx;
-    const int32_t* gl = glist + u.g0;
-    const int n = u.gn;
+__device__ __forceinline__ void grid_band(cplx<T>* __restrict__ acc, cplx<T>* __restrict__ vv, T* __restrict__ wts,
+                                          const int32_t* __restrict__ gl, int n, const int32_t* __restrict__ cell,
+                                          const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals,
+                                          const T* __restrict__ weight, int ox, int oy, int Ky, int TT,
+                                          const KBPoly<T>& kb, int lane) {
+    if (n <= 0) return;
+    const int TS = grid_stride(TT);
+    const int jx = lane & 7, jy = lane >> 3, lane_off = jy * TS + jx;
     // global loads run one batch ahead (entry data) and two batches ahead (list positions)
     const int pos0 = lane < n ? gl[lane] : -1;
     int posn = 64 + lane < n ? gl[64 + lane] : -1;
     GridFetch<T> nxt;
     grid_fetch<T>(nxt, pos0, cell, frac, vals, weight);
-    for (int e = lane; e < TA * TS; e += 64) acc[e] = {T(0), T(0)};
-    const int ox = (u.tile % gtiles_x - 1) * TT, oy = (u.tile / gtiles_x) * TT;   // ox = -T for the margin tile
     // key of an entry: accumulator offset of its first tap (a bijection with the
-    // first-tap cell); before the first entry the open "run" adds zeros at 0
+    // first-tap cell).  The first run's cells are read when the band starts.
     int prev = -1, slot = lane_off;
     cplx<T> racc{T(0), T(0)}, old{T(0), T(0)};
     for (int base = 0; base < n; base += 64) {
@@ -827,12 +811,17 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             for (int j = 0; j < 16; ++j) wv[j] = T(0);
             vv[lane] = {T(0), T(0)};
         }
+        if (base == 0) {
+            prev = __shfl(key, 0);
+            slot = prev + lane_off;
+            old = acc[slot];
+        }
         // a run starts where the key changes (the previous batch's last key carries over)
         int before = __shfl_up(key, 1);
         if (lane == 0) before = prev;
         const unsigned long long starts = __ballot(e < n && key != before);
         prev = __shfl(key, 63);
-        __syncthreads();
+        wave_lds_sync();
         // walk the batch; entry v + 1's staged values are loaded while entry v is added
         T wxn = wts[jx], wyn = wts[8 + jy];
         cplx<T> valn = vv[0];
@@ -855,19 +844,47 @@ __global__ __launch_bounds__(64) void k_grid_pull(
             racc.re += w * val.re;
             racc.im += w * val.im;
         }
-        __syncthreads();
+        wave_lds_sync();
     }
     acc[slot] = {old.re + racc.re, old.im + racc.im};
+}
+
+// Three waves share the tile accumulator: bands 0, 2, 4 first, then 1, 3.
+constexpr int GR_WAVES = 3;
+
+template <typename T>
+__global__ __launch_bounds__(64 * GR_WAVES) void k_grid_pull(
+    const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
+    const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int TT, int gtiles_x,
+    KBPoly<T> kb) {
+    extern __shared__ unsigned char smem_raw[];
+    const int TS = grid_stride(TT), TA = TT + 2 * GR_APRON;
+    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TA][TS]: rows/cols -7 .. T+6
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    cplx<T>* vv = acc + TA * TS + w * 64;                          // [64] per wave
+    T* wts = reinterpret_cast<T*>(acc + TA * TS + GR_WAVES * 64) + w * 64 * GW;   // [64][GW] per wave
+    const GridUnit* up = units + blockIdx.x;
+    const int l = up->l, tile = up->tile;
+    const int ox = (tile % gtiles_x - 1) * TT, oy = (tile / gtiles_x) * TT;   // ox = -T for the margin tile
+    for (int e = threadIdx.x; e < TA * TS; e += 64 * GR_WAVES) acc[e] = {T(0), T(0)};
     __syncthreads();
-    if (u.nsplit == 1) {
-        cplx<T>* g = grid + (size_t)u.l * Ky * Wg + TT;   // column of kx = 0
-        for (int e = lane; e < TT * TT; e += 64) {
+    grid_band<T>(acc, vv, wts, glist + up->bs[2 * w], up->bn[2 * w], cell, frac, vals, weight, ox, oy, Ky, TT, kb,
+                 lane);
+    __syncthreads();
+    if (w < 2)
+        grid_band<T>(acc, vv, wts, glist + up->bs[2 * w + 1], up->bn[2 * w + 1], cell, frac, vals, weight, ox, oy,
+                     Ky, TT, kb, lane);
+    __syncthreads();
+    if (up->nsplit == 1) {
+        cplx<T>* g = grid + (size_t)l * Ky * Wg + TT;   // column of kx = 0
+        for (int e = threadIdx.x; e < TT * TT; e += 64 * GR_WAVES) {
             const int ry = e / TT, rx = e - ry * TT;
             g[(size_t)(oy + ry) * Wg + ox + rx] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
         }
     } else {
-        cplx<T>* p = partial + (size_t)(u.partial + u.split) * TT * TT;
-        for (int e = lane; e < TT * TT; e += 64) {
+        cplx<T>* p = partial + (size_t)(up->partial + up->split) * TT * TT;
+        for (int e = threadIdx.x; e < TT * TT; e += 64 * GR_WAVES) {
             const int ry = e / TT, rx = e - ry * TT;
             p[e] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
         }
@@ -1022,7 +1039,7 @@ void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v) {
     k_degrid_dual<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
-        c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+        c->d.chunk_run, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
 }
 
 template <typename T>
@@ -1045,9 +1062,9 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
 
 template <typename T>
 void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    const size_t lds = (size_t)(c->T + 2 * GR_APRON) * grid_stride(c->T) * sizeof(cplx<T>) + 64 * sizeof(cplx<T>) +
-                       64 * GW * sizeof(T);
-    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, lds, c->stream>>>(
+    const size_t lds = (size_t)(c->T + 2 * GR_APRON) * grid_stride(c->T) * sizeof(cplx<T>) +
+                       GR_WAVES * 64 * (sizeof(cplx<T>) + GW * sizeof(T));
+    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64 * GR_WAVES, lds, c->stream>>>(
         c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
         (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->T, c->gtiles_x, kbpoly<T>(c));
     if (!c->splits.empty())
