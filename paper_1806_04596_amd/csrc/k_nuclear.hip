@@ -19,29 +19,47 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GR_SLAB = 64;   // pixels per LDS slab
 
-template <typename T>
+template <typename T, bool HAS2>
 __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* __restrict__ Xt,
                                               double* __restrict__ part, int L, int64_t N, int64_t chunk) {
     __shared__ double S[MAX_L][GR_SLAB + 2];
+    constexpr int PER = MAX_L * GR_SLAB / 256;   // staged values per thread and slab
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t p_begin = (int64_t)blockIdx.x * chunk;
     const int64_t p_end = min(N, p_begin + chunk);
     double4_t acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int64_t p0 = p_begin; p0 < p_end; p0 += GR_SLAB) {
-        for (int e = tid; e < MAX_L * GR_SLAB; e += 256) {
+    // slab values for this thread: channel e / GR_SLAB, pixel e mod GR_SLAB, e = tid + 256 k;
+    // the next slab is loaded into registers while the current one is multiplied.
+    // Loads are unconditional (clamped indices, padding zeroed after the load) so
+    // that they are all in flight together.
+    T nv[PER], nv2[PER];
+    bool nin[PER];
+    auto load = [&](int64_t p0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
             const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
             const int64_t pix = p0 + pp;
-            double v = 0.0;
-            if (ch < L && pix < p_end) {
-                T z = P[(size_t)ch * N + pix];
-                if (Xt) z += Xt[(size_t)ch * N + pix];
-                v = (double)z;
-            }
-            S[ch][pp] = v;
+            nin[k] = ch < L && pix < p_end;
+            const size_t idx = (size_t)min(ch, L - 1) * N + (size_t)min(pix, p_end - 1);
+            nv[k] = P[idx];
+            if (HAS2) nv2[k] = Xt[idx];
+        }
+    };
+    load(p_begin);
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += GR_SLAB) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            T z = nv[k];
+            if (HAS2) z += nv2[k];
+            S[ch][pp] = nin[k] ? (double)z : 0.0;
         }
         __syncthreads();
+        if (p0 + GR_SLAB < p_end) load(p0 + GR_SLAB);
         const int i = lane & 15, kq = lane >> 4;
 #pragma unroll 4
         for (int kk = 0; kk < GR_SLAB; kk += 4) {
@@ -68,18 +86,23 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* 
     }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, double* __restrict__ C, int nparts) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= MAX_L * MAX_L) return;
-    // eight independent partial sums (fixed assignment), then a fixed combine
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int k = 0;
-    for (; k + 8 <= nparts; k += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) s[j] += part[(size_t)(k + j) * MAX_L * MAX_L + e];
+// C[e] = sum of the partial Grams in a fixed order: 8 interleaved groups of
+// partials (group g takes partials g, g + 8, ...), then a fixed combine.
+constexpr int GRR_E = 32;   // Gram entries per reduction work-group
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, double* __restrict__ C,
+                                                     int nparts) {
+    __shared__ double sg[8][GRR_E];
+    const int el = threadIdx.x % GRR_E, g = threadIdx.x / GRR_E;
+    const int e = blockIdx.x * GRR_E + el;
+    double a = 0.0;
+    if (e < MAX_L * MAX_L) {
+#pragma unroll 8
+        for (int k = g; k < nparts; k += 8) a += part[(size_t)k * MAX_L * MAX_L + e];
     }
-    for (; k < nparts; ++k) s[k & 7] += part[(size_t)k * MAX_L * MAX_L + e];
-    C[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    sg[g][el] = a;
+    __syncthreads();
+    if (g == 0 && e < MAX_L * MAX_L)
+        C[e] = ((sg[0][el] + sg[1][el]) + (sg[2][el] + sg[3][el])) + ((sg[4][el] + sg[5][el]) + (sg[6][el] + sg[7][el]));
 }
 
 // ------------------------------------------------------------------ Jacobi
@@ -261,31 +284,81 @@ __global__ __launch_bounds__(256) void k_eig(const double* __restrict__ Cg, doub
     }
 }
 
-// out[b][p] = sum_a Z[a][p] W[a][b], Z = in1 + in2 (in2 may be null).
+typedef float float4_t __attribute__((ext_vector_type(4)));
+template <typename T> struct Acc16;
+template <> struct Acc16<float> { typedef float4_t type; };
+template <> struct Acc16<double> { typedef double4_t type; };
+__device__ __forceinline__ float4_t mfma16x16x4(float a, float b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double4_t mfma16x16x4(double a, double b, double4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row of the 16 x 16 result held in element r of this lane (its column is
+// lane & 15): f32 puts rows 4 (lane >> 4) + r in a lane, f64 rows (lane >> 4) + 4 r.
 template <typename T>
-__global__ __launch_bounds__(256) void k_backproject(const T* __restrict__ in1, const T* __restrict__ in2,
-                                                     const T* __restrict__ Wg, T* __restrict__ out, int L,
-                                                     int64_t N) {
-    __shared__ T W[MAX_L * MAX_L];
-    for (int e = threadIdx.x; e < MAX_L * MAX_L; e += blockDim.x) W[e] = Wg[e];
-    __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    T z[MAX_L];
+__device__ __forceinline__ int mfma16_row(int lane, int r) {
+    return sizeof(T) == 4 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
+}
+
+// out[b][p] = sum_a W[a][b] Z[a][p], Z = in1 + in2 (in2 may be null): the
+// product W^T Z on the matrix cores.  A wave owns 16-pixel column tiles of Z;
+// its W^T fragments (b = 16 bb + (lane & 15), a = 4 s + (lane >> 4)) stay in
+// registers for all its tiles, Z fragments come straight from memory (the next
+// tile's while the current one is multiplied).  W is zero beyond L, so padded
+// channels (clamped loads of channel L - 1) add nothing.  out may alias in1: a
+// wave reads every channel of a tile before writing it.
+constexpr int BP_WAVES = 2048;
+template <typename T, bool HAS2>
+__global__ __launch_bounds__(256) void k_backproject(const T* in1, const T* __restrict__ in2,
+                                                     const T* __restrict__ Wg, T* out, int L, int64_t N) {
+    typedef typename Acc16<T>::type acc_t;
+    constexpr bool PREF = sizeof(T) == 4;          // register budget allows prefetch in FP32
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6), nw = gridDim.x * 4;
+    const int il = lane & 15, kq = lane >> 4;
+    T A[4][MAX_L / 4];
 #pragma unroll
-    for (int a = 0; a < MAX_L; ++a) {
-        if (a < L) {
-            T v = in1[(size_t)a * N + p];
-            if (in2) v += in2[(size_t)a * N + p];
-            z[a] = v;
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int st = 0; st < MAX_L / 4; ++st) A[bb][st] = Wg[(4 * st + kq) * MAX_L + 16 * bb + il];
+    const int64_t nt = (N + 15) / 16;
+    T B[MAX_L / 4], B2[MAX_L / 4];
+    auto load = [&](int64_t t) {
+        const int64_t p = t * 16 + il;
+        const int64_t pc = p < N ? p : N - 1;
+#pragma unroll
+        for (int st = 0; st < MAX_L / 4; ++st) {
+            const int a = 4 * st + kq;
+            const size_t idx = (size_t)(a < L ? a : L - 1) * N + (size_t)pc;
+            B[st] = in1[idx];
+            if (HAS2) B2[st] = in2[idx];
         }
-    }
-    for (int b = 0; b < L; ++b) {
-        T s = T(0);
+    };
+    if (gw < nt) load(gw);
+    for (int64_t t = gw; t < nt; t += nw) {
+        T Z[MAX_L / 4];
 #pragma unroll
-        for (int a = 0; a < MAX_L; ++a)
-            if (a < L) s += z[a] * W[a * MAX_L + b];
-        out[(size_t)b * N + p] = s;
+        for (int st = 0; st < MAX_L / 4; ++st) Z[st] = HAS2 ? B[st] + B2[st] : B[st];
+        if (PREF && t + nw < nt) load(t + nw);
+        acc_t acc[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[bb] = acc_t{};
+#pragma unroll
+        for (int st = 0; st < MAX_L / 4; ++st)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[bb] = mfma16x16x4(A[bb][st], Z[st], acc[bb]);
+        const int64_t p = t * 16 + il;
+        if (p < N) {
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int b = 16 * bb + mfma16_row<T>(lane, r);
+                    if (b < L) out[(size_t)b * N + p] = acc[bb][r];
+                }
+        }
+        if (!PREF && t + nw < nt) load(t + nw);
     }
 }
 
@@ -302,8 +375,9 @@ void launch_gram(hs_ctx* c, const T* P, const T* Xt) {
     int64_t chunk = (c->N + NGRAM - 1) / NGRAM;
     chunk = (chunk + GR_SLAB - 1) / GR_SLAB * GR_SLAB;
     const int nparts = (int)((c->N + chunk - 1) / chunk);
-    k_gram<T><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
-    k_gram_reduce<<<(MAX_L * MAX_L + 255) / 256, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
+    if (Xt) k_gram<T, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    else k_gram<T, false><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
 }
 
 void launch_eig(hs_ctx* c, int mode) {
@@ -318,8 +392,10 @@ void launch_eig(hs_ctx* c, int mode) {
 
 template <typename T>
 void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2) {
-    k_backproject<T><<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L,
-                                                                           c->N);
+    const int64_t nt = (c->N + 15) / 16;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(BP_WAVES, nt) / 4);
+    if (in2) k_backproject<T, true><<<nb, 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L, c->N);
+    else k_backproject<T, false><<<nb, 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L, c->N);
 }
 
 template void launch_gram<float>(hs_ctx*, const float*, const float*);
