@@ -33,24 +33,59 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
 // Steps 20-23: G = k1 P + k2 At + k3 D (P or At null: that prior is off);
 // X <- max(X - tau G, 0); Xt <- 2X_new - X_old;
 // FP64 partial sums of ||X_new - X_old||^2 and ||X_new||^2 per block (fixed grid).
+// 16 bytes of T.
 template <typename T>
+struct Vec16 {
+    T v[16 / sizeof(T)];
+};
+
+template <typename T, bool HAS_P, bool HAS_AT>
 __global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict__ Xt, const T* __restrict__ P,
                                                 const T* __restrict__ At, const T* __restrict__ D, T k1, T k2, T k3,
                                                 T tau, int64_t n, double* __restrict__ part) {
+    // n is a multiple of 16 / sizeof(T): every operand is read and written in
+    // 16-byte vectors, two per array in flight per thread and step
+    constexpr int V = 16 / sizeof(T), U = 2;
     __shared__ double sh[4];
     double dd = 0.0, xx = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T g = k3 * D[i];
-        if (P) g += k1 * P[i];
-        if (At) g += k2 * At[i];
-        const T xo = X[i];
-        T xn = xo - tau * g;
-        xn = xn > T(0) ? xn : T(0);
-        X[i] = xn;
-        Xt[i] = T(2) * xn - xo;
-        const double df = (double)xn - (double)xo;
-        dd += df * df;
-        xx += (double)xn * (double)xn;
+    const int64_t nv = n / V;
+    const Vec16<T>* Dv = reinterpret_cast<const Vec16<T>*>(D);
+    const Vec16<T>* Pv = reinterpret_cast<const Vec16<T>*>(P);
+    const Vec16<T>* Av = reinterpret_cast<const Vec16<T>*>(At);
+    Vec16<T>* Xv = reinterpret_cast<Vec16<T>*>(X);
+    Vec16<T>* Xtv = reinterpret_cast<Vec16<T>*>(Xt);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nv; i0 += U * stride) {
+        Vec16<T> d[U], pp[U], aa[U], xo[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride < nv ? i0 + u * stride : i0;
+            d[u] = Dv[i];
+            if (HAS_P) pp[u] = Pv[i];
+            if (HAS_AT) aa[u] = Av[i];
+            xo[u] = Xv[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * stride >= nv) break;
+            Vec16<T> xn, xt;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                T g = k3 * d[u].v[k];
+                if (HAS_P) g += k1 * pp[u].v[k];
+                if (HAS_AT) g += k2 * aa[u].v[k];
+                const T x0 = xo[u].v[k];
+                T x1 = x0 - tau * g;
+                x1 = x1 > T(0) ? x1 : T(0);
+                xn.v[k] = x1;
+                xt.v[k] = T(2) * x1 - x0;
+                const double df = (double)x1 - (double)x0;
+                dd += df * df;
+                xx += (double)x1 * (double)x1;
+            }
+            Xv[i0 + u * stride] = xn;
+            Xtv[i0 + u * stride] = xt;
+        }
     }
     dd = block_sum_256(dd, sh);
     xx = block_sum_256(xx, sh);
@@ -195,9 +230,15 @@ void launch_primal(hs_ctx* c, const T* Atsum, const T* Dimg, bool use_p) {
     const int64_t n = (int64_t)c->L * c->N;
     int grid = (int)std::min<int64_t>(NRED, (n + 255) / 256);
     if (grid < 1) grid = 1;
-    k_primal<T><<<grid, 256, 0, c->stream>>>((T*)c->d.X, (T*)c->d.Xt, use_p ? (const T*)c->d.P : nullptr, Atsum,
-                                              Dimg, (T)c->k1,
-                                              (T)c->k2, (T)c->k3, (T)c->tau, n, c->d.red_part);
+    const T* P = use_p ? (const T*)c->d.P : nullptr;
+#define HS_PRIMAL(HP, HA)                                                                                         \
+    k_primal<T, HP, HA><<<grid, 256, 0, c->stream>>>((T*)c->d.X, (T*)c->d.Xt, P, Atsum, Dimg, (T)c->k1, (T)c->k2, \
+                                                     (T)c->k3, (T)c->tau, n, c->d.red_part)
+    if (P && Atsum) HS_PRIMAL(true, true);
+    else if (P) HS_PRIMAL(true, false);
+    else if (Atsum) HS_PRIMAL(false, true);
+    else HS_PRIMAL(false, false);
+#undef HS_PRIMAL
     k_finish_beta<<<1, 64, 0, c->stream>>>(c->d.red_part, c->d.scal, grid);
 }
 

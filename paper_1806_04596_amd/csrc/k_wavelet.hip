@@ -328,32 +328,38 @@ __global__ void k_psi_sum(const T* __restrict__ Y, const T* __restrict__ C0, T* 
 //  mode 1 (prox, eq:prox-L21): Z = A, A <- Z max(||Z|| - thr*wbar, 0)/||Z||;
 //  mode 2 (dual of the per-channel weighted l1 of the SARA variant, eq:min-sara):
 //         Z = A + Psi_d^dag Xt, A <- clip(Z, -thr*wbar, thr*wbar) element by element.
-template <typename T>
+template <typename T, bool HAS_S>
 __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restrict__ Xt, const T* __restrict__ coef,
                       const T* __restrict__ wbar, double thr, int L, int64_t N, int mode) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int d = blockIdx.y;
     T* Ad = A + (size_t)d * L * N + p;
-    const T* Sd = (mode != 1) ? ((d == 0) ? Xt + p : coef + (size_t)(d - 1) * L * N + p) : nullptr;
+    const T* Sd = HAS_S ? ((d == 0) ? Xt + p : coef + (size_t)(d - 1) * L * N + p) : nullptr;
     if (mode == 2) {
         // SARA variant: weighted l1 per channel, Z - soft(Z) = clip(Z, -t, t) element by element
         const T t = (T)(thr * (wbar ? (double)wbar[(size_t)d * N + p] : 1.0));
         for (int l = 0; l < L; ++l) {
-            const T v = Ad[(size_t)l * N] + Sd[(size_t)l * N];
+            const T v = Ad[(size_t)l * N] + (HAS_S ? Sd[(size_t)l * N] : T(0));
             Ad[(size_t)l * N] = v > t ? t : (v < -t ? -t : v);
         }
         return;
     }
-    T z[MAX_L];
+    // every channel's loads are issued together (clamped channel index; channels
+    // >= L are never used), then the row norm and the shrink
+    T z[MAX_L], z2[MAX_L];
+#pragma unroll
+    for (int l = 0; l < MAX_L; ++l) {
+        const size_t o = (size_t)(l < L ? l : L - 1) * N;
+        z[l] = Ad[o];
+        if (HAS_S) z2[l] = Sd[o];
+    }
     double n2 = 0.0;
 #pragma unroll
     for (int l = 0; l < MAX_L; ++l) {
         if (l < L) {
-            T v = Ad[(size_t)l * N];
-            if (Sd) v += Sd[(size_t)l * N];
-            z[l] = v;
-            n2 += (double)v * (double)v;
+            if (HAS_S) z[l] += z2[l];
+            n2 += (double)z[l] * (double)z[l];
         }
     }
     const double nrm = sqrt(n2);
@@ -419,7 +425,8 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout) {
 template <typename T>
 void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T* coef, const T* wbar, double thr, int mode) {
     dim3 g(nblk(c->N, 256), c->D);
-    k_l21<T><<<g, 256, 0, c->stream>>>(A, Xt, coef, wbar, thr, c->L, c->N, mode);
+    if (mode != 1) k_l21<T, true><<<g, 256, 0, c->stream>>>(A, Xt, coef, wbar, thr, c->L, c->N, mode);
+    else k_l21<T, false><<<g, 256, 0, c->stream>>>(A, Xt, coef, wbar, thr, c->L, c->N, mode);
 }
 
 #define HS_INST(T)                                                                   \
