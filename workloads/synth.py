@@ -36,6 +36,8 @@ class WorkloadConfig:
     n_blocks: int
     isnr_db: float
     seed: int
+    n_lines: int = 0       # emission lines added to each source spectrum (own random stream)
+    src_sigma: tuple = (1.0, 3.0)   # range of the Gaussian source widths (pixels)
 
     @property
     def N(self) -> int:
@@ -75,7 +77,7 @@ def make_sky(cfg: WorkloadConfig) -> np.ndarray:
     nu = cfg.freqs() / cfg.f_lo
     cy = cfg.ny / 2 + rng.uniform(-0.4, 0.4, cfg.n_src) * cfg.ny
     cx = cfg.nx / 2 + rng.uniform(-0.4, 0.4, cfg.n_src) * cfg.nx
-    sig = rng.uniform(1.0, 3.0, cfg.n_src)
+    sig = rng.uniform(cfg.src_sigma[0], cfg.src_sigma[1], cfg.n_src)
     peak = 10.0 ** rng.uniform(-3.0, 0.0, cfg.n_src)
     alpha = rng.normal(-0.7, 0.2, cfg.n_src)
     curv = rng.normal(0.0, 0.1, cfg.n_src) if cfg.curved else np.zeros(cfg.n_src)
@@ -85,6 +87,16 @@ def make_sky(cfg: WorkloadConfig) -> np.ndarray:
     for q in range(cfg.n_src):
         S[q] = peak[q] * np.exp(-((yy - cy[q]) ** 2 + (xx - cx[q]) ** 2) / (2 * sig[q] ** 2))
     H = nu[:, None] ** (alpha[None, :] + curv[None, :] * np.log(nu)[:, None])  # [L][Q]
+    if cfg.n_lines > 0:
+        # Gaussian emission lines on the continua (Sec. 4.1 adds lines of varied
+        # positions and amplitudes); drawn from a stream of their own
+        rl = _rng(cfg.seed, 6)
+        ch = np.arange(cfg.L)[:, None]
+        for q in range(cfg.n_src):
+            pos = rl.uniform(0, cfg.L - 1, cfg.n_lines)
+            amp = rl.uniform(0.2, 1.0, cfg.n_lines) * H[:, q].max()
+            wid = rl.uniform(0.5, 2.0, cfg.n_lines)
+            H[:, q] += (amp[None, :] * np.exp(-0.5 * ((ch - pos[None, :]) / wid[None, :]) ** 2)).sum(axis=1)
     X = np.tensordot(H, S, axes=(1, 0))
     return np.ascontiguousarray(X)
 
