@@ -53,7 +53,7 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.gunits, c->gunits.size() * sizeof(GridUnit), base);
     k.take(d.splits, c->splits.size() * sizeof(SplitTile), base);
     k.take(d.glist, c->h_glist.size() * 4, base);
-    k.take(d.gpartial, (size_t)c->npartial * c->T * c->T * cx, base);
+    k.take(d.gpartial, (size_t)c->npartial * GB * GB * cx, base);
     k.take(d.bin_u, (size_t)c->nbins * 8, base);
     k.take(d.bin_block, (size_t)c->nbins * 4, base);
     k.take(d.blk_bin_ptr, (size_t)(c->nblk + 1) * 4, base);

@@ -16,8 +16,7 @@ constexpr int KB_MAX_TERMS = 40;    // power-series terms of the kernel (upper b
 constexpr int MAX_L = 64;           // channels (Gram matrix edge)
 constexpr int DEG_THREADS = 256;    // degridding workgroup = one batch of visibilities
 constexpr int DEG_BATCHES = 4;      // batches per degridding work unit
-constexpr int GRID_SPLIT = 2048;    // pull elements per gridding work unit
-constexpr int N_GRANGES = 13;       // visibility ranges feeding one tile core
+constexpr int GRID_SPLIT = 1024;    // entries per gridding work unit
 constexpr int MAX_DB = 8;
 constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
 
@@ -35,15 +34,17 @@ struct DegridUnit {
 // `tile` of channel l (its own visibilities and its neighbours' border ones, by
 // first-tap cell), part `split` of `nsplit`.  nsplit > 1 writes a partial tile
 // to slot partial + split; nsplit == 1 writes the grid directly.
-// One gridding work-group: a tile (or one split part of it) whose entries are
-// cut into GR_BANDS row bands of first-tap rows; bands 0, 2, 4 are gridded
-// together by the three waves, then bands 1, 3 (their footprints never share
-// a core cell with another band of the same pass).
-constexpr int GR_BANDS = 5;
+// Gridding works on GB x GB output blocks of the half-plane grid; the grid rows
+// carry GR_MARGIN cells beyond kx = 0 and kx = Kx/2 (column = kx + GR_MARGIN).
+constexpr int GB = 16;
+constexpr int GR_MARGIN = 32;
+// One gridding work unit: entries [g0, g0 + gn) of the entry list of output
+// block `tile` of channel l (every visibility whose footprint meets the block),
+// part `split` of `nsplit`.  nsplit > 1 writes a partial block to slot
+// partial + split; nsplit == 1 writes the grid directly.
 struct GridUnit {
     int32_t l, tile, split, nsplit;
-    int32_t partial, pad;
-    int32_t bs[GR_BANDS], bn[GR_BANDS];   // glist start and length of each band
+    int32_t partial, g0, gn, pad;
 };
 
 // A tile whose gridding was split: the partials are summed in order.
@@ -157,10 +158,10 @@ struct hs_ctx {
     bool planned = false, bound = false;
     // Hermitian half plane: visibilities live at kx in [0, Kx/2] (those at
     // negative kx are reflected); visibility tiles cover [0, Kx/2 + T), gridding
-    // tiles [-T, Kx/2 + T) = the Wg columns of a grid row (column = kx + T).
+    // blocks [-GB, Kx/2 + GB) of the Wg columns of a grid row (column = kx + GR_MARGIN).
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0;   // visibility tiles
-    int gtiles_x = 0, ngtiles = 0;                      // gridding tiles
-    int Kh = 0, Wh = 0, Wg = 0, Hs = 0;                 // Kx/2, Kx/2 + 1, Kx/2 + 2T, Kx/2 + 16
+    int gtiles_x = 0, ngtiles = 0;                      // gridding blocks (GB x GB) in x, in all
+    int Kh = 0, Wh = 0, Wg = 0, Hs = 0;                 // Kx/2, Kx/2 + 1, Kx/2 + 2 GR_MARGIN, Kx/2 + 16
     int64_t Mtot = 0;
     std::vector<int64_t> chan_off;     // [L+1]
     std::vector<int32_t> blk_off;      // [L+1]

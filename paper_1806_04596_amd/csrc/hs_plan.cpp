@@ -291,42 +291,6 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
     }
 }
 
-// The source ranges feeding the core of gridding tile (gtx, tyi) (origin
-// ((gtx - 1) T, tyi T)): the visibility tile with the same origin and the
-// border regions of its neighbours whose kernel footprints reach into it.
-// Periodic in y; in x the half plane has no wrap (the margins beyond kx = 0
-// and kx = Kx/2 are folded after gridding).  Empty ranges fill the rest.
-static void tile_ranges(const std::vector<int64_t>& rp, int64_t base, int tiles_x, int tiles_y, int gtx, int tyi,
-                        int32_t* out) {
-    int k = 0;
-    auto push = [&](int64_t s, int64_t e) {
-        out[2 * k] = (int32_t)(base + s);
-        out[2 * k + 1] = (int32_t)(base + e);
-        ++k;
-    };
-    const int txi = gtx - 1;   // visibility tile of the same origin (may be -1 or tiles_x)
-    for (int dy = -1; dy <= 1; ++dy) {
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int sx = txi - dx, sy = (tyi - dy + tiles_y) % tiles_y;
-            if (sx < 0 || sx >= tiles_x) continue;
-            const int64_t t = (int64_t)sy * tiles_x + sx;
-            // source at target - (dx,dy): dx = +1 -> source right border (class 2)
-            const int rc = (dy == 1) ? 2 : 0;   // row class when dy != 0
-            const int cc = (dx == 1) ? 2 : 0;
-            if (dx == 0 && dy == 0) {
-                push(rp[t * 9], rp[t * 9 + 9]);
-            } else if (dx == 0) {
-                push(rp[t * 9 + 3 * rc], rp[t * 9 + 3 * rc + 3]);
-            } else if (dy == 0) {
-                for (int r = 0; r < 3; ++r) push(rp[t * 9 + 3 * r + cc], rp[t * 9 + 3 * r + cc + 1]);
-            } else {
-                push(rp[t * 9 + 3 * rc + cc], rp[t * 9 + 3 * rc + cc + 1]);
-            }
-        }
-    }
-    while (k < N_GRANGES) push(0, 0);
-}
-
 hs_status build_plan(hs_ctx* c) {
     const int L = c->L;
     for (int l = 0; l < L; ++l)
@@ -341,13 +305,13 @@ hs_status build_plan(hs_ctx* c) {
     c->T = T;
     c->Kh = c->Kx / 2;
     c->Wh = c->Kh + 1;
-    c->Wg = c->Kh + 2 * T;
+    c->Wg = c->Kh + 2 * GR_MARGIN;
     c->Hs = c->Kh + 16;
     c->tiles_x = c->Kh / T + 1;
     c->tiles_y = c->Ky / T;
     c->ntiles = c->tiles_x * c->tiles_y;
-    c->gtiles_x = c->tiles_x + 1;
-    c->ngtiles = c->gtiles_x * c->tiles_y;
+    c->gtiles_x = c->Kh / GB + 2;   // blocks cover kx in [-GB, Kx/2 + GB)
+    c->ngtiles = c->gtiles_x * (c->Ky / GB);
     // offsets
     c->chan_off.assign(L + 1, 0);
     c->blk_off.assign(L + 1, 0);
@@ -376,24 +340,6 @@ hs_status build_plan(hs_ctx* c) {
     c->gunits.clear();
     c->splits.clear();
     c->h_glist.clear();
-    std::vector<int32_t> kcount((size_t)(T + 7) * (T + 7) + 1);
-    // Row bands of a gridding tile's entries by first-tap row r in 0 .. T+6 (an
-    // entry's footprint covers accumulator rows r .. r+7).  Bands 0, 2, 4 are
-    // gridded concurrently and bands 1, 3 afterwards; bands 1 and 3 are 7 rows
-    // high, so the footprints of one pass never share a row.
-    int band_row[GR_BANDS + 1];
-    {
-        const int R = T + 7;
-        if (R - 14 >= 21) {   // three bands of >= 7 rows in the first pass
-            const int na = (R - 14) / 3;
-            const int rows[GR_BANDS + 1] = {0, na, na + 7, 2 * na + 7, 2 * na + 14, R};
-            std::copy(rows, rows + GR_BANDS + 1, band_row);
-        } else {              // two bands in the first pass, one in the second
-            const int na = (R - 7) / 2;
-            const int rows[GR_BANDS + 1] = {0, na, na + 7, R, R, R};
-            std::copy(rows, rows + GR_BANDS + 1, band_row);
-        }
-    }
     std::vector<std::pair<int32_t, int32_t>> run_bin;  // (bin, run)
     int64_t nruns = 0, npartial = 0;
     int64_t bin_base = 0;
@@ -454,46 +400,46 @@ hs_status build_plan(hs_ctx* c) {
                 c->dunits.push_back(du);
             }
         }
-        // gridding units (every tile gets at least one: empty tiles write zeros).
-        // The entries meeting a tile -- its own visibilities and the border
-        // regions of its 8 neighbours -- are listed sorted by first-tap cell
-        // relative to the tile (counting sort, stable), so that the kernel sees
-        // runs of visibilities sharing a footprint.
-        for (int tyi = 0; tyi < c->tiles_y; ++tyi) {
-            for (int gtx = 0; gtx < c->gtiles_x; ++gtx) {
-                const int t = tyi * c->gtiles_x + gtx;
-                const int ox = (gtx - 1) * T, oy = tyi * T, W7 = T + 7;
-                int32_t rg[2 * N_GRANGES];
-                tile_ranges(o.region_ptr, base, c->tiles_x, c->tiles_y, gtx, tyi, rg);
-                auto key_of = [&](int64_t g) -> int {
-                    const int32_t cl = c->h_cell[g];
-                    const int relx = (cl & 0x7FFF) - ox;
-                    int rely = (cl >> 16) - oy;
-                    if (rely < -T) rely += c->Ky;
-                    if (rely >= 2 * T) rely -= c->Ky;
-                    const int rx0 = relx - 3, ry0 = rely - 3;
-                    if (rx0 < -7 || rx0 >= T || ry0 < -7 || ry0 >= T) return -1;
-                    return (ry0 + 7) * W7 + (rx0 + 7);
-                };
-                std::fill(kcount.begin(), kcount.end(), 0);
-                int64_t E = 0;
-                for (int r = 0; r < N_GRANGES; ++r)
-                    for (int64_t g = rg[2 * r]; g < rg[2 * r + 1]; ++g) {
-                        const int k = key_of(g);
-                        if (k < 0) return fail(c, HS_ERR_INVALID_ARG, "hs_plan: internal error in tile ranges");
-                        ++kcount[k + 1];
-                        ++E;
-                    }
-                for (int k = 0; k < W7 * W7; ++k) kcount[k + 1] += kcount[k];
-                // band boundaries (positions in the sorted list) from the first-tap rows
-                int64_t bpos[GR_BANDS + 1];
-                for (int b = 0; b <= GR_BANDS; ++b) bpos[b] = kcount[band_row[b] * W7];
-                const int64_t g0 = (int64_t)c->h_glist.size();
-                if (g0 + E > INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: too many gridding entries");
-                c->h_glist.resize(g0 + E);
-                for (int r = 0; r < N_GRANGES; ++r)
-                    for (int64_t g = rg[2 * r]; g < rg[2 * r + 1]; ++g) c->h_glist[g0 + kcount[key_of(g)]++] = (int32_t)g;
-                const int nsplit = (int)std::max<int64_t>(1, (E + GRID_SPLIT - 1) / GRID_SPLIT);
+        // gridding units (every block gets at least one: empty blocks write
+        // zeros).  Every visibility is listed by each GB x GB block its 8 x 8
+        // footprint meets (one to four; periodic in y), in plan order (stable
+        // counting sort by block).
+        {
+            const int nbx = c->gtiles_x, nby = c->Ky / GB, Ky = c->Ky;
+            auto blocks_of = [&](int64_t g, int32_t* out) -> int {
+                const int32_t cl = c->h_cell[g];
+                const int x0 = (cl & 0x7FFF) - 3 + GB;   // first tap, in block units shifted by one block
+                int ya = (cl >> 16) - 3;
+                if (ya < 0) ya += Ky;
+                int yb = ya + 7;
+                if (yb >= Ky) yb -= Ky;
+                const int bx[2] = {x0 / GB, (x0 + 7) / GB}, by[2] = {ya / GB, yb / GB};
+                int n = 0;
+                for (int i = 0; i < (by[1] != by[0] ? 2 : 1); ++i)
+                    for (int j = 0; j < (bx[1] != bx[0] ? 2 : 1); ++j) out[n++] = by[i] * nbx + bx[j];
+                return n;
+            };
+            std::vector<int64_t> bcnt((size_t)nbx * nby + 1, 0);
+            int32_t ids[4];
+            for (int64_t k = 0; k < ch.M; ++k) {
+                const int n = blocks_of(base + k, ids);
+                for (int i = 0; i < n; ++i) {
+                    if (ids[i] < 0 || ids[i] >= nbx * nby) return fail(c, HS_ERR_INVALID_ARG, "hs_plan: internal error in gridding blocks");
+                    ++bcnt[ids[i] + 1];
+                }
+            }
+            for (int b = 0; b < nbx * nby; ++b) bcnt[b + 1] += bcnt[b];
+            const int64_t g0 = (int64_t)c->h_glist.size(), E = bcnt[(size_t)nbx * nby];
+            if (g0 + E > INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: too many gridding entries");
+            c->h_glist.resize(g0 + E);
+            std::vector<int64_t> fill(bcnt.begin(), bcnt.end() - 1);
+            for (int64_t k = 0; k < ch.M; ++k) {
+                const int n = blocks_of(base + k, ids);
+                for (int i = 0; i < n; ++i) c->h_glist[g0 + fill[ids[i]]++] = (int32_t)(base + k);
+            }
+            for (int t = 0; t < nbx * nby; ++t) {
+                const int64_t s0 = bcnt[t], e0 = bcnt[t + 1], En = e0 - s0;
+                const int nsplit = (int)std::max<int64_t>(1, (En + GRID_SPLIT - 1) / GRID_SPLIT);
                 for (int sp = 0; sp < nsplit; ++sp) {
                     GridUnit gu{};
                     gu.l = l;
@@ -501,12 +447,9 @@ hs_status build_plan(hs_ctx* c) {
                     gu.split = sp;
                     gu.nsplit = nsplit;
                     gu.partial = (int32_t)npartial;
-                    for (int b = 0; b < GR_BANDS; ++b) {
-                        const int64_t len = bpos[b + 1] - bpos[b];
-                        const int64_t a = (sp * len) / nsplit, e = ((sp + 1) * len) / nsplit;
-                        gu.bs[b] = (int32_t)(g0 + bpos[b] + a);
-                        gu.bn[b] = (int32_t)(e - a);
-                    }
+                    const int64_t a = (sp * En) / nsplit, e = ((sp + 1) * En) / nsplit;
+                    gu.g0 = (int32_t)(g0 + s0 + a);
+                    gu.gn = (int32_t)(e - a);
                     c->gunits.push_back(gu);
                 }
                 if (nsplit > 1) {

@@ -13,13 +13,12 @@
 //  * G (degridding): visibilities are stored tile-major; a work unit stages the
 //    (T+8)^2 grid neighbourhood of its tile in LDS and each thread interpolates
 //    one visibility (8 + 8 kernel values, 64 taps from LDS).
-//  * G^T (gridding): "pull" form with no global atomics: one wave owns the
-//    T x T core of a tile and consumes every visibility whose footprint reaches
-//    it (its own tile plus the border regions of the 8 neighbours, 13 ranges),
-//    accumulating in LDS; each grid cell is written exactly once.  Tiles with
-//    many visibilities are split and their partial cores summed in fixed order.
-//    Gridding tiles also cover one tile-wide margin beyond kx = 0 and kx = Kx/2;
-//    the adjoint column pass folds the margins back (conjugate mirror cells).
+//  * G^T (gridding): output-stationary on the matrix cores: one wave owns a
+//    16 x 16 block of the grid and forms it as the product of the y-kernel
+//    matrix and the x-kernel-times-value matrix over the visibilities whose
+//    footprints meet the block; no atomics, each grid cell written once.
+//    Blocks also cover a 16-cell margin beyond kx = 0 and kx = Kx/2; the
+//    adjoint column pass folds the margins back (conjugate mirror cells).
 //  * Per-block FP64 sums for the ellipsoid projection are produced by a
 //    deterministic segmented scan in the degridding pass and reduced per
 //    (block, preconditioner value) bin, so the secular equation of the exact
@@ -246,7 +245,7 @@ __device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
                                                        const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
-                                                       int Hs, int Wg, int TT, int CT) {
+                                                       int Hs, int Wg, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
     const int c = xcd_pair_tile(blockIdx.x, gridDim.x) * CT + s;
     const bool live = c <= Kh;
     const cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
-    cplx<T>* Gl = G + (size_t)l * Ky * Wg + TT + c;
+    cplx<T>* Gl = G + (size_t)l * Ky * Wg + GR_MARGIN + c;
     fft_run<T, false, false>(buf, u, s, Ky, CT, tw,
         [&](int q) {
             int j = q + (ny >> 1);
@@ -276,7 +275,7 @@ constexpr int GR_FOLD = 4;
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H,
                                                        const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
-                                                       int Hs, int Wg, int TT, int CT) {
+                                                       int Hs, int Wg, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
@@ -285,7 +284,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict_
     const bool live = c <= Kh;
     const bool fold = c <= GR_FOLD || (c >= Kh - GR_FOLD && live);
     const int mx = c <= GR_FOLD ? -c : 2 * Kh - c;
-    const cplx<T>* G0 = G + (size_t)l * Ky * Wg + TT;   // kx = 0
+    const cplx<T>* G0 = G + (size_t)l * Ky * Wg + GR_MARGIN;   // kx = 0
     cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
     fft_run<T, true, false>(buf, u, s, Ky, CT, tw,
         [&](int q) {
@@ -409,7 +408,7 @@ void launch_fft_cols_fwd(hs_ctx* c, int L) {
     dim3 grid((c->Wh + ct - 1) / ct, L);
     k_fft_cols_fwd<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
         (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
-        c->T, ct);
+        ct);
 }
 template <typename T>
 void launch_fft_cols_adj(hs_ctx* c, int L) {
@@ -417,7 +416,7 @@ void launch_fft_cols_adj(hs_ctx* c, int L) {
     dim3 grid((c->Wh + ct - 1) / ct, L);
     k_fft_cols_adj<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
         (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
-        c->T, ct);
+        ct);
 }
 template <typename T>
 void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
@@ -511,7 +510,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
     const DegridUnit u = units[blockIdx.x];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + TT, ox, oy, TT, Kh, Ky, Wg);
+    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
     for (int i = threadIdx.x; i < u.count; i += DEG_THREADS) {
@@ -542,7 +541,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
     const DegridUnit u = units[blockIdx.x];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
-    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + TT, ox, oy, TT, Kh, Ky, Wg);
+    stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -704,56 +703,37 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ upre
 }
 
 // ---------------------------------------------------------- gridding (pull)
-// Output-stationary gridding, one wave per (tile, split) unit.  The plan lists
-// the entries meeting each tile (its own visibilities and its neighbours'
-// border ones) sorted by first-tap cell, so visibilities sharing a footprint
-// arrive in runs.  Lane (jx, jy) owns tap (jx, jy) of the current footprint:
-// within a run every lane adds phi_x(jx) phi_y(jy) val into one register; at
-// the end of a run the 64 sums are added into the tile accumulator in LDS (a
-// plain read-modify-write: the 64 taps are 64 distinct cells), whose old
-// values were read when the run started, so the write does not wait on a
-// fresh read; one wave issues its LDS operations in order, so that read sees
-// the previous run's write.  The
-// accumulator has a 7-cell apron on every side, so every tap of every listed
-// footprint lands in it without a bounds test; the apron is discarded (the
-// neighbouring tiles grid those cells themselves).  No atomics; the summation
-// order is fixed by the list.
-// Each wave waits on its run-start reads, so three waves share one tile: the
-// plan cuts the tile's sorted list into five bands of first-tap rows; bands
-// 0, 2, 4 are gridded by waves 0, 1, 2 at once, then bands 1 and 3 by waves
-// 0 and 1.  The footprints of one pass never share an accumulator row, so the
-// waves never touch the same cell at the same time.
-// Entries come in batches of 64: lane i stages the 8 + 8 kernel values, the
-// value and the accumulator offset of entry i; a ballot marks where runs
-// start; the walk over the batch is unrolled, so every LDS address in it is an
-// immediate offset.
-constexpr int GR_APRON = 7;
-constexpr int GW = 17;      // staged kernel values per entry (8 + 8, odd stride: bank-free staging)
-
-// Accumulator row stride for a T-cell tile with its aprons (no padding: the
-// smaller footprint raises occupancy by more than the bank conflicts cost).
-__host__ __device__ constexpr int grid_stride(int TT) { return TT + 2 * GR_APRON; }
-
+// Output-stationary gridding on the matrix cores.  One wave owns a GB x GB
+// (16 x 16) output block and consumes every visibility whose 8 x 8 footprint
+// meets it (the plan lists them, in plan order).  For entries e with first-tap
+// offset (dy_e, dx_e) from the block origin, kernel values wy_e, wx_e and value
+// v_e, the block is
+//     G[i][j] = sum_e wy_e(i - dy_e) wx_e(j - dx_e) v_e
+// (terms outside the footprint are zero), i.e. the product A B of the 16 x E
+// matrix A[i][e] = wy_e(i - dy_e) and the E x 16 matrix B[e][j] = wx_e(j - dx_e) v_e.
+// Each 16x16x4 MFMA takes four entries: lane (i, k) = (lane & 15, lane >> 4)
+// supplies A[i][k] and B[k][i] from the staged values of entry 4q + k; the real
+// and imaginary parts of v are two products with a shared A.  The accumulators
+// stay in registers; each grid cell is written once (no atomics, fixed order).
+// Entries come in batches of 64: lane e stages entry e's kernel values, offsets
+// and value in LDS.  Blocks with many entries are split; their partial blocks
+// are summed in fixed order.
+typedef float grid_f4 __attribute__((ext_vector_type(4)));
+typedef double grid_d4 __attribute__((ext_vector_type(4)));
+template <typename T> struct GridAcc;
+template <> struct GridAcc<float> { typedef grid_f4 type; };
+template <> struct GridAcc<double> { typedef grid_d4 type; };
+__device__ __forceinline__ grid_f4 grid_mfma(float a, float b, grid_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ grid_d4 grid_mfma(double a, double b, grid_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row of the 16 x 16 result held in element r of this lane (column lane & 15):
+// f32 puts rows 4 (lane >> 4) + r in a lane, f64 rows (lane >> 4) + 4 r.
 template <typename T>
-struct GridFetch {
-    int cc;
-    cplx<T> f, val;
-};
-
-template <typename T>
-__device__ __forceinline__ void grid_fetch(GridFetch<T>& g, int pos, const int32_t* __restrict__ cell,
-                                           const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals,
-                                           const T* __restrict__ weight) {
-    if (pos >= 0) {
-        g.cc = cell[pos];
-        g.f = frac[pos];
-        g.val = vals[pos];
-        if (weight) {
-            const T w = weight[pos];
-            g.val.re *= w;
-            g.val.im *= w;
-        }
-    }
+__device__ __forceinline__ int grid_mfma_row(int lane, int r) {
+    return sizeof(T) == 4 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
 }
 
 // Orders this wave's LDS accesses around a wave-local exchange (the LDS
@@ -764,148 +744,107 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave grids the n entries gl[0 .. n) of a band into the accumulator.
-template <typename T>
-__device__ __forceinline__ void grid_band(cplx<T>* __restrict__ acc, cplx<T>* __restrict__ vv, T* __restrict__ wts,
-                                          const int32_t* __restrict__ gl, int n, const int32_t* __restrict__ cell,
-                                          const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals,
-                                          const T* __restrict__ weight, int ox, int oy, int Ky, int TT,
-                                          const KBPoly<T>& kb, int lane) {
-    if (n <= 0) return;
-    const int TS = grid_stride(TT);
-    const int jx = lane & 7, jy = lane >> 3, lane_off = jy * TS + jx;
-    // global loads run one batch ahead (entry data) and two batches ahead (list positions)
-    const int pos0 = lane < n ? gl[lane] : -1;
-    int posn = 64 + lane < n ? gl[64 + lane] : -1;
-    GridFetch<T> nxt;
-    grid_fetch<T>(nxt, pos0, cell, frac, vals, weight);
-    // key of an entry: accumulator offset of its first tap (a bijection with the
-    // first-tap cell).  The first run's cells are read when the band starts.
-    int prev = -1, slot = lane_off;
-    cplx<T> racc{T(0), T(0)}, old{T(0), T(0)};
-    for (int base = 0; base < n; base += 64) {
-        const int e = base + lane;
-        const GridFetch<T> g = nxt;
-        if (base + 64 < n) {
-            grid_fetch<T>(nxt, posn, cell, frac, vals, weight);
-            posn = base + 128 + lane < n ? gl[base + 128 + lane] : -1;
-        }
-        int key = -1;
-        T* wv = wts + lane * GW;
-        if (e < n) {
-            const int relx = (g.cc & 0x7FFF) - ox;   // the half plane has no wrap in x
-            int rely = (g.cc >> 16) - oy;
-            if (rely < -TT) rely += Ky;
-            if (rely >= 2 * TT) rely -= Ky;
-            key = (rely - 3 + GR_APRON) * TS + (relx - 3 + GR_APRON);
-            T w8[KB_J];
-            kb_weights(g.f.re, kb, w8);
-#pragma unroll
-            for (int j = 0; j < KB_J; ++j) wv[j] = w8[j];
-            kb_weights(g.f.im, kb, w8);
-#pragma unroll
-            for (int j = 0; j < KB_J; ++j) wv[8 + j] = w8[j];
-            vv[lane] = (g.cc & 0x8000) ? cplx<T>{g.val.re, -g.val.im} : g.val;   // reflected: conjugate value
-        } else {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) wv[j] = T(0);
-            vv[lane] = {T(0), T(0)};
-        }
-        if (base == 0) {
-            prev = __shfl(key, 0);
-            slot = prev + lane_off;
-            old = acc[slot];
-        }
-        // a run starts where the key changes (the previous batch's last key carries over)
-        int before = __shfl_up(key, 1);
-        if (lane == 0) before = prev;
-        const unsigned long long starts = __ballot(e < n && key != before);
-        prev = __shfl(key, 63);
-        wave_lds_sync();
-        // walk the batch; entry v + 1's staged values are loaded while entry v is added
-        T wxn = wts[jx], wyn = wts[8 + jy];
-        cplx<T> valn = vv[0];
-#pragma unroll
-        for (int v = 0; v < 64; ++v) {
-            const T wx = wxn, wy = wyn;
-            const cplx<T> val = valn;
-            if (v < 63) {
-                wxn = wts[(v + 1) * GW + jx];
-                wyn = wts[(v + 1) * GW + 8 + jy];
-                valn = vv[v + 1];
-            }
-            if ((starts >> v) & 1ull) {
-                acc[slot] = {old.re + racc.re, old.im + racc.im};
-                racc = {T(0), T(0)};
-                slot = __builtin_amdgcn_readlane(key, v) + lane_off;
-                old = acc[slot];
-            }
-            const T w = wx * wy;
-            racc.re += w * val.re;
-            racc.im += w * val.im;
-        }
-        wave_lds_sync();
-    }
-    acc[slot] = {old.re + racc.re, old.im + racc.im};
-}
-
-// Three waves share the tile accumulator: bands 0, 2, 4 first, then 1, 3.
-constexpr int GR_WAVES = 3;
+constexpr int GR_WS = KB_J + 1;   // staged kernel values per entry (odd stride)
 
 template <typename T>
-__global__ __launch_bounds__(64 * GR_WAVES) void k_grid_pull(
+__global__ __launch_bounds__(64) void k_grid_pull(
     const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
     const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
-    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int TT, int gtiles_x,
-    KBPoly<T> kb) {
-    extern __shared__ unsigned char smem_raw[];
-    const int TS = grid_stride(TT), TA = TT + 2 * GR_APRON;
-    cplx<T>* acc = reinterpret_cast<cplx<T>*>(smem_raw);          // [TA][TS]: rows/cols -7 .. T+6
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    cplx<T>* vv = acc + TA * TS + w * 64;                          // [64] per wave
-    T* wts = reinterpret_cast<T*>(acc + TA * TS + GR_WAVES * 64) + w * 64 * GW;   // [64][GW] per wave
-    const GridUnit* up = units + blockIdx.x;
-    const int l = up->l, tile = up->tile;
-    const int ox = (tile % gtiles_x - 1) * TT, oy = (tile / gtiles_x) * TT;   // ox = -T for the margin tile
-    for (int e = threadIdx.x; e < TA * TS; e += 64 * GR_WAVES) acc[e] = {T(0), T(0)};
-    __syncthreads();
-    grid_band<T>(acc, vv, wts, glist + up->bs[2 * w], up->bn[2 * w], cell, frac, vals, weight, ox, oy, Ky, TT, kb,
-                 lane);
-    __syncthreads();
-    if (w < 2)
-        grid_band<T>(acc, vv, wts, glist + up->bs[2 * w + 1], up->bn[2 * w + 1], cell, frac, vals, weight, ox, oy,
-                     Ky, TT, kb, lane);
-    __syncthreads();
-    if (up->nsplit == 1) {
-        cplx<T>* g = grid + (size_t)l * Ky * Wg + TT;   // column of kx = 0
-        for (int e = threadIdx.x; e < TT * TT; e += 64 * GR_WAVES) {
-            const int ry = e / TT, rx = e - ry * TT;
-            g[(size_t)(oy + ry) * Wg + ox + rx] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int nbx, KBPoly<T> kb) {
+    typedef typename GridAcc<T>::type acc_t;
+    __shared__ T swx[64 * GR_WS], swy[64 * GR_WS];
+    __shared__ T svr[64], svi[64];
+    __shared__ int sdx[64], sdy[64];   // offsets of the first tap from the block origin
+    const GridUnit u = units[blockIdx.x];
+    const int lane = threadIdx.x, il = lane & 15, kq = lane >> 4;
+    const int bx0 = (u.tile % nbx - 1) * GB, by0 = (u.tile / nbx) * GB;   // bx0 = -GB for the margin block
+    const int32_t* gl = glist + u.g0;
+    const int n = u.gn;
+    // two accumulator pairs (even and odd groups of four entries), so that
+    // consecutive products do not wait on each other
+    acc_t are0{}, aim0{}, are1{}, aim1{};
+    // the next batch's list positions are loaded while this batch is gridded
+    int posn = lane < n ? gl[lane] : -1;
+    for (int base = 0; base < n; base += 64) {
+        const int pos = posn;
+        posn = base + 64 + lane < n ? gl[base + 64 + lane] : -1;
+        int dx = 64, dy = 64;   // an empty slot: every tap falls outside the block
+        T vr = T(0), vi = T(0);
+        T wx8[KB_J], wy8[KB_J];
+        if (pos >= 0) {
+            const int cc = cell[pos];
+            const cplx<T> f = frac[pos];
+            cplx<T> val = vals[pos];
+            if (weight) {
+                const T w = weight[pos];
+                val.re *= w;
+                val.im *= w;
+            }
+            dx = (cc & 0x7FFF) - 3 - bx0;   // the half plane has no wrap in x
+            dy = (cc >> 16) - 3 - by0;
+            if (dy < -(KB_J - 1)) dy += Ky;
+            if (dy > GB - 1) dy -= Ky;
+            kb_weights(f.re, kb, wx8);
+            kb_weights(f.im, kb, wy8);
+            vr = val.re;
+            vi = (cc & 0x8000) ? -val.im : val.im;   // reflected: conjugate value
+        } else {
+#pragma unroll
+            for (int j = 0; j < KB_J; ++j) wx8[j] = wy8[j] = T(0);
         }
-    } else {
-        cplx<T>* p = partial + (size_t)(up->partial + up->split) * TT * TT;
-        for (int e = threadIdx.x; e < TT * TT; e += 64 * GR_WAVES) {
-            const int ry = e / TT, rx = e - ry * TT;
-            p[e] = acc[(ry + GR_APRON) * TS + rx + GR_APRON];
+#pragma unroll
+        for (int j = 0; j < KB_J; ++j) {
+            swx[lane * GR_WS + j] = wx8[j];
+            swy[lane * GR_WS + j] = wy8[j];
         }
+        svr[lane] = vr;
+        svi[lane] = vi;
+        sdx[lane] = dx;
+        sdy[lane] = dy;
+        wave_lds_sync();
+        const int ng = (min(64, n - base) + 3) >> 2;
+        auto step = [&](int q, acc_t& are, acc_t& aim) {
+            const int e = 4 * q + kq;
+            const int ty = il - sdy[e], tx = il - sdx[e];
+            const T a = ((unsigned)ty < (unsigned)KB_J) ? swy[e * GR_WS + (ty & (KB_J - 1))] : T(0);
+            const T w = ((unsigned)tx < (unsigned)KB_J) ? swx[e * GR_WS + (tx & (KB_J - 1))] : T(0);
+            are = grid_mfma(a, w * svr[e], are);
+            aim = grid_mfma(a, w * svi[e], aim);
+        };
+        int q = 0;
+        for (; q + 1 < ng; q += 2) {
+            step(q, are0, aim0);
+            step(q + 1, are1, aim1);
+        }
+        if (q < ng) step(q, are0, aim0);
+        wave_lds_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = grid_mfma_row<T>(lane, r);
+        const cplx<T> v{are0[r] + are1[r], aim0[r] + aim1[r]};
+        if (u.nsplit == 1)
+            grid[(size_t)u.l * Ky * Wg + (size_t)(by0 + row) * Wg + GR_MARGIN + bx0 + il] = v;
+        else
+            partial[(size_t)(u.partial + u.split) * GB * GB + row * GB + il] = v;
     }
 }
 
 template <typename T>
 __global__ void k_grid_merge(const SplitTile* __restrict__ splits, const cplx<T>* __restrict__ partial,
-                             cplx<T>* __restrict__ grid, int Ky, int Wg, int TT, int gtiles_x) {
+                             cplx<T>* __restrict__ grid, int Ky, int Wg, int nbx) {
     const SplitTile s = splits[blockIdx.x];
-    const int ox = (s.tile % gtiles_x - 1) * TT, oy = (s.tile / gtiles_x) * TT;
-    cplx<T>* g = grid + (size_t)s.l * Ky * Wg + TT;
-    for (int e = threadIdx.x; e < TT * TT; e += blockDim.x) {
+    const int bx0 = (s.tile % nbx - 1) * GB, by0 = (s.tile / nbx) * GB;
+    cplx<T>* g = grid + (size_t)s.l * Ky * Wg + GR_MARGIN;
+    for (int e = threadIdx.x; e < GB * GB; e += blockDim.x) {
         cplx<T> acc{T(0), T(0)};
         for (int k = 0; k < s.nsplit; ++k) {
-            const cplx<T> p = partial[(size_t)(s.partial + k) * TT * TT + e];
+            const cplx<T> p = partial[(size_t)(s.partial + k) * GB * GB + e];
             acc.re += p.re;
             acc.im += p.im;
         }
-        const int ry = e / TT, rx = e - ry * TT;
-        g[(size_t)(oy + ry) * Wg + ox + rx] = acc;
+        const int ry = e / GB, rx = e - ry * GB;
+        g[(size_t)(by0 + ry) * Wg + bx0 + rx] = acc;
     }
 }
 
@@ -1062,14 +1001,12 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
 
 template <typename T>
 void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    const size_t lds = (size_t)(c->T + 2 * GR_APRON) * grid_stride(c->T) * sizeof(cplx<T>) +
-                       GR_WAVES * 64 * (sizeof(cplx<T>) + GW * sizeof(T));
-    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64 * GR_WAVES, lds, c->stream>>>(
+    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, 0, c->stream>>>(
         c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
-        (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->T, c->gtiles_x, kbpoly<T>(c));
+        (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->gtiles_x, kbpoly<T>(c));
     if (!c->splits.empty())
         k_grid_merge<T><<<(unsigned)c->splits.size(), 256, 0, c->stream>>>(
-            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->T, c->gtiles_x);
+            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->gtiles_x);
 }
 
 template <typename T>

@@ -12,13 +12,15 @@ namespace hs {
 
 // filt: [n_db][2][16] (h then g, zero padded), basis b = db(b+1) with 2(b+1) taps.
 //
-// Analysis, one launch per level: a workgroup owns a TB x TB tile of each of the
-// four subbands of one channel, stages the (2TB + 14)^2 input window (periodic
-// wrap) in LDS, filters rows then columns in LDS and writes the three detail
-// subbands to their Mallat positions; the approximation goes to a compact
-// buffer for the next level (or to its Mallat place at the last level).  At
-// level 0 the input X is shared by every basis, so one workgroup loops over
-// the bases and reads X once.
+// Analysis, one launch per level: a work item is a TB x TB tile of each of the
+// four subbands of one channel (and one basis, below level 0); its
+// (2TB + 14)^2 input window (periodic wrap) is staged in LDS, filtered along
+// rows then columns in LDS, and the three detail subbands go to their Mallat
+// positions; the approximation goes to a compact buffer for the next level (or
+// to its Mallat place at the last level).  At level 0 the input X is shared by
+// every basis, so one item loops over the bases and reads X once.  Work-groups
+// loop over items and load the next item's window into registers while the
+// current one is filtered.
 constexpr int WV_TB = 16;   // analysis output tile per subband
 constexpr int WV_TO = 32;   // synthesis output tile
 constexpr int WV_HALO = 14; // 2 * 8 - 2
@@ -110,37 +112,57 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
                                                    T* __restrict__ coef, T* __restrict__ llout,
                                                    const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                    int lev0, int last, int n_db) {
-    constexpr int TB = WV_TB, WI = WV_WI;
+    constexpr int TB = WV_TB, WI = WV_WI, NW = (WI * WI + 255) / 256;
     __shared__ T inS[WI][WI + 1];
     __shared__ T tmpS[WI][2 * TB + 1];
     const int hx = mx >> 1, hy = my >> 1;
-    const int ntx = (hx + TB - 1) / TB;
-    const int ky0 = (blockIdx.x / ntx) * TB, kx0 = (blockIdx.x % ntx) * TB;
-    const int l = blockIdx.y;
+    const int ntx = (hx + TB - 1) / TB, nty = (hy + TB - 1) / TB, ntiles = ntx * nty;
     const size_t N = (size_t)nx * ny;
     const int tid = threadIdx.x;
-    const int b_first = lev0 ? 0 : (int)blockIdx.z;
-    const int b_last = lev0 ? n_db : (int)blockIdx.z + 1;
-    for (int b = b_first; b < b_last; ++b) {
-        // stage the input window (level 0: once for all bases)
-        if (b == b_first) {
-            const T* src = lev0 ? X + (size_t)l * N : llin + ((size_t)b * L + l) * (size_t)my * mx;
-            const int stride = lev0 ? nx : mx;
-            for (int e = tid; e < WI * WI; e += 256) {
+    // work items: (tile, channel) at level 0 (all bases share the window), else (tile, channel, basis)
+    const int nitems = ntiles * L * (lev0 ? 1 : n_db);
+    T win[NW];
+    auto fetch = [&](int item) {
+        const int tile = item % ntiles, rest = item / ntiles;
+        const int l = rest % L, b = rest / L;
+        const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
+        const T* src = lev0 ? X + (size_t)l * N : llin + ((size_t)b * L + l) * (size_t)my * mx;
+        const int stride = lev0 ? nx : mx;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int e = tid + 256 * k;
+            if (e < WI * WI) {
                 const int r = e / WI, cc = e - r * WI;
                 const int gy = wrap_idx(2 * ky0 + r, my), gx = wrap_idx(2 * kx0 + cc, mx);
-                inS[r][cc] = src[(size_t)gy * stride + gx];
+                win[k] = src[(size_t)gy * stride + gx];
             }
-            __syncthreads();
-        } else {
-            __syncthreads();
         }
-        const T* f = filt + b * 32;
-        WV_DISPATCH(b, dwt_rows, f, inS, tmpS)
+    };
+    int item = blockIdx.x;
+    if (item < nitems) fetch(item);
+    for (; item < nitems; item += gridDim.x) {
+        const int tile = item % ntiles, rest = item / ntiles;
+        const int l = rest % L;
+        const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
+        const int b_first = lev0 ? 0 : rest / L;
+        const int b_last = lev0 ? n_db : b_first + 1;
+        __syncthreads();   // the previous item is done with inS and tmpS
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int e = tid + 256 * k;
+            if (e < WI * WI) inS[e / WI][e % WI] = win[k];
+        }
         __syncthreads();
-        T* cb = coef + ((size_t)b * L + l) * N;
-        T* llb = llout + ((size_t)b * L + l) * (size_t)hy * hx;
-        WV_DISPATCH(b, dwt_cols, f, tmpS, cb, llb, ky0, kx0, hx, hy, nx, last)
+        if (item + (int)gridDim.x < nitems) fetch(item + gridDim.x);   // in flight during the filters
+        for (int b = b_first; b < b_last; ++b) {
+            if (b != b_first) __syncthreads();
+            const T* f = filt + b * 32;
+            WV_DISPATCH(b, dwt_rows, f, inS, tmpS)
+            __syncthreads();
+            T* cb = coef + ((size_t)b * L + l) * N;
+            T* llb = llout + ((size_t)b * L + l) * (size_t)hy * hx;
+            WV_DISPATCH(b, dwt_cols, f, tmpS, cb, llb, ky0, kx0, hx, hy, nx, last)
+        }
     }
 }
 
@@ -391,7 +413,8 @@ void launch_psi_adj(hs_ctx* c, const T* X, T* Cout) {
         const int tiles = ((hy + WV_TB - 1) / WV_TB) * ((hx + WV_TB - 1) / WV_TB);
         T* llout = (lev % 2 == 0) ? slotA : slotB;
         const int last = (lev == c->levels - 1) ? 1 : 0;
-        dim3 g(tiles, c->L, lev == 0 ? 1 : c->n_db);
+        const int items = tiles * c->L * (lev == 0 ? 1 : c->n_db);
+        dim3 g(std::min(items, 4096));
         k_dwt_level<T><<<g, 256, 0, c->stream>>>(X, llin, out, llout, filt, c->L, c->nx, c->ny, mx, my,
                                                  lev == 0 ? 1 : 0, last, c->n_db);
         llin = llout;
