@@ -223,12 +223,16 @@ struct PhaseMarks {
 
 // Steps 4, 10, 11 on dual v (grid order, in place); Step 12 + F^H Z^T into adj if given.
 template <typename T>
-static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const PhaseMarks& pm = PhaseMarks()) {
-    launch_fft_rows_fwd<T>(c, Xt, c->L);
-    launch_fft_cols_fwd<T>(c, c->L);
+static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const PhaseMarks& pm = PhaseMarks(),
+                           bool fft_fwd = true, hipEvent_t after_degrid = nullptr) {
+    if (fft_fwd) {
+        launch_fft_rows_fwd<T>(c, Xt, c->L);
+        launch_fft_cols_fwd<T>(c, c->L);
+    }
     pm.mark(c, HS_PH_FFT_FWD + 1);
     launch_degrid_dual_v<T>(c, v);
     pm.mark(c, HS_PH_DEGRID + 1);
+    if (after_degrid) (void)hipEventRecord(after_degrid, c->stream);
     launch_bins_and_roots<T>(c);
     pm.mark(c, HS_PH_ROOTS + 1);
     launch_dual_apply_v<T>(c, v);
@@ -270,27 +274,47 @@ static void dual_l21_impl(hs_ctx* c, T* A, const T* Xt, const T* wbar, double mu
 // One iteration of Algorithm 2 as three independent branches (data fidelity,
 // low rankness, joint sparsity) joined before the primal update; used for the
 // captured graph so the branches overlap on the device.
+// Where the side branches start: 0 at the iteration start, 1 after the forward
+// FFT, 2 after the degridding pass.
+constexpr int L21_START = 1, NUC_START = 1;
 template <typename T>
 static void pd_iter_forked(hs_ctx* c) {
     Dev& d = c->d;
     T* Xt = (T*)d.Xt;
     hipStream_t main = c->stream;
     const bool nuc = use_nuclear(c), sp = use_sparsity(c);
-    (void)hipEventRecord(c->ev_fork, main);
-    if (nuc) {
-        (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0);
+    auto branch_nuc = [&]() {
         c->stream = c->side[0];
         dual_nuclear_impl<T>(c, (T*)d.P, Xt);
         (void)hipEventRecord(c->ev_join[0], c->side[0]);
-    }
-    if (sp) {
-        (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0);
+        c->stream = main;
+    };
+    auto branch_l21 = [&]() {
         c->stream = c->side[1];
         dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1);
         (void)hipEventRecord(c->ev_join[1], c->side[1]);
+        c->stream = main;
+    };
+    (void)hipEventRecord(c->ev_fork, main);
+    if (nuc && NUC_START == 0) { (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0); branch_nuc(); }
+    if (sp && L21_START == 0) { (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0); branch_l21(); }
+    launch_fft_rows_fwd<T>(c, Xt, c->L);
+    launch_fft_cols_fwd<T>(c, c->L);
+    if ((nuc && NUC_START == 1) || (sp && L21_START == 1)) {
+        (void)hipEventRecord(c->ev_mid, main);
+        if (nuc && NUC_START == 1) { (void)hipStreamWaitEvent(c->side[0], c->ev_mid, 0); branch_nuc(); }
+        if (sp && L21_START == 1) { (void)hipStreamWaitEvent(c->side[1], c->ev_mid, 0); branch_l21(); }
     }
-    c->stream = main;
-    dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0);
+    const bool late = (nuc && NUC_START == 2) || (sp && L21_START == 2);
+    if (late) {
+        // record after the degridding; the branches are forked below, after the
+        // data branch's remaining launches are enqueued in capture order
+        dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0, PhaseMarks(), false, c->ev_mid);
+        if (nuc && NUC_START == 2) { (void)hipStreamWaitEvent(c->side[0], c->ev_mid, 0); branch_nuc(); }
+        if (sp && L21_START == 2) { (void)hipStreamWaitEvent(c->side[1], c->ev_mid, 0); branch_l21(); }
+    } else {
+        dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0, PhaseMarks(), false);
+    }
     if (nuc) (void)hipStreamWaitEvent(main, c->ev_join[0], 0);
     if (sp) (void)hipStreamWaitEvent(main, c->ev_join[1], 0);
     launch_primal<T>(c, sp ? (const T*)d.img1 : nullptr, (const T*)d.img0, nuc);
@@ -497,6 +521,7 @@ hs_status hs_destroy(hs_ctx* c) {
         if (c->ev_join[k]) hipEventDestroy(c->ev_join[k]);
     }
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_mid) hipEventDestroy(c->ev_mid);
     delete c;
     return HS_OK;
 }
@@ -846,6 +871,7 @@ static hs_status pd_capture(hs_ctx* c) {
             s = hip_check(c, hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming), "join event");
     }
     if (!s && !c->ev_fork) s = hip_check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
+    if (!s && !c->ev_mid) s = hip_check(c, hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming), "mid event");
     if (s) return s;
     s = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
     if (s) return s;

@@ -191,7 +191,7 @@ struct hs_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t side[2] = {nullptr, nullptr};   // fork/join branches of the captured iteration
-    hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join[2] = {nullptr, nullptr};
     bool graph_valid = false;
 };
 

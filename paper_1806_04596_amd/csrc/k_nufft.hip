@@ -803,11 +803,16 @@ __global__ __launch_bounds__(64) void k_grid_pull(
         sdy[lane] = dy;
         wave_lds_sync();
         const int ng = (min(64, n - base) + 3) >> 2;
+        // the staged reads are unconditional (indices wrapped into the entry's
+        // row) and masked afterwards, so they carry no branches and the reads
+        // of later groups overlap the products of earlier ones
         auto step = [&](int q, acc_t& are, acc_t& aim) {
             const int e = 4 * q + kq;
             const int ty = il - sdy[e], tx = il - sdx[e];
-            const T a = ((unsigned)ty < (unsigned)KB_J) ? swy[e * GR_WS + (ty & (KB_J - 1))] : T(0);
-            const T w = ((unsigned)tx < (unsigned)KB_J) ? swx[e * GR_WS + (tx & (KB_J - 1))] : T(0);
+            const T ay = swy[e * GR_WS + (ty & (KB_J - 1))];
+            const T wx = swx[e * GR_WS + (tx & (KB_J - 1))];
+            const T a = ((unsigned)ty < (unsigned)KB_J) ? ay : T(0);
+            const T w = ((unsigned)tx < (unsigned)KB_J) ? wx : T(0);
             are = grid_mfma(a, w * svr[e], are);
             aim = grid_mfma(a, w * svi[e], aim);
         };
