@@ -25,6 +25,7 @@ constexpr int WV_TB = 16;   // analysis output tile per subband
 constexpr int WV_TO = 32;   // synthesis output tile
 constexpr int WV_HALO = 14; // 2 * 8 - 2
 constexpr int WV_W = WV_TO / 2 + 8;   // synthesis coefficient window per subband
+constexpr int64_t IDWT_MIN_WG = 2048;  // smallest synthesis grid worth looping bases for
 
 // k mod n for 0 <= k < 2n + W (one subtraction in the usual case; small
 // coarse levels fall back to the remainder).
@@ -228,10 +229,10 @@ __device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
                                                     T* __restrict__ out, const T* __restrict__ C0,
                                                     const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
-                                                    int coarsest, int final_level, int n_db) {
+                                                    int coarsest, int final_level, int n_db, int bpw) {
     constexpr int TO = WV_TO, W = WV_W;
     static_assert(TO * TO / 2 == 2 * 256, "two output pairs per thread");
     __shared__ T S[4][W][W + 1];           // subband (sy*2 + sx)
@@ -247,8 +248,8 @@ __global__ __launch_bounds__(256) void k_idwt_level(const T* __restrict__ C, con
     int kxlo = (m0x / 2 - 8) % hx;
     if (kxlo < 0) kxlo += hx;
     T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
-    const int b_first = final_level ? 0 : (int)blockIdx.z;
-    const int b_last = final_level ? n_db : (int)blockIdx.z + 1;
+    const int b_first = final_level ? 0 : (int)blockIdx.z * bpw;
+    const int b_last = final_level ? n_db : min(b_first + bpw, n_db);
     // This thread's window elements: the same offsets in every basis, computed once.
     // Element i comes from the coarser approximation (llin) when it is in subband 0
     // below the coarsest level, else from the coefficient image.
@@ -438,9 +439,15 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout) {
         const int tiles = ((my + WV_TO - 1) / WV_TO) * ((mx + WV_TO - 1) / WV_TO);
         const int fin = (lev == 0) ? 1 : 0;
         T* out = fin ? Xout : ((lev % 2 == 1) ? slotA : slotB);
-        dim3 g(tiles, c->L, fin ? 1 : c->n_db);
+        // bases per work-group: as many as keep the grid at IDWT_MIN_WG or more, so the
+        // next basis's window is fetched while this one is filtered
+        int bpw = 1;
+        while (!fin && bpw < c->n_db && (int64_t)tiles * c->L * ((c->n_db + 2 * bpw - 1) / (2 * bpw)) >= IDWT_MIN_WG)
+            bpw *= 2;
+        const int nz = fin ? 1 : (c->n_db + bpw - 1) / bpw;
+        dim3 g(tiles, c->L, nz);
         k_idwt_level<T><<<g, 256, 0, c->stream>>>(Cdb, llin, out, C0, filt, c->L, c->nx, c->ny, mx, my,
-                                                  lev == c->levels - 1 ? 1 : 0, fin, c->n_db);
+                                                  lev == c->levels - 1 ? 1 : 0, fin, c->n_db, bpw);
         llin = out;
     }
 }
