@@ -63,7 +63,7 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.blk_vartheta, (size_t)c->nblk * 4, base);
     k.take(d.run_sum, (size_t)c->nruns * 16, base);
     k.take(d.bin_run_ptr, (size_t)(c->nbins + 1) * 4, base);
-    k.take(d.bin_runs, (size_t)c->nruns * 4, base);
+    k.take(d.run_slot, (size_t)c->nruns * 4, base);
     k.take(d.chunk_run, c->h_chunk_run.size() * 4, base);
     k.take(d.bin_S, (size_t)c->nbins * 16, base);
     k.take(d.grid, (size_t)c->L * c->Ky * c->Wg * cx, base);
@@ -139,7 +139,7 @@ static hs_status bind_impl(hs_ctx* c) {
     upload(d.blk_bin_ptr, c->h_blk_bin_ptr);
     upload(d.blk_eps, c->h_blk_eps);
     upload(d.bin_run_ptr, c->h_bin_run_ptr);
-    upload(d.bin_runs, c->h_bin_runs);
+    upload(d.run_slot, c->h_run_slot);
     upload(d.chunk_run, c->h_chunk_run);
     // FFT twiddles exp(-2 pi i k / K) and deapodisation 1/phihat(p/K)
     const long double pi = 3.141592653589793238462643383279502884L;

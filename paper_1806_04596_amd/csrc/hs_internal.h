@@ -23,7 +23,8 @@ constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
 // One degridding work unit: `count` (<= DEG_THREADS*DEG_BATCHES) visibilities of
 // one tile of channel l starting at global position `start`.  Runs of equal bin
 // are cut at every DEG_CHUNK visibilities of the unit (one wave's share);
-// chunk_run[chunk0 + j] is the number of the first run of chunk j.
+// chunk_run[chunk0 + j] is the number of the first run of chunk j; the sums of
+// run r are stored at slot run_slot[r], so that each bin's runs are contiguous.
 constexpr int DEG_CHUNK = 64;
 struct DegridUnit {
     int32_t l, tile, start, count;
@@ -97,7 +98,7 @@ struct Dev {
     int32_t* blk_vartheta = nullptr; // [nblk]
     double* run_sum = nullptr;     // [nruns][2] (|d|^2, |y - Phi Xt|^2)
     int32_t* bin_run_ptr = nullptr;// [nbins+1]
-    int32_t* bin_runs = nullptr;   // [nruns]
+    int32_t* run_slot = nullptr;   // [nruns] slot of each run's sums in run_sum (grouped by bin)
     int32_t* chunk_run = nullptr;  // [chunks] first run of each DEG_CHUNK-visibility chunk
     double* bin_S = nullptr;       // [nbins][2]
     // FFT
@@ -172,7 +173,7 @@ struct hs_ctx {
     int kb_terms = 0;
     std::vector<double> kb_c;          // power-series coefficients
     // host staging of the plan (uploaded at bind)
-    std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_bin_runs;
+    std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_run_slot;
     std::vector<int32_t> h_chunk_run;
     std::vector<double> h_frac, h_y, h_theta, h_u, h_bin_u, h_blk_eps;
     std::vector<int64_t> h_pos_of;     // caller global index -> grid position

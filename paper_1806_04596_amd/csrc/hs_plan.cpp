@@ -463,14 +463,15 @@ hs_status build_plan(hs_ctx* c) {
     c->nbins = bin_base;
     c->nruns = nruns;
     c->npartial = npartial;
-    // CSR: bin -> runs (increasing run index within a bin)
+    // Run sums are stored grouped by bin (increasing run index within a bin):
+    // run r goes to slot run_slot[r], and bin k owns slots [bin_run_ptr[k], bin_run_ptr[k + 1]).
     c->h_bin_run_ptr.assign(c->nbins + 1, 0);
     for (auto& pr : run_bin) c->h_bin_run_ptr[pr.first + 1]++;
     for (int64_t k = 0; k < c->nbins; ++k) c->h_bin_run_ptr[k + 1] += c->h_bin_run_ptr[k];
-    c->h_bin_runs.assign(nruns, 0);
+    c->h_run_slot.assign(nruns, 0);
     {
         std::vector<int32_t> fillp(c->h_bin_run_ptr.begin(), c->h_bin_run_ptr.end() - 1);
-        for (auto& pr : run_bin) c->h_bin_runs[fillp[pr.first]++] = pr.second;
+        for (auto& pr : run_bin) c->h_run_slot[pr.second] = fillp[pr.first]++;
     }
     // kernel polynomial (Chebyshev interpolant, rounding-level accurate)
     c->kb_terms = c->dtype == HS_F64 ? KBTerms<double>::n : KBTerms<float>::n;

@@ -535,7 +535,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ uprec,
     const cplx<T>* __restrict__ yv, const int32_t* __restrict__ vbin, cplx<T>* __restrict__ v,
-    const int32_t* __restrict__ chunk_run, double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x,
+    const int32_t* __restrict__ chunk_run, const int32_t* __restrict__ run_slot, double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x,
     KBPoly<T> kb) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -586,25 +586,25 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
         }
         const bool last = lane == 63 || !act || ((heads >> (lane + 1)) & 1ull) || (i + 1 >= u.count);
         if (act && last) {
-            const int slot = chunk_run[u.chunk0 + j] + __popcll(heads & le) - 1;
+            const int slot = run_slot[chunk_run[u.chunk0 + j] + __popcll(heads & le) - 1];
             run_sum[2 * (size_t)slot] = a0;
             run_sum[2 * (size_t)slot + 1] = a1;
         }
     }
 }
 
-// Bin sums (fixed order, one wave per bin): S[bin] = sum of its runs.
-__global__ void k_bin_reduce(const int32_t* __restrict__ bin_run_ptr, const int32_t* __restrict__ bin_runs,
-                             const double* __restrict__ run_sum, double* __restrict__ S, int nbins) {
+// Bin sums (fixed order, one wave per bin): S[bin] = sum of its runs, which
+// the degridding stored in the bin's contiguous slot range.
+__global__ void k_bin_reduce(const int32_t* __restrict__ bin_run_ptr, const double* __restrict__ run_sum,
+                             double* __restrict__ S, int nbins) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wave >= nbins) return;
     const int r0 = bin_run_ptr[wave], r1 = bin_run_ptr[wave + 1];
     double a = 0.0, b = 0.0;
     for (int k = r0 + lane; k < r1; k += 64) {
-        const int r = bin_runs[k];
-        a += run_sum[2 * (size_t)r];
-        b += run_sum[2 * (size_t)r + 1];
+        a += run_sum[2 * (size_t)k];
+        b += run_sum[2 * (size_t)k + 1];
     }
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
@@ -983,13 +983,13 @@ void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v) {
     k_degrid_dual<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
-        c->d.chunk_run, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+        c->d.chunk_run, c->d.run_slot, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
 }
 
 template <typename T>
 void launch_bins_and_roots(hs_ctx* c) {
     if (c->nbins == 0) return;
-    k_bin_reduce<<<nblocks(c->nbins * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr, c->d.bin_runs, c->d.run_sum,
+    k_bin_reduce<<<nblocks(c->nbins * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr, c->d.run_sum,
                                                                        c->d.bin_S, (int)c->nbins);
     k_block_roots<<<nblocks(c->nblk * 64, 256), 256, 0, c->stream>>>(
         c->d.blk_bin_ptr, c->d.bin_S, c->d.bin_u, c->d.blk_eps, c->d.blk_lambda, c->d.blk_rho2, c->d.blk_vartheta,

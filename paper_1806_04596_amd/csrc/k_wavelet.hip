@@ -173,68 +173,77 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
 // inverts along y then x in LDS, and writes a compact approximation for the
 // next finer level.  At level 0 it loops over the bases and writes
 // Xout = C0 + sum_b Psi_b C_b once.  Outputs 2p and 2p + 1 of a filter pass
-// read the same coefficients (even taps for the first, odd for the second), so
-// each thread produces such a pair.
+// read the same coefficients (even taps for the first, odd for the second).
+// Each thread owns a short run of adjacent outputs: it reads the coefficients
+// the run needs once into registers and forms every output as a chain of
+// FMAs, so the inner loops carry no index arithmetic.
+
+// Column (y) inverse: thread t < 192 owns x-subband sx, window column wx and
+// the output rows 2p, 2p + 1 for p in [p0, p0 + 4).
+constexpr int IDWT_YP = 4;
 template <typename T, int NT>
 __device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T (*S)[WV_W][WV_W + 1],
-                                       T (*Tm)[WV_TO][WV_W + 1]) {
-    constexpr int TO = WV_TO, W = WV_W;
-    T h[NT], g[NT];
+                                       T (*Tm)[WV_TO][WV_W + 1], int sx, int wx, int p0) {
+    constexpr int NH = NT / 2, NR = NH + IDWT_YP - 1;
+    T a[NR], d[NR];
+    const int r0 = p0 + 9 - NH;   // first window row of the run
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        h[j] = f[j];
-        g[j] = f[16 + j];
+    for (int k = 0; k < NR; ++k) {
+        a[k] = S[sx][r0 + k][wx];
+        d[k] = S[2 + sx][r0 + k][wx];
     }
-    for (int e = threadIdx.x; e < 2 * (TO / 2) * W; e += blockDim.x) {
-        const int wx = e % W, t = e / W;
-        const int p = t % (TO / 2), sx = t / (TO / 2);
+#pragma unroll
+    for (int j = 0; j < IDWT_YP; ++j) {
         T xe = T(0), xo = T(0);
 #pragma unroll
-        for (int i = 0; i < NT / 2; ++i) {
-            const int w = p - i + 8;
-            const T a = S[sx][w][wx], d = S[2 + sx][w][wx];
-            xe += h[2 * i] * a + g[2 * i] * d;
-            xo += h[2 * i + 1] * a + g[2 * i + 1] * d;
+        for (int i = 0; i < NH; ++i) {
+            const int k = j - i + NH - 1;   // row p0 + j - i + 8
+            xe = fma(f[2 * i], a[k], xe);
+            xe = fma(f[16 + 2 * i], d[k], xe);
+            xo = fma(f[2 * i + 1], a[k], xo);
+            xo = fma(f[16 + 2 * i + 1], d[k], xo);
         }
-        Tm[sx][2 * p][wx] = xe;
-        Tm[sx][2 * p + 1][wx] = xo;
+        Tm[sx][2 * (p0 + j)][wx] = xe;
+        Tm[sx][2 * (p0 + j) + 1][wx] = xo;
     }
 }
 
-// x pass: thread item k covers row m = e / (TO/2), columns 2q, 2q + 1.
+// Row (x) inverse: thread t owns output row m and columns 2q0 .. 2q0 + 3.
 template <typename T, int NT>
-__device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV_TO][WV_W + 1], T (&res)[2][2]) {
-    constexpr int TO = WV_TO;
-    T h[NT], g[NT];
+__device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV_TO][WV_W + 1], int m, int q0,
+                                       T (&res)[4]) {
+    constexpr int NH = NT / 2, NC = NH + 1;
+    T a[NC], d[NC];
+    const int c0 = q0 + 9 - NH;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        h[j] = f[j];
-        g[j] = f[16 + j];
+    for (int k = 0; k < NC; ++k) {
+        a[k] = Tm[0][m][c0 + k];
+        d[k] = Tm[1][m][c0 + k];
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int e = threadIdx.x + k * 256;
-        const int m = e / (TO / 2), q = e % (TO / 2);
+    for (int j = 0; j < 2; ++j) {
         T xe = T(0), xo = T(0);
 #pragma unroll
-        for (int i = 0; i < NT / 2; ++i) {
-            const int w = q - i + 8;
-            const T a = Tm[0][m][w], d = Tm[1][m][w];
-            xe += h[2 * i] * a + g[2 * i] * d;
-            xo += h[2 * i + 1] * a + g[2 * i + 1] * d;
+        for (int i = 0; i < NH; ++i) {
+            const int k = j - i + NH - 1;   // column q0 + j - i + 8
+            xe = fma(f[2 * i], a[k], xe);
+            xe = fma(f[16 + 2 * i], d[k], xe);
+            xo = fma(f[2 * i + 1], a[k], xo);
+            xo = fma(f[16 + 2 * i + 1], d[k], xo);
         }
-        res[k][0] = xe;
-        res[k][1] = xo;
+        res[2 * j] = xe;
+        res[2 * j + 1] = xo;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
                                                     T* __restrict__ out, const T* __restrict__ C0,
                                                     const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                     int coarsest, int final_level, int n_db, int bpw) {
     constexpr int TO = WV_TO, W = WV_W;
-    static_assert(TO * TO / 2 == 2 * 256, "two output pairs per thread");
+    static_assert(TO * TO == 4 * 256, "four outputs per thread");
+    static_assert(2 * W * (TO / 2) == IDWT_YP * 192, "y runs on three waves");
     __shared__ T S[4][W][W + 1];           // subband (sy*2 + sx)
     __shared__ T Tm[2][TO][W + 1];         // after the column inverse, per x-subband
     const int hx = mx >> 1, hy = my >> 1;
@@ -247,7 +256,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
     if (kylo < 0) kylo += hy;
     int kxlo = (m0x / 2 - 8) % hx;
     if (kxlo < 0) kxlo += hx;
-    T acc[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    // thread roles in the two filter passes
+    const bool ylive = tid < 192;
+    const int yc = tid % 48, ysx = yc / W, ywx = yc - ysx * W, yp0 = (tid / 48) * IDWT_YP;
+    const int xm = tid >> 3, xq0 = 2 * (tid & 7);
+    T acc[4] = {T(0), T(0), T(0), T(0)};
     const int b_first = final_level ? 0 : (int)blockIdx.z * bpw;
     const int b_last = final_level ? n_db : min(b_first + bpw, n_db);
     // This thread's window elements: the same offsets in every basis, computed once.
@@ -297,41 +310,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
         __syncthreads();
         if (b + 1 < b_last) fetch(b + 1);
         const T* f = filt + b * 32;
-        WV_DISPATCH(b, idwt_y, f, S, Tm)
+        if (ylive) {
+            WV_DISPATCH(b, idwt_y, f, S, Tm, ysx, ywx, yp0)
+        }
         __syncthreads();
-        T res[2][2];
-        WV_DISPATCH(b, idwt_x, f, Tm, res)
+        T res[4];
+        WV_DISPATCH(b, idwt_x, f, Tm, xm, xq0, res)
         if (final_level) {
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                acc[k][0] += res[k][0];
-                acc[k][1] += res[k][1];
-            }
+            for (int k = 0; k < 4; ++k) acc[k] += res[k];
         } else {
+            const int gy = m0y + xm, gx = m0x + 2 * xq0;
+            T* o = out + ((size_t)b * L + l) * (size_t)my * mx + (size_t)gy * mx + gx;
+            if (gy < my) {
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int e = tid + k * 256;
-                const int m = e / (TO / 2), n = 2 * (e % (TO / 2));
-                if (m0y + m < my && m0x + n < mx) {
-                    T* o = out + ((size_t)b * L + l) * (size_t)my * mx + (size_t)(m0y + m) * mx + m0x + n;
-                    o[0] = res[k][0];
-                    o[1] = res[k][1];
-                }
+                for (int k = 0; k < 4; ++k)
+                    if (gx + k < mx) o[k] = res[k];
             }
         }
         __syncthreads();
     }
     if (final_level) {
+        // mx is a power of two, so for mx >= 4 the four outputs are all in or all out
+        const int gy = m0y + xm, gx = m0x + 2 * xq0;
+        const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
+        if (gy < my && mx >= 4 && gx < mx) {
+            T v[4];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int e = tid + k * 256;
-            const int m = e / (TO / 2), n = 2 * (e % (TO / 2));
-            const int gy = m0y + m, gx = m0x + n;
-            if (gy < my && gx < mx) {
-                const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
-                out[idx] = (C0 ? C0[idx] : T(0)) + acc[k][0];
-                out[idx + 1] = (C0 ? C0[idx + 1] : T(0)) + acc[k][1];
-            }
+            for (int k = 0; k < 4; ++k) v[k] = (C0 ? C0[idx + k] : T(0)) + acc[k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[idx + k] = v[k];
+        } else if (gy < my) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (gx + k < mx) out[idx + k] = (C0 ? C0[idx + k] : T(0)) + acc[k];
         }
     }
 }
