@@ -155,36 +155,35 @@ __device__ __forceinline__ void fft_store_glb(const cplx<T>* a, int u, int n, in
     }
 }
 
-#define HS_RADIX_SWITCH(R, BODY)                              \
-    switch (R) {                                              \
-        case 16: { constexpr int RR = 16; BODY; } break;      \
-        case 8: { constexpr int RR = 8; BODY; } break;        \
-        case 4: { constexpr int RR = 4; BODY; } break;        \
-        default: { constexpr int RR = 2; BODY; } break;       \
-    }
-
 // The whole transform of this thread's part of sequence s (u: thread index
-// within the sequence, n/16 threads per sequence).
-template <typename T, bool INV, bool ROWS, typename LD, typename ST>
-__device__ __forceinline__ void fft_run(cplx<T>* buf, int u, int s, int n, int CT, const cplx<T>* __restrict__ tw,
-                                        LD ld, ST st) {
-    cplx<T> a[16];
-    int Ns = 1;
-    int R = n < 16 ? n : 16;
-    HS_RADIX_SWITCH(R, (fft_load_glb<T, RR>(a, u, n, ld)))
-    for (;;) {
-        HS_RADIX_SWITCH(R, (fft_compute<T, INV, RR>(a, u, n, Ns, tw)))
-        if (Ns * R == n) {
-            HS_RADIX_SWITCH(R, (fft_store_glb<T, RR>(a, u, n, Ns, st)))
-            break;
-        }
-        HS_RADIX_SWITCH(R, (fft_store_lds<T, ROWS, RR>(a, buf, u, s, n, Ns, CT)))
+// within the sequence, N/16 threads per sequence).  The length is a template
+// parameter: the radix schedule (16, 16, ..., then the remainder), every index
+// and every twiddle stride fold to constants, so only the live data and the
+// current pass's twiddles occupy registers.
+template <typename T, bool INV, bool ROWS, int N, int NS, typename ST>
+__device__ __forceinline__ void fft_pass_ct(cplx<T>* a, cplx<T>* buf, int u, int s, int CT,
+                                            const cplx<T>* __restrict__ tw, ST st) {
+    constexpr int R = (N / NS) < 16 ? (N / NS) : 16;
+    fft_compute<T, INV, R>(a, u, N, NS, tw);
+    if constexpr (NS * R == N) {
+        fft_store_glb<T, R>(a, u, N, NS, st);
+    } else {
+        constexpr int NS2 = NS * R;
+        constexpr int R2 = (N / NS2) < 16 ? (N / NS2) : 16;
+        fft_store_lds<T, ROWS, R>(a, buf, u, s, N, NS, CT);
         __syncthreads();
-        Ns *= R;
-        R = (n / Ns) < 16 ? (n / Ns) : 16;
-        HS_RADIX_SWITCH(R, (fft_load_lds<T, ROWS, RR>(a, buf, u, s, n, CT)))
+        fft_load_lds<T, ROWS, R2>(a, buf, u, s, N, CT);
         __syncthreads();
+        fft_pass_ct<T, INV, ROWS, N, NS2>(a, buf, u, s, CT, tw, st);
     }
+}
+template <typename T, bool INV, bool ROWS, int N, typename LD, typename ST>
+__device__ __forceinline__ void fft_run_ct(cplx<T>* buf, int u, int s, int CT, const cplx<T>* __restrict__ tw,
+                                           LD ld, ST st) {
+    static_assert(N >= 16 && (N & (N - 1)) == 0, "power-of-two length of at least 16");
+    cplx<T> a[16];
+    fft_load_glb<T, 16>(a, u, N, ld);
+    fft_pass_ct<T, INV, ROWS, N, 1>(a, buf, u, s, CT, tw, st);
 }
 
 // Real-to-complex row pass of F Z.  Rows ja = 2p and jb = 2p + 1 of image l are
@@ -193,10 +192,10 @@ __device__ __forceinline__ void fft_run(cplx<T>* buf, int u, int s, int n, int C
 // transform of a real sequence, X_a[k] = (Z[k] + conj Z[-k]) / 2 and
 // X_b[k] = -i (Z[k] - conj Z[-k]) / 2, and only k in [0, Kx/2] is kept
 // (row stride Hs).  The last FFT pass writes Z to LDS for the separation.
-template <typename T>
+template <typename T, int Kx>
 __global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, cplx<T>* __restrict__ H,
                                                        const T* __restrict__ sx, const T* __restrict__ sy,
-                                                       const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                                                       const cplx<T>* __restrict__ tw, int nx, int ny,
                                                        int Hs, int pairs) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -207,7 +206,7 @@ __global__ __launch_bounds__(512) void k_fft_rows_fwd(const T* __restrict__ X, c
     const T* Xa = X + ((size_t)l * ny + ja) * nx;
     const T* Xb = Xa + nx;
     const T sya = sy[ja], syb = sy[ja + 1];
-    fft_run<T, false, true>(buf, u, s, Kx, 0, tw,
+    fft_run_ct<T, false, true, Kx>(buf, u, s, 0, tw,
         [&](int q) {
             int i = q + (nx >> 1);
             if (i >= Kx) i -= Kx;
@@ -242,9 +241,9 @@ __device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
 // Column pass of F over the half plane: columns kx in [0, Kx/2] in tiles of CT
 // adjacent columns (the last tile is partly idle), rows placed at
 // (j - ny/2) mod Ky.  The grid row has Wg cells, kx = 0 at cell T.
-template <typename T>
+template <typename T, int Ky>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
-                                                       const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kh,
                                                        int Hs, int Wg, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
     const bool live = c <= Kh;
     const cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
     cplx<T>* Gl = G + (size_t)l * Ky * Wg + GR_MARGIN + c;
-    fft_run<T, false, false>(buf, u, s, Ky, CT, tw,
+    fft_run_ct<T, false, false, Ky>(buf, u, s, CT, tw,
         [&](int q) {
             int j = q + (ny >> 1);
             if (j >= Ky) j -= Ky;
@@ -272,9 +271,9 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
 // so columns within GR_FOLD of either edge add the conjugate of their mirror
 // cell as they are loaded (the factor 1/2 is applied by the row pass).
 constexpr int GR_FOLD = 4;
-template <typename T>
+template <typename T, int Ky>
 __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ H,
-                                                       const cplx<T>* __restrict__ tw, int ny, int Kh, int Ky,
+                                                       const cplx<T>* __restrict__ tw, int ny, int Kh,
                                                        int Hs, int Wg, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -286,7 +285,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict_
     const int mx = c <= GR_FOLD ? -c : 2 * Kh - c;
     const cplx<T>* G0 = G + (size_t)l * Ky * Wg + GR_MARGIN;   // kx = 0
     cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
-    fft_run<T, true, false>(buf, u, s, Ky, CT, tw,
+    fft_run_ct<T, true, false, Ky>(buf, u, s, CT, tw,
         [&](int q) {
             if (!live) return cplx<T>{T(0), T(0)};
             cplx<T> g = G0[(size_t)q * Wg + c];
@@ -309,10 +308,10 @@ __global__ __launch_bounds__(512) void k_fft_cols_adj(const cplx<T>* __restrict_
 // A[k] = conj A[Kx - k] beyond Kx/2 (and the real parts at k = 0 and Kx/2,
 // which is what the real part of the full inverse transform keeps) gives
 // x_a + i x_b in one inverse DFT.  Crop, deapodise, times 1/2.
-template <typename T>
+template <typename T, int Kx>
 __global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict__ H, T* __restrict__ X,
                                                        const T* __restrict__ sx, const T* __restrict__ sy,
-                                                       const cplx<T>* __restrict__ tw, int nx, int ny, int Kx,
+                                                       const cplx<T>* __restrict__ tw, int nx, int ny,
                                                        int Hs, int pairs) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -326,7 +325,7 @@ __global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict_
     T* Xa = X + ((size_t)l * ny + ja) * nx;
     T* Xb = Xa + nx;
     const T sya = sy[ja] * T(0.5), syb = sy[ja + 1] * T(0.5);
-    fft_run<T, true, true>(buf, u, s, Kx, 0, tw,
+    fft_run_ct<T, true, true, Kx>(buf, u, s, 0, tw,
         [&](int q) {
             const bool up = q > Kh;
             const int k = up ? Kx - q : q;
@@ -378,13 +377,30 @@ static size_t row_lds(const hs_ctx* c, int rows, size_t csz) {
 
 // Allow up to 160 KiB of dynamic LDS for every FFT instantiation (set once,
 // outside any stream capture).
+// Transform lengths (Kx = 2 nx, Ky = 2 ny with nx, ny powers of two in 16..2048).
+#define HS_FFT_LEN_SWITCH(n, BODY)                         \
+    switch (n) {                                           \
+        case 32: { constexpr int NN = 32; BODY; } break;   \
+        case 64: { constexpr int NN = 64; BODY; } break;   \
+        case 128: { constexpr int NN = 128; BODY; } break; \
+        case 256: { constexpr int NN = 256; BODY; } break; \
+        case 512: { constexpr int NN = 512; BODY; } break; \
+        case 1024: { constexpr int NN = 1024; BODY; } break; \
+        case 2048: { constexpr int NN = 2048; BODY; } break; \
+        default: { constexpr int NN = 4096; BODY; } break; \
+    }
+
+template <typename T, int NN>
+static void fft_attrs_len() {
+    const size_t b = 160 * 1024;
+    set_lds(k_fft_rows_fwd<T, NN>, b);
+    set_lds(k_fft_cols_fwd<T, NN>, b);
+    set_lds(k_fft_cols_adj<T, NN>, b);
+    set_lds(k_fft_rows_adj<T, NN>, b);
+}
 template <typename T>
 static void fft_attrs_one() {
-    const size_t b = 160 * 1024;
-    set_lds(k_fft_rows_fwd<T>, b);
-    set_lds(k_fft_cols_fwd<T>, b);
-    set_lds(k_fft_cols_adj<T>, b);
-    set_lds(k_fft_rows_adj<T>, b);
+    for (int n = 32; n <= 4096; n *= 2) HS_FFT_LEN_SWITCH(n, (fft_attrs_len<T, NN>()))
 }
 void fft_init_attrs() {
     static bool done = false;
@@ -398,33 +414,31 @@ template <typename T>
 void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L) {
     const int p = row_group(c);
     dim3 grid(c->ny / (2 * p), L);
-    k_fft_rows_fwd<T><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
-        X, (cplx<T>*)c->d.H, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Kx,
-        c->Hs, p);
+    HS_FFT_LEN_SWITCH(c->Kx, (k_fft_rows_fwd<T, NN><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
+        X, (cplx<T>*)c->d.H, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
+        c->Hs, p)))
 }
 template <typename T>
 void launch_fft_cols_fwd(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
     dim3 grid((c->Wh + ct - 1) / ct, L);
-    k_fft_cols_fwd<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
-        ct);
+    HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_fwd<T, NN><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
 }
 template <typename T>
 void launch_fft_cols_adj(hs_ctx* c, int L) {
     const int ct = col_group<T>(c);
     dim3 grid((c->Wh + ct - 1) / ct, L);
-    k_fft_cols_adj<T><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Ky, c->Hs, c->Wg,
-        ct);
+    HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_adj<T, NN><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
+        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
 }
 template <typename T>
 void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
     const int p = row_group(c);
     dim3 grid(c->ny / (2 * p), L);
-    k_fft_rows_adj<T><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
+    HS_FFT_LEN_SWITCH(c->Kx, (k_fft_rows_adj<T, NN><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
         (const cplx<T>*)c->d.H, Xout, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
-        c->Kx, c->Hs, p);
+        c->Hs, p)))
 }
 
 // ------------------------------------------------------------- KB kernel
