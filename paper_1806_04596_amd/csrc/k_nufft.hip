@@ -513,8 +513,10 @@ __device__ __forceinline__ cplx<T> interp(const cplx<T>* tileS, int W, int lx, i
     return acc;
 }
 
-// out[dst] = theta * mult * (G ghat)(vis), dst = perm[pos] (caller order) or pos.
-template <typename T>
+// out[dst] = theta * mult * (G ghat)(vis), dst = perm[pos] (caller order, PERM) or
+// pos; mult is applied when MULT.  The optional operands are template switches,
+// so the loop body has no branches after the interpolation.
+template <typename T, bool PERM, bool MULT>
 __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ mult,
@@ -527,18 +529,24 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
     const int W = TT + 8;
-    for (int i = threadIdx.x; i < u.count; i += DEG_THREADS) {
-        const int pos = u.start + i;
-        const int cc = cell[pos];
-        const int cx = cc & 0x7FFF, cy = cc >> 16;
-        const cplx<T> f = frac[pos];
-        cplx<T> a = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
-        if (cc & 0x8000) a.im = -a.im;   // reflected visibility: conjugate of the value at -t
-        T s = theta[pos];
-        if (mult) s *= mult[pos];
-        a.re *= s;
-        a.im *= s;
-        out[perm ? perm[pos] : pos] = a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // chunk j of the unit (DEG_CHUNK visibilities) is walked by wave j mod 4
+    for (int j = wave; j * DEG_CHUNK < u.count; j += DEG_THREADS / DEG_CHUNK) {
+        const int i = j * DEG_CHUNK + lane;
+        if (i < u.count) {
+            const int pos = u.start + i;
+            const int cc = cell[pos];
+            const int cx = cc & 0x7FFF, cy = cc >> 16;
+            const cplx<T> f = frac[pos];
+            cplx<T> a = interp(tileS, W, cx - ox, cy - oy, f.re, f.im, kb);
+            if (cc & 0x8000) a.im = -a.im;   // reflected visibility: conjugate of the value at -t
+            T s = theta[pos];
+            if constexpr (MULT) s *= mult[pos];
+            a.re *= s;
+            a.im *= s;
+            if constexpr (PERM) out[perm[pos]] = a;
+            else out[pos] = a;
+        }
     }
 }
 
@@ -974,7 +982,7 @@ template <typename T>
 void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user) {
     if (c->dunits.empty()) return;
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
-    k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
+    k_degrid_plain<T, true, false><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
         c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x,
         kbpoly<T>(c));
@@ -985,9 +993,13 @@ template <typename T>
 void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult) {
     if (c->dunits.empty()) return;
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
-    k_degrid_plain<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
-        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
-        (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+    auto launch = [&](auto kern) {
+        kern<<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
+            c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+            (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+    };
+    if (mult) launch(k_degrid_plain<T, false, true>);
+    else launch(k_degrid_plain<T, false, false>);
 }
 
 template <typename T>
