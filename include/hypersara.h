@@ -198,8 +198,8 @@ hs_status hs_get_info(const hs_ctx* ctx, hs_info* info);
 hs_status hs_density_precond(int64_t M, const double* uv, int32_t nx, int32_t ny, double* out);
 
 /* The library's visibility order for one channel: perm[k] = input index of the
- * k-th visibility in tile-major order, sorted by (tile, region, bin) with ties
- * in input order; region_ptr[t*9 + r] = first position of region r of tile t,
+ * k-th visibility in tile-major order, sorted by (tile, region, bin, cell within
+ * the tile in raster order) with ties in input order; region_ptr[t*9 + r] = first position of region r of tile t,
  * region_ptr has (nx/tile + 1)(2ny/tile)*9 + 1 entries.  Cells are those of the
  * Hermitian half plane: a visibility with (u Kx) mod Kx > Kx/2 is binned at -t
  * (the transform of a real image is conjugate-symmetric), so tiles cover

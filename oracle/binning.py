@@ -18,7 +18,8 @@ for bit.  For channel l with oversampled grid Kx x Ky and square tile T:
   whose kernel footprint reaches into the previous / next tile;
 * bin = block * C + class_of(U), with C the number of distinct preconditioner
   values of the channel and class_of the rank of U_m among them (ascending);
-* order = stable sort by (tile, region, bin), ties kept in input order.
+* order = stable sort by (tile, region, bin, cell within the tile in raster
+  order), ties kept in input order.
 """
 from __future__ import annotations
 
@@ -59,7 +60,9 @@ def bins(u: np.ndarray | None, block_ptr: np.ndarray, M: int):
 
 
 def order(uv: np.ndarray, u: np.ndarray | None, block_ptr: np.ndarray, nx: int, ny: int, T: int):
-    """Returns (perm, region_ptr): perm[k] = input index of the k-th visibility;
+    """The plan's visibility order: by (tile, region, bin, cell within the tile in
+    raster order, input index).  Returns (perm, region_ptr): perm[k] = input index
+    of the k-th visibility;
     region_ptr[(tile*9 + region)] = first position of that (tile, region)."""
     M = uv.shape[0]
     Kx, Ky = 2 * nx, 2 * ny
@@ -69,7 +72,8 @@ def order(uv: np.ndarray, u: np.ndarray | None, block_ptr: np.ndarray, nx: int, 
     reg = 3 * region_class(cy % T, T) + region_class(cx % T, T)
     b, _, _ = bins(u, block_ptr, M)
     key_major = tile * 9 + reg
-    perm = np.lexsort((np.arange(M), b, key_major))
+    cell_in_tile = (cy % T) * T + (cx % T)   # raster order of the cell within its tile
+    perm = np.lexsort((np.arange(M), cell_in_tile, b, key_major))
     ntr = tx * (Ky // T) * 9
     counts = np.bincount(key_major, minlength=ntr)
     region_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)

@@ -241,6 +241,7 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
     o.fy.resize(M);
     o.refl.resize(M);
     std::vector<int64_t> key(M);
+    std::vector<int32_t> loc(M);   // cell within the tile, raster order
     for (int64_t m = 0; m < M; ++m) {
         const HalfCell h = half_cell(uv[2 * m], uv[2 * m + 1], Kx, Ky);
         o.cx[m] = h.cx;
@@ -251,6 +252,7 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
         const int64_t tile = (h.cy / T) * tx + (h.cx / T);
         const int reg = 3 * region_class(h.cy % T, T) + region_class(h.cx % T, T);
         key[m] = tile * 9 + reg;
+        loc[m] = (h.cy % T) * T + (h.cx % T);
     }
     // bins: block * C + rank of the preconditioner value
     o.bin_local.assign(M, 0);
@@ -273,13 +275,24 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
         for (int64_t m = 0; m < M; ++m) o.bin_local[m] = blk[m];
     }
     if (M == 0) o.C = std::max(o.C, 1);
-    // stable counting sorts: by bin, then by (tile, region)
+    // stable counting sorts: by cell within the tile, then by bin, then by (tile,
+    // region).  Within a (tile, region, bin) group the visibilities come in raster
+    // order of their cells, so neighbouring lanes of the degridding read
+    // neighbouring grid cells.
     const int64_t nbins = (int64_t)std::max(nb, 1) * o.C;
-    std::vector<int64_t> cnt(std::max<int64_t>(nbins, ntr) + 1, 0);
-    std::vector<int64_t> tmp(M);
+    const int64_t nloc = (int64_t)T * T;
+    std::vector<int64_t> cnt(std::max<int64_t>(std::max<int64_t>(nbins, ntr), nloc) + 1, 0);
+    std::vector<int64_t> tmp0(M), tmp(M);
+    for (int64_t m = 0; m < M; ++m) cnt[loc[m] + 1]++;
+    for (int64_t k = 0; k < nloc; ++k) cnt[k + 1] += cnt[k];
+    for (int64_t m = 0; m < M; ++m) tmp0[cnt[loc[m]]++] = m;
+    std::fill(cnt.begin(), cnt.end(), 0);
     for (int64_t m = 0; m < M; ++m) cnt[o.bin_local[m] + 1]++;
     for (int64_t k = 0; k < nbins; ++k) cnt[k + 1] += cnt[k];
-    for (int64_t m = 0; m < M; ++m) tmp[cnt[o.bin_local[m]]++] = m;
+    for (int64_t k = 0; k < M; ++k) {
+        const int64_t m = tmp0[k];
+        tmp[cnt[o.bin_local[m]]++] = m;
+    }
     std::fill(cnt.begin(), cnt.end(), 0);
     for (int64_t m = 0; m < M; ++m) cnt[key[m] + 1]++;
     for (int64_t k = 0; k < ntr; ++k) cnt[k + 1] += cnt[k];
