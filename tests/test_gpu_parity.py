@@ -46,6 +46,26 @@ def test_phi_adj_parity(name, dtype):
     check_rel_pc(X, ref, TOL[dtype], "X")
 
 
+# The FFT kernels are instantiated per transform length (2 nx and 2 ny): the
+# shortest (32) and the longest (2048 and 4096) beside the lengths of the cases
+# above, with unequal row and column lengths in the last shape.
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(16, 16), (1024, 1024), (2048, 256)])
+def test_phi_and_adjoint_transform_lengths(shape, dtype):
+    nx, ny = shape
+    over = dict(nx=nx, ny=ny, L=2, m_per_chan=3000, n_blocks=2)
+    cfg, inp, op = oracle_case("c1", **over)
+    prob, _, _ = gpu_case("c1", dtype, **over)
+    X = inp["X0"] + 0.1 * _seeded(inp["X0"].shape, 3)
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    ref = op.phi(X)
+    err = max(rel(Y[l], ref[l]) for l in range(cfg.L))
+    assert err <= TOL[dtype], err
+    y = _seeded(prob.M, 4, complex_=True)
+    Xa = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
+    check_rel_pc(Xa, op.phi_adj(split(y, prob.counts)), TOL[dtype], "X")
+
+
 def test_dot_test_f64():
     prob, _, _ = gpu_case("t2", "f64")
     x = _seeded((prob.L, prob.ny, prob.nx), 3)
