@@ -4,8 +4,9 @@
 A step is one iteration of Algorithm 2 (all operators: Phi, Phi^dagger, the
 SARA dictionary, the nuclear, l2,1 and data-fidelity duals, the primal update)
 over the whole synthetic 512 x 512 x 60 cube with uneven channels (workload
-"c3"), batched in FP32 and replayed from a captured HIP graph.  Prints one JSON
-line (see the design doc for the fields).
+"cube512_L60"), batched in FP32 and replayed from a captured HIP graph.  Prints one JSON
+line: the metric, its value and unit, the per-phase times, the roofline of the dominant
+kernel, the FP64 comparison and the CPU-oracle baseline.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="c3")
+    p.add_argument("--workload", default="cube512_L60")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-channels", type=int, default=3, help="channels of the oracle's CPU sample")
@@ -209,8 +210,7 @@ def main():
         write_traffic(*args.traffic_from)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported "
-                                   "(see DESIGN.md for how the path would shard)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus above 1 is not supported"}))
         sys.exit(2)
     import numpy as np
     import torch

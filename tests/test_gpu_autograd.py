@@ -26,7 +26,7 @@ def _rand(torch, prob, shape, seed, complex_=False):
 def test_gradcheck_f64(op):
     import torch
     from paper_1806_04596_amd import autograd as AG
-    prob, _, _ = gpu_case("t1", "f64")
+    prob, _, _ = gpu_case("cube32_L3", "f64")
     shapes = {"phi": (prob.L, prob.ny, prob.nx), "phi_adj": (prob.M,), "psi_adj": (prob.L, prob.ny, prob.nx),
               "psi": (prob.D, prob.L, prob.ny, prob.nx)}
     x = _rand(torch, prob, shapes[op], 10, complex_=(op == "phi_adj")).requires_grad_(True)
@@ -39,7 +39,7 @@ def test_gradcheck_f64(op):
 def test_backward_is_the_adjoint_call():
     import torch
     from paper_1806_04596_amd import autograd as AG
-    prob, _, _ = gpu_case("t2", "f32")
+    prob, _, _ = gpu_case("cube64_L5", "f32")
     x = _rand(torch, prob, (prob.L, prob.ny, prob.nx), 11).requires_grad_(True)
     gy = _rand(torch, prob, (prob.M,), 12, complex_=True)
     AG.phi(prob, x).backward(gy)
@@ -56,8 +56,8 @@ def test_loss_gradient_vs_oracle(dtype):
     Re Phi^dag (Phi X - y) + lam Psi (C_r / ||C_r||)."""
     import torch
     from paper_1806_04596_amd import autograd as AG
-    cfg, inp, op = oracle_case("t2")
-    prob, _, _ = gpu_case("t2", dtype)
+    cfg, inp, op = oracle_case("cube64_L5")
+    prob, _, _ = gpu_case("cube64_L5", dtype)
     rng = np.random.default_rng(20)
     X = inp["X0"] + 0.05 * np.abs(rng.standard_normal(inp["X0"].shape)) * inp["X0"].max()
     y = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
@@ -89,7 +89,7 @@ def test_full_cube_finite_differences():
     import torch
     from paper_1806_04596_amd import autograd as AG
     from paper_1806_04596_amd.workload import build_problem
-    cfg = W.CONFIGS["c4"]
+    cfg = W.CONFIGS["cube512_L60_autograd"]
     inp = W.make_problem_inputs(cfg)
     grads = {}
     for dtype in ("f64", "f32"):

@@ -16,7 +16,7 @@ from gpu_cases import TOL, check_rel, host, rel, split, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-CFG = W.CONFIGS["c3"]
+CFG = W.CONFIGS["cube512_L60"]
 
 
 @pytest.fixture(scope="module")
@@ -31,7 +31,7 @@ def big():
     sub = {"X0": inp["X0"][S], "uv": [inp["uv"][l] for l in S], "block_ptr": [inp["block_ptr"][l] for l in S],
            "noise": [inp["noise"][l] for l in S]}
     op, _ = pd.build_problem(CFG.scaled(L=len(S)), sub)
-    print(f"c3 full size: sampled channels {S}, M = {prob.M}", flush=True)
+    print(f"cube512_L60 full size: sampled channels {S}, M = {prob.M}", flush=True)
     return {"inp": inp, "prob": prob, "S": S, "op": op}
 
 

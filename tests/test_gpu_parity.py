@@ -11,7 +11,7 @@ from gpu_cases import TOL, check_rel, check_rel_pc, gpu_case, host, oracle_case,
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["t1", "t2", "t3", "c1"]
+CASES = ["cube32_L3", "cube64_L5", "cube128x64_L4", "cube64_L4"]
 DTYPES = ["f64", "f32"]
 
 
@@ -54,8 +54,8 @@ def test_phi_adj_parity(name, dtype):
 def test_phi_and_adjoint_transform_lengths(shape, dtype):
     nx, ny = shape
     over = dict(nx=nx, ny=ny, L=2, m_per_chan=3000, n_blocks=2)
-    cfg, inp, op = oracle_case("c1", **over)
-    prob, _, _ = gpu_case("c1", dtype, **over)
+    cfg, inp, op = oracle_case("cube64_L4", **over)
+    prob, _, _ = gpu_case("cube64_L4", dtype, **over)
     X = inp["X0"] + 0.1 * _seeded(inp["X0"].shape, 3)
     Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
     ref = op.phi(X)
@@ -67,7 +67,7 @@ def test_phi_and_adjoint_transform_lengths(shape, dtype):
 
 
 def test_dot_test_f64():
-    prob, _, _ = gpu_case("t2", "f64")
+    prob, _, _ = gpu_case("cube64_L5", "f64")
     x = _seeded((prob.L, prob.ny, prob.nx), 3)
     y = _seeded(prob.M, 4, complex_=True)
     Phix = host(prob.phi(to_dev(prob, x)))
@@ -79,8 +79,8 @@ def test_dot_test_f64():
 
 def test_phi_vs_nudft_f64():
     # the GPU operator approximates the exact NUDFT to the kernel's accuracy
-    cfg, inp, op = oracle_case("t1")
-    prob, _, _ = gpu_case("t1", "f64")
+    cfg, inp, op = oracle_case("cube32_L3")
+    prob, _, _ = gpu_case("cube32_L3", "f64")
     X = inp["X0"]
     Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
     for l in range(cfg.L):
@@ -90,7 +90,7 @@ def test_phi_vs_nudft_f64():
 
 # --------------------------------------------------------------- wavelets
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["t1", "t3", "c1"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube128x64_L4", "cube64_L4"])
 def test_psi_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
@@ -105,7 +105,7 @@ def test_psi_parity(name, dtype):
 
 
 def test_psi_perfect_reconstruction_f64():
-    prob, _, _ = gpu_case("t3", "f64")
+    prob, _, _ = gpu_case("cube128x64_L4", "f64")
     X = _seeded((prob.L, prob.ny, prob.nx), 7)
     Xr = host(prob.psi(prob.psi_adj(to_dev(prob, X))))
     check_rel(Xr, 9.0 * X, 1e-13, "Xr")
@@ -114,8 +114,8 @@ def test_psi_perfect_reconstruction_f64():
 # ------------------------------------------------------------------ proxes
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_prox_l21_and_dual_l21(dtype):
-    cfg, inp, op = oracle_case("t2")
-    prob, _, _ = gpu_case("t2", dtype)
+    cfg, inp, op = oracle_case("cube64_L5")
+    prob, _, _ = gpu_case("cube64_L5", dtype)
     rng = np.random.default_rng(8)
     A = 0.05 * rng.standard_normal((9, cfg.L, cfg.ny, cfg.nx))
     wbar = rng.uniform(0.2, 1.0, (9, cfg.ny, cfg.nx))
@@ -133,7 +133,7 @@ def test_prox_l21_and_dual_l21(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["t2", "c1"])
+@pytest.mark.parametrize("name", ["cube64_L5", "cube64_L4"])
 def test_nuclear_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
@@ -152,7 +152,7 @@ def test_nuclear_parity(name, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["t1", "t2", "c1"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4"])
 def test_dual_data_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
@@ -176,8 +176,8 @@ def test_dual_data_parity(name, dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_proj_ellipsoid_parity(dtype):
-    cfg, inp, op = oracle_case("t2")
-    prob, _, _ = gpu_case("t2", dtype)
+    cfg, inp, op = oracle_case("cube64_L5")
+    prob, _, _ = gpu_case("cube64_L5", dtype)
     rng = np.random.default_rng(10)
     for l in (0, 3):
         bp = op.block_ptr[l]
@@ -193,8 +193,8 @@ def test_proj_ellipsoid_parity(dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_op_norm_parity_fixed_iterations(dtype):
-    cfg, inp, op = oracle_case("t1")
-    prob, _, _ = gpu_case("t1", dtype)
+    cfg, inp, op = oracle_case("cube32_L3")
+    prob, _, _ = gpu_case("cube32_L3", dtype)
     x0 = W.synth.power_start(cfg)
     val, per, it = prob.op_norm(to_dev(prob, x0), max_it=40, tol=0.0)
     assert it == 40
@@ -219,7 +219,7 @@ def _run_gpu_iteration(prob, st, prm, w, n=1):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["t1", "t2", "c1"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4"])
 def test_pd_one_iteration_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
@@ -245,8 +245,8 @@ def test_pd_one_iteration_parity(name, dtype):
 
 
 def test_pd_twenty_iterations_f64():
-    cfg, inp, op = oracle_case("c1")
-    prob, _, _ = gpu_case("c1", "f64")
+    cfg, inp, op = oracle_case("cube64_L4")
+    prob, _, _ = gpu_case("cube64_L4", "f64")
     st = W.make_state(cfg, inp["X0"], prob.counts)
     w = np.ones(cfg.L)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
@@ -260,8 +260,8 @@ def test_pd_twenty_iterations_f64():
 
 
 def test_graph_replays_match_oracle_each_time():
-    cfg, inp, op = oracle_case("t1")
-    prob, _, _ = gpu_case("t1", "f64")
+    cfg, inp, op = oracle_case("cube32_L3")
+    prob, _, _ = gpu_case("cube32_L3", "f64")
     st = W.make_state(cfg, inp["X0"], prob.counts)
     w = np.ones(cfg.L)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
@@ -281,8 +281,8 @@ def test_graph_replays_match_oracle_each_time():
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_determinism(dtype):
-    cfg, inp, op = oracle_case("t2")
-    prob, _, _ = gpu_case("t2", dtype)
+    cfg, inp, op = oracle_case("cube64_L5")
+    prob, _, _ = gpu_case("cube64_L5", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op))
     a, _, _ = _run_gpu_iteration(prob, st, prm, np.ones(cfg.L), n=3)

@@ -36,7 +36,7 @@ def _set(prob, st):
 def test_reweighted_solve_vs_oracle(dtype):
     """Two reweights (eq:weights-l21, eq:weights-n) between three runs of 6 PD
     iterations each, warm-started, gamma factor 0.8."""
-    cfg, inp, op, prob = _fresh("t1", dtype)
+    cfg, inp, op, prob = _fresh("cube32_L3", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op))
     ost, oprm, hist = pd.solve(op, prm, (1.0, 1.0 / 9.0, prm.kappa3), n_reweights=2, iters_per=6, factor=0.8,
@@ -54,7 +54,7 @@ def test_reweighted_solve_vs_oracle(dtype):
 def test_adaptive_bounds_vs_oracle(dtype):
     """Steps 13-19 with lam1 large enough and vartheta_bar = 1 so that the bounds
     move within a few iterations: eps, rho and X follow the oracle."""
-    cfg, inp, op, prob = _fresh("t2", dtype)
+    cfg, inp, op, prob = _fresh("cube64_L5", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), adaptive_eps=True, lam1=10.0, lam2=0.01, lam3=0.618,
                     vartheta_bar=1)
@@ -83,7 +83,7 @@ def test_adaptive_bounds_vs_oracle(dtype):
 def test_dirty_cube_and_mu_hat_vs_oracle(dtype):
     """X_dirty = Re Phi^dag y normalised by the PSF peak and mu_hat = ||X_dirty||_* /
     ||Psi^dag X_dirty||_{2,1} (Sec. 2.3)."""
-    cfg, inp, op, prob = _fresh("t2", dtype)
+    cfg, inp, op, prob = _fresh("cube64_L5", dtype)
     mu, Xd = prob.dirty_mu()
     check_rel(host(Xd), pd.dirty_cube(op), TOL[dtype], "X_dirty")
     ref = pd.mu_hat(op)
@@ -94,9 +94,9 @@ def test_dirty_cube_and_mu_hat_vs_oracle(dtype):
 @pytest.mark.parametrize("prior", ["lr", "jas", "sara"])
 def test_prior_variants_one_iteration_vs_oracle(prior, dtype):
     """LR, JAS and SARA (Sec. 4.2) through the graph-replayed iteration, three iterations."""
-    cfg, inp, op = oracle_case("t2")
+    cfg, inp, op = oracle_case("cube64_L5")
     from gpu_cases import gpu_case
-    prob, _, _ = gpu_case("t2", dtype)
+    prob, _, _ = gpu_case("cube64_L5", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)
     prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), prior=prior)
     ost = _oracle_state(st, op)

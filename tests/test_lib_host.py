@@ -37,7 +37,7 @@ def test_status_strings():
 
 def test_density_precond_bit_exact():
     from paper_1806_04596_amd import density_precond
-    for name in ("t2", "t3"):
+    for name in ("cube64_L5", "cube128x64_L4"):
         cfg = W.CONFIGS[name]
         uvs, _ = W.synth.make_uv(cfg)
         for uv in uvs:
@@ -46,7 +46,7 @@ def test_density_precond_bit_exact():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,tile,pre", [("t1", 8, True), ("t2", 16, True), ("t2", 32, False), ("t3", 16, True)])
+@pytest.mark.parametrize("name,tile,pre", [("cube32_L3", 8, True), ("cube64_L5", 16, True), ("cube64_L5", 32, False), ("cube128x64_L4", 16, True)])
 def test_visibility_order_bit_exact(name, tile, pre):
     from paper_1806_04596_amd import visibility_order
     cfg = W.CONFIGS[name]

@@ -10,7 +10,7 @@ from oracle import binning, precond
 
 
 def test_density_counts_vs_dictionary_count():
-    cfg = W.CONFIGS["t2"]
+    cfg = W.CONFIGS["cube64_L5"]
     uvs, _ = W.synth.make_uv(cfg)
     for uv in uvs[:2]:
         n = precond.density_counts(uv, cfg.nx, cfg.ny)
@@ -21,7 +21,7 @@ def test_density_counts_vs_dictionary_count():
 
 
 def test_order_definition_properties():
-    cfg = W.CONFIGS["t2"]
+    cfg = W.CONFIGS["cube64_L5"]
     uvs, bps = W.synth.make_uv(cfg)
     T = 16
     for uv, bp in zip(uvs[:2], bps[:2]):

@@ -44,7 +44,7 @@ def test_golden_constants_match_defaults():
 
 def test_one_iteration_pieces_and_positivity():
     prob, X0 = _tiny_problem(1)
-    cfg = W.CONFIGS["t1"].scaled(nx=16, ny=16, L=2)
+    cfg = W.CONFIGS["cube32_L3"].scaled(nx=16, ny=16, L=2)
     st0 = W.make_state(cfg, X0, [len(y) for y in prob.y])
     st = pd.State(X=st0["X"], Xt=st0["Xt"], P=st0["P"], A=st0["A"], v=st0["v"],
                   eps=[e.copy() for e in prob.eps], vartheta=[np.zeros(2, np.int64)] * 2)
@@ -162,7 +162,7 @@ def test_mu_hat_definition():
 
 
 def test_workload_measurements_and_bounds():
-    cfg = W.CONFIGS["t2"]
+    cfg = W.CONFIGS["cube64_L5"]
     inp = W.make_problem_inputs(cfg)
     prob, y_raw = pd.build_problem(cfg, inp)
     for l in range(cfg.L):

@@ -55,15 +55,15 @@ class WorkloadConfig:
 # The five workloads (64^2 x 4 FP64, 256^2 x 15 FP64, 512^2 x 60 uneven FP32,
 # the same cube for autograd, 1024^2 x 32 mixed precision).
 CONFIGS = {
-    "c1": WorkloadConfig("c1", 64, 64, 4, 1.0, 2.0, 20, False, 2048, None, 1, 60.0, 1),
-    "c2": WorkloadConfig("c2", 256, 256, 15, 1.4, 2.8, 50, True, 32768, None, 4, 40.0, 2),
-    "c3": WorkloadConfig("c3", 512, 512, 60, 1.4, 2.8, 50, True, 0, (0.2, 2.0), 8, 40.0, 3),
-    "c4": WorkloadConfig("c4", 512, 512, 60, 1.4, 2.8, 50, True, 0, (0.2, 2.0), 8, 40.0, 4),
-    "c5": WorkloadConfig("c5", 1024, 1024, 32, 1.4, 2.8, 50, True, 1048576, None, 4, 40.0, 5),
+    "cube64_L4": WorkloadConfig("cube64_L4", 64, 64, 4, 1.0, 2.0, 20, False, 2048, None, 1, 60.0, 1),
+    "cube256_L15": WorkloadConfig("cube256_L15", 256, 256, 15, 1.4, 2.8, 50, True, 32768, None, 4, 40.0, 2),
+    "cube512_L60": WorkloadConfig("cube512_L60", 512, 512, 60, 1.4, 2.8, 50, True, 0, (0.2, 2.0), 8, 40.0, 3),
+    "cube512_L60_autograd": WorkloadConfig("cube512_L60_autograd", 512, 512, 60, 1.4, 2.8, 50, True, 0, (0.2, 2.0), 8, 40.0, 4),
+    "cube1024_L32": WorkloadConfig("cube1024_L32", 1024, 1024, 32, 1.4, 2.8, 50, True, 1048576, None, 4, 40.0, 5),
     # small cases used by parity tests: several tiles, ragged block sizes
-    "t1": WorkloadConfig("t1", 32, 32, 3, 1.0, 2.0, 6, False, 700, None, 3, 40.0, 11),
-    "t2": WorkloadConfig("t2", 64, 64, 5, 1.4, 2.8, 12, True, 0, (0.2, 2.0), 4, 40.0, 12),
-    "t3": WorkloadConfig("t3", 128, 64, 4, 1.4, 2.8, 15, True, 0, (0.2, 2.0), 3, 30.0, 13),
+    "cube32_L3": WorkloadConfig("cube32_L3", 32, 32, 3, 1.0, 2.0, 6, False, 700, None, 3, 40.0, 11),
+    "cube64_L5": WorkloadConfig("cube64_L5", 64, 64, 5, 1.4, 2.8, 12, True, 0, (0.2, 2.0), 4, 40.0, 12),
+    "cube128x64_L4": WorkloadConfig("cube128x64_L4", 128, 64, 4, 1.4, 2.8, 15, True, 0, (0.2, 2.0), 3, 30.0, 13),
 }
 
 
