@@ -7,7 +7,7 @@ so the cube's rank is below L; curved power-law spectra with emission lines), it
 visibilities are simulated with the library's Phi on a Gaussian-density uv
 coverage scaled per channel, and noise is added at the given InSNR.  Each method
 then runs on the GPU from a zero state; every (re)weighted problem is solved
-until the relative variation beta of Step 23 falls below `--tol` (checked every
+until the relative variation beta of Algorithm 2 falls below `--tol` (checked every
 100 iterations, at most `--iters` iterations per problem):
 
 * LR, JAS, LRJAS: one PD solve with all weights 1 (Sec. 4.2, eq:min-lr,

@@ -95,7 +95,7 @@ typedef struct {
  * wbar: device real [D][ny][nx] l2,1 weights (NULL = ones), copied.
  * w: host double [L] nuclear weights paired with singular values in
  *    decreasing order (NULL = ones), copied.
- * adaptive_eps: nonzero enables Steps 13-19 with lam1..lam3, vartheta_bar
+ * adaptive_eps: nonzero enables the adaptive l2 bounds (Sec. 3.6) with lam1..lam3, vartheta_bar
  *    (Appendix A: 5e-4, 0.01, 0.618, 100).
  * prior: the regularisation of the minimisation task (Sec. 2.3, Sec. 4.2):
  *    HS_PRIOR_LRJAS  low rankness + joint average sparsity (eq:min; reweighted by
@@ -231,7 +231,7 @@ hs_status hs_psi(hs_ctx* ctx, const void* C, void* X);
  * are shrunk by max(||a|| - t*wbar, 0)/||a||.  wbar: real [D][ny][nx] or NULL (ones). */
 hs_status hs_prox_l21(hs_ctx* ctx, void* A, const void* wbar, double t);
 
-/* Algorithm 2 Steps 7-8: A_d <- (I - S^{l21}_{wbar mu D})(A_d + Psi_d^dagger Xt) in place,
+/* Algorithm 2, l2,1 dual: A_d <- (I - S^{l21}_{wbar mu D})(A_d + Psi_d^dagger Xt) in place,
  * and, when At_sum is not NULL, At_sum = sum_d Psi_d A_d (real [L][ny][nx]). */
 hs_status hs_dual_l21(hs_ctx* ctx, void* A, const void* Xt, const void* wbar, double mu, void* At_sum);
 
@@ -241,13 +241,13 @@ hs_status hs_dual_l21(hs_ctx* ctx, void* A, const void* Xt, const void* wbar, do
  * the singular values of the input in decreasing order.  Synchronising. */
 hs_status hs_prox_nuclear(hs_ctx* ctx, void* X, const double* w, double* sigma_out);
 
-/* Algorithm 2 Step 5: P <- (I - S*_w)(P + Xt) in place. */
+/* Algorithm 2, nuclear dual: P <- (I - S*_w)(P + Xt) in place. */
 hs_status hs_dual_nuclear(hs_ctx* ctx, void* P, const void* Xt, const double* w);
 
-/* Algorithm 2 Steps 4, 10, 11 for every block (l, b): v_l^b <- the
+/* Algorithm 2, data-fidelity dual, for every block (l, b): v_l^b <- the
  * preconditioned data-fidelity dual update from Xt (eq:md with the ellipsoid
  * projection solved exactly).  v: complex [sum M_l] caller order, in place.
- * When adj_out is not NULL it receives Re Phi^dagger v_new (Steps 12, 20; real [L][ny][nx]). */
+ * When adj_out is not NULL it receives Re Phi^dagger v_new (the primal data term; real [L][ny][nx]). */
 hs_status hs_dual_data(hs_ctx* ctx, void* v, const void* Xt, void* adj_out);
 
 /* Prox of the indicator of B(y_l^b, eps_l^b) in the metric U_l^b (eq:prox,
@@ -283,28 +283,28 @@ hs_status hs_pd_init(hs_ctx* ctx, const hs_pd_params* params);
  * iterations (vartheta) = 0; the eigen-solver warm start is reset too. */
 hs_status hs_pd_set_state(hs_ctx* ctx, const hs_state_ptrs* st);
 hs_status hs_pd_get_state(hs_ctx* ctx, const hs_state_ptrs* st);
-/* n iterations of Algorithm 2 (Steps 3-23).  The first call captures one
+/* n iterations of Algorithm 2.  The first call captures one
  * iteration into a HIP graph that later calls replay. */
 hs_status hs_pd_iterate(hs_ctx* ctx, int32_t n);
-/* beta of the last iteration (Step 23), and per-block residual norms rho
- * (Step 13, host [n_blocks], may be NULL) and bounds eps (host [n_blocks],
+/* beta of the last iteration (relative variation of X), and per-block residual norms rho
+ * (host [n_blocks], may be NULL) and bounds eps (host [n_blocks],
  * may be NULL).  Synchronising. */
 hs_status hs_pd_stats(hs_ctx* ctx, double* beta, double* rho, double* eps);
 /* Diagnostics: phases of one iteration, in execution order. */
 enum {
-    HS_PH_FFT_FWD = 0,   /* Z and F of Xt (Step 4) */
-    HS_PH_DEGRID,        /* Theta G and the dual pre-step (Step 10), per-run FP64 sums */
-    HS_PH_ROOTS,         /* per-bin sums and per-block projection roots (Steps 11, 13-19) */
-    HS_PH_DUAL_APPLY,    /* v update (Step 11) */
-    HS_PH_GRID,          /* G^T Theta^T v (Step 12) */
-    HS_PH_FFT_ADJ,       /* F^H and Z^T, real part (Step 20 data term) */
-    HS_PH_GRAM,          /* L x L Gram of P + Xt (Step 5) */
-    HS_PH_EIG,           /* FP64 eigen-decomposition and W (Step 5) */
-    HS_PH_BACKPROJ,      /* P <- (P + Xt) W (Step 5) */
-    HS_PH_PSI_ADJ,       /* Psi^dagger Xt (Step 7) */
-    HS_PH_L21,           /* l2,1 dual update (Step 7) */
-    HS_PH_PSI,           /* sum_d Psi_d A_d (Steps 8, 20) */
-    HS_PH_PRIMAL,        /* Steps 20-23 */
+    HS_PH_FFT_FWD = 0,   /* Z and F of Xt */
+    HS_PH_DEGRID,        /* Theta G and the data-dual step, per-run FP64 sums */
+    HS_PH_ROOTS,         /* per-bin sums, per-block projection roots, adaptive bounds */
+    HS_PH_DUAL_APPLY,    /* v update (the projection) */
+    HS_PH_GRID,          /* G^T Theta^T v */
+    HS_PH_FFT_ADJ,       /* F^H and Z^T, real part (the primal data term) */
+    HS_PH_GRAM,          /* L x L Gram of P + Xt (nuclear dual) */
+    HS_PH_EIG,           /* FP64 eigen-decomposition and W (nuclear dual) */
+    HS_PH_BACKPROJ,      /* P <- (P + Xt) W (nuclear dual) */
+    HS_PH_PSI_ADJ,       /* Psi^dagger Xt (l2,1 dual) */
+    HS_PH_L21,           /* l2,1 dual update */
+    HS_PH_PSI,           /* sum_d Psi_d A_d (the primal sparsity term) */
+    HS_PH_PRIMAL,        /* primal update and beta */
     HS_NPHASES
 };
 /* Runs n eager iterations of Algorithm 2 with HIP events between the phases

@@ -3,13 +3,13 @@
 Readings taken (paper silent or ambiguous):
 * one iteration consumes (X^{t-1}, X~^{t-1}, P, A_d, v_l^b) and returns the next
   state; dual updates use only iterate t-1 (Algorithm 2 runs them side by side);
-* Step 20's data term: channel l's adjoint lands in column l (the selection
+* the primal step's data term: channel l's adjoint lands in column l (the selection
   k_l^dagger of the adjoint in the dual problem is implied);
 * kappa1 = 1, kappa2 = 1/||Psi^dagger||_S^2 = 1/D, kappa3 = 1/||U^{1/2} Phi||_S^2
   (Sec. 3.4); the norm is the largest eigenvalue of x -> Re Phi^dag U Phi x over
   real images, by power iteration (max over channels: Phi is block diagonal);
 * tau = 0.33 by default (the paper requires 0 < tau < 1/3);
-* adaptive l2 bounds (Steps 13-19) use the Appendix A constants and are off by
+* adaptive l2 bounds (Sec. 3.6) use the Appendix A constants and are off by
   default (simulation mode, Sec. 4.1);
 * reweighting (Algorithm 1, eq:weights-l21, eq:weights-n): gamma and gamma_bar
   start at 1 and are multiplied by a fixed factor (0.8 by default) after each
@@ -127,7 +127,7 @@ def step_sizes(prob: Problem, prm: Params, phi_norm2: float):
 
 
 def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_parts: bool = False) -> State:
-    """One iteration of Algorithm 2 (Steps 3-23)."""
+    """One iteration of Algorithm 2."""
     k1, k2, k3 = kappa
     L = prob.L
     wbar = prm.wbar if prm.wbar is not None else np.ones((prob.D, prob.ny, prob.nx))
@@ -137,9 +137,9 @@ def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_par
 
     use_nuc = prm.prior in ("lrjas", "lr")
     use_sp = prm.prior in ("lrjas", "jas", "sara")
-    # Step 5: low rankness dual
+    # low rankness dual
     P = prox.dual_nuclear(st.P, Xt, w, method="svd") if use_nuc else st.P
-    # Steps 6-8: joint average sparsity duals (or per-channel l1 for SARA) and their synthesis
+    # joint average sparsity duals (or per-channel l1 for SARA) and their synthesis
     if use_sp:
         PsiXt = wavelets.psi_adj(Xt, prob.levels, prob.n_db)
         if prm.prior == "sara":
@@ -149,33 +149,33 @@ def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_par
         At_sum = wavelets.psi(A, prob.levels)
     else:
         A, At_sum = st.A, np.zeros_like(Xt)
-    # Steps 3-4 and 9-12: data fidelity duals, per (l, b)
+    # data fidelity duals, per (l, b)
     v_new, lams, rho = [], [], []
     eps_new = [e.copy() for e in st.eps] if st.eps is not None else [np.array(e) for e in prob.eps]
     vth_new = [t_.copy() for t_ in st.vartheta] if st.vartheta is not None else [np.zeros(len(e), np.int64) for e in prob.eps]
     data_adj = np.zeros_like(Xt)
     for l in range(L):
-        Phix = nufft.phi(Xt[l], prob.uv[l], prob.theta[l])        # Theta G u_l (Steps 4 and 10)
-        vbar = st.v[l] + prob.u[l] * Phix                           # Step 10
+        Phix = nufft.phi(Xt[l], prob.uv[l], prob.theta[l])        # Theta G F Z x~_l
+        vbar = st.v[l] + prob.u[l] * Phix                           # dual step
         vl = np.empty_like(vbar)
         lam_l, rho_l = [], []
         bp = prob.block_ptr[l]
         for b in range(len(bp) - 1):
             s = slice(bp[b], bp[b + 1])
             e_prev = st.eps[l][b] if st.eps is not None else prob.eps[l][b]
-            vl[s], lam = prox.dual_data_block(vbar[s], prob.y[l][s], prob.u[l][s], e_prev)   # Step 11
+            vl[s], lam = prox.dual_data_block(vbar[s], prob.y[l][s], prob.u[l][s], e_prev)   # projection (eq:md)
             lam_l.append(lam)
-            r = float(np.linalg.norm(prob.y[l][s] - Phix[s]))                                # Step 13
+            r = float(np.linalg.norm(prob.y[l][s] - Phix[s]))                                # residual norm
             rho_l.append(r)
             if prm.adaptive_eps and (st.beta < prm.lam1) and (t - vth_new[l][b] > prm.vartheta_bar) \
-                    and (abs(r - e_prev) / e_prev > prm.lam2):                               # Step 14
-                eps_new[l][b] = prm.lam3 * r + (1 - prm.lam3) * e_prev                       # Step 15
-                vth_new[l][b] = t                                                            # Step 16
+                    and (abs(r - e_prev) / e_prev > prm.lam2):                               # bound-update test
+                eps_new[l][b] = prm.lam3 * r + (1 - prm.lam3) * e_prev                       # new bound
+                vth_new[l][b] = t                                                            # its iteration
         v_new.append(vl)
         lams.append(np.array(lam_l))
         rho.append(np.array(rho_l))
-        data_adj[l] = nufft.phi_adj(vl, prob.uv[l], prob.theta[l], prob.ny, prob.nx)   # Steps 12, 20
-    # Steps 20-23: primal update
+        data_adj[l] = nufft.phi_adj(vl, prob.uv[l], prob.theta[l], prob.ny, prob.nx)   # adjoint of the data dual
+    # primal update
     G = (k1 * P if use_nuc else 0.0) + k2 * At_sum + k3 * data_adj
     X = prox.proj_pos(st.X - prm.tau * G)
     Xt_new = 2.0 * X - st.X

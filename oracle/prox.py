@@ -2,14 +2,14 @@
 
 * proj_pos         : eq:proj-plus, componentwise projection onto R_+ (of Re x).
 * prox_l21         : eq:prox-L21, row-wise soft-thresholding of length-L rows.
-* dual_l21         : Algorithm 2 Step 7, A <- (I - S^{l21}_{w mu ||Psi^dag||^2})(A + Psi_d^dag X~).
+* dual_l21         : Algorithm 2, l2,1 dual: A <- (I - S^{l21}_{w mu ||Psi^dag||^2})(A + Psi_d^dag X~).
 * prox_nuclear_*   : eq:prox-L*, singular-value soft-thresholding, by SVD (the
                      definition) and by the L x L Gram matrix (the route the
                      GPU takes).
-* dual_nuclear     : Algorithm 2 Step 5, P <- (I - S*_w)(P + X~).
+* dual_nuclear     : Algorithm 2, nuclear dual: P <- (I - S*_w)(P + X~).
 * proj_ball_precond: prox of the l2-ball indicator in the metric U (eq:prox),
                      i.e. the ellipsoid projection of Sec. 3.3, solved exactly.
-* dual_data_block  : Algorithm 2 Step 11 via the Moreau identity eq:md.
+* dual_data_block  : Algorithm 2, data-dual projection via the Moreau identity eq:md.
 
 Readings (paper silent):
 * the nuclear weights w_j pair with the singular values sorted in decreasing
@@ -39,7 +39,7 @@ def prox_l21(Z: np.ndarray, t: np.ndarray | float, axis: int = 1) -> np.ndarray:
 
 
 def dual_l21(A: np.ndarray, PsiXt: np.ndarray, wbar: np.ndarray, mu: float, psi_norm2: float) -> np.ndarray:
-    """Algorithm 2 Step 7 for all d at once.
+    """The l2,1 dual update of Algorithm 2 for all d at once.
 
     A, PsiXt: [D][L][ny][nx]; a row is the length-L vector at fixed (d, y, x);
     wbar: [D][ny][nx].  Returns Z - S(Z) with Z = A + PsiXt and threshold
@@ -55,7 +55,7 @@ def soft_threshold(Z: np.ndarray, t) -> np.ndarray:
 
 
 def dual_l1(A: np.ndarray, PsiXt: np.ndarray, wbar: np.ndarray, mu: float, psi_norm2: float) -> np.ndarray:
-    """Step 7 for the SARA variant: the weighted l1 norm of each channel's
+    """The same dual for the SARA variant: the weighted l1 norm of each channel's
     coefficients in place of the l2,1 norm (Sec. 4.2).  A, PsiXt: [D][L][ny][nx];
     wbar: [D][ny][nx] (shared by the channels).  Returns Z - soft(Z) with
     Z = A + PsiXt and threshold mu * wbar * psi_norm2, element by element."""
@@ -105,7 +105,7 @@ def prox_nuclear_gram(X: np.ndarray, w: np.ndarray) -> tuple[np.ndarray, np.ndar
 
 
 def dual_nuclear(P: np.ndarray, Xt: np.ndarray, w: np.ndarray, method: str = "svd") -> np.ndarray:
-    """Algorithm 2 Step 5: P <- (I - S*_w)(P + X~)."""
+    """The nuclear dual of Algorithm 2: P <- (I - S*_w)(P + X~)."""
     Z = P + Xt
     if method == "svd":
         return Z - prox_nuclear_svd(Z, w)[0]
@@ -158,7 +158,7 @@ def proj_ball_precond(c: np.ndarray, y: np.ndarray, u: np.ndarray, eps: float):
 
 
 def dual_data_block(vbar: np.ndarray, y: np.ndarray, u: np.ndarray, eps: float):
-    """Algorithm 2 Step 11: v = U^{1/2}(I - P_E)(U^{-1/2} vbar) = vbar - U q, q = prox(U^{-1} vbar).
+    """The data-dual projection of Algorithm 2: v = U^{1/2}(I - P_E)(U^{-1/2} vbar) = vbar - U q, q = prox(U^{-1} vbar).
 
     Follows from eq:md with zeta = 1 and the metric U.  Returns (v, lambda).
     """

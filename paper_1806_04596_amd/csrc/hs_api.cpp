@@ -105,7 +105,7 @@ static void upload(void* dst, const std::vector<V>& src) {
     if (!src.empty()) (void)hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
 }
 
-// Algorithm 2's initial values: t = 0, beta = 1 (Step 14 cannot fire before a
+// Algorithm 2's initial values: t = 0, beta = 1 (the adaptive-bound test cannot fire before a
 // real iteration), the l2 bounds given by hs_set_data and their last-update
 // iterations vartheta = 0.
 static void restart_counters(hs_ctx* c) {
@@ -221,7 +221,8 @@ struct PhaseMarks {
     }
 };
 
-// Steps 4, 10, 11 on dual v (grid order, in place); Step 12 + F^H Z^T into adj if given.
+// Data-fidelity dual of Algorithm 2 on v (grid order, in place); its adjoint G^T Theta^T
+// and F^H Z^T into adj if given.
 template <typename T>
 static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const PhaseMarks& pm = PhaseMarks(),
                            bool fft_fwd = true, hipEvent_t after_degrid = nullptr) {
@@ -326,16 +327,16 @@ static void pd_iter_impl(hs_ctx* c, const PhaseMarks& pm = PhaseMarks()) {
     Dev& d = c->d;
     T* Xt = (T*)d.Xt;
     pm.mark(c, 0);
-    // data fidelity (Steps 3-4, 9-12) -> img0 = Re Phi^dag v
+    // data fidelity -> img0 = Re Phi^dag v
     dual_data_impl<T>(c, (cplx<T>*)d.v, Xt, (T*)d.img0, pm);
-    // low rankness (Step 5); a prior that is off still records its phase marks
+    // low rankness; a prior that is off still records its phase marks
     const bool nuc = use_nuclear(c), sp = use_sparsity(c);
     if (nuc) dual_nuclear_impl<T>(c, (T*)d.P, Xt, pm);
     else for (int k = HS_PH_GRAM; k <= HS_PH_BACKPROJ; ++k) pm.mark(c, k + 1);
-    // joint average sparsity (Steps 6-8) -> img1 = sum_d Psi_d A_d
+    // joint average sparsity -> img1 = sum_d Psi_d A_d
     if (sp) dual_l21_impl<T>(c, (T*)d.A, Xt, (const T*)d.wbar, c->mu, (T*)d.img1, pm);
     else for (int k = HS_PH_PSI_ADJ; k <= HS_PH_PSI; ++k) pm.mark(c, k + 1);
-    // primal (Steps 20-23)
+    // primal update
     launch_primal<T>(c, sp ? (const T*)d.img1 : nullptr, (const T*)d.img0, nuc);
     pm.mark(c, HS_PH_PRIMAL + 1);
 }

@@ -94,7 +94,7 @@ struct Dev {
     int32_t* blk_bin_ptr = nullptr;// [nblk+1]
     double* blk_eps = nullptr;     // [nblk]
     double* blk_lambda = nullptr;  // [nblk]
-    double* blk_rho2 = nullptr;    // [nblk] ||y - Phi Xt||^2 (Step 13)
+    double* blk_rho2 = nullptr;    // [nblk] ||y - Phi Xt||^2 (residual norms, Sec. 3.6)
     int32_t* blk_vartheta = nullptr; // [nblk]
     double* run_sum = nullptr;     // [nruns][2] (|d|^2, |y - Phi Xt|^2)
     int32_t* bin_run_ptr = nullptr;// [nbins+1]

@@ -1,4 +1,4 @@
-// Primal update (Algorithm 2, Steps 20-23), FP64 reductions, power-iteration
+// Primal update (Algorithm 2), FP64 reductions, power-iteration
 // helpers (Sec. 3.4 step sizes) and the reweighting of Algorithm 1
 // (eq:weights-l21).
 #include "hs_internal.h"
@@ -30,7 +30,7 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
     return s;
 }
 
-// Steps 20-23: G = k1 P + k2 At + k3 D (P or At null: that prior is off);
+// Primal update: G = k1 P + k2 At + k3 D (P or At null: that prior is off);
 // X <- max(X - tau G, 0); Xt <- 2X_new - X_old;
 // FP64 partial sums of ||X_new - X_old||^2 and ||X_new||^2 per block (fixed grid).
 // 16 bytes of T.
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_primal(T* __restrict__ X, T* __restrict
     }
 }
 
-// beta (Step 23) into scal[0]; iteration counter scal[1] += 1.  One wave:
+// beta (the relative variation of Algorithm 2) into scal[0]; iteration counter scal[1] += 1.  One wave:
 // lane-strided partial sums, then a fixed butterfly (deterministic).
 __global__ void k_finish_beta(const double* __restrict__ part, double* __restrict__ scal, int nparts) {
     const int lane = threadIdx.x;

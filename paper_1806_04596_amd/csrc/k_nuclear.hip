@@ -1,5 +1,5 @@
 // Nuclear-norm proximity operator through the L x L Gram matrix (eq:prox-L*,
-// Algorithm 2 Step 5).
+// Algorithm 2, nuclear-norm dual).
 //
 //  * Gram C = Z^T Z of the N x L matrix Z (= P + Xt, column l = channel l): FP64
 //    MFMA (v_mfma_f64_16x16x4f64) on 64-pixel slabs staged in LDS; inputs in the

@@ -1,5 +1,6 @@
 // Measurement operator Phi_l = Theta_l G_l F Z and its adjoint (Sec. 2.1, eq:inverse),
-// and the data-fidelity dual update (Algorithm 2, Steps 4 and 10-12, eq:md).
+// and the data-fidelity dual update (Algorithm 2: forward operator, dual step, its
+// ellipsoid projection by eq:md, and the adjoint).
 //
 // Design (gfx950):
 //  * Hermitian half plane: the image is real, so its transform at -k is the
@@ -550,7 +551,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     }
 }
 
-// Phase 1 of the data dual (Steps 4 and 10): g = Theta G u, d = v + U (g - y)
+// Phase 1 of the data dual (Algorithm 2): g = Theta G u, d = v + U (g - y)
 // (= vbar - U y) stored in v; per-run FP64 sums of |d|^2 and |y - g|^2.
 template <typename T>
 __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
@@ -645,8 +646,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 // Root of f(lam) = sum_c S_c/(u_c + lam)^2 - eps^2 per block (exact ellipsoid
 // projection, eq:prox with the metric U), one wave per block; Newton from
-// lam = 0, monotone for this convex decreasing f.  Also Step 13 (rho) and
-// Steps 14-19 (adaptive bound) when enabled.
+// lam = 0, monotone for this convex decreasing f.  Also the residual norms rho
+// and the adaptive l2 bounds of Algorithm 2 (Sec. 3.6) when enabled.
 __global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const double* __restrict__ S,
                               const double* __restrict__ bin_u, double* __restrict__ eps, double* __restrict__ lam_out,
                               double* __restrict__ rho2, int32_t* __restrict__ vartheta, const double* __restrict__ scal,
@@ -707,7 +708,7 @@ __global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const dou
     }
 }
 
-// Phase 2 (Step 11): v = d * lam/(u + lam) (= vbar - U q); lam = inf gives v = d.
+// Phase 2 (the projection of Algorithm 2): v = d * lam/(u + lam) (= vbar - U q); lam = inf gives v = d.
 template <typename T>
 __global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ uprec, const int32_t* __restrict__ vbin,
                              const int32_t* __restrict__ bin_block, const double* __restrict__ lam, int64_t M) {

@@ -1,5 +1,5 @@
 // SARA dictionary Psi = (Dirac, db1..db8) (Sec. 2.3) and the joint-average-sparsity
-// l2,1 dual update (Algorithm 2, Steps 7-8; eq:prox-L21).
+// l2,1 dual update (Algorithm 2; eq:prox-L21).
 //
 // Each Daubechies basis is the periodised orthonormal 2-D Mallat transform.  One
 // launch covers every (basis, channel) pair of one level and one direction, so a
@@ -359,7 +359,7 @@ __global__ void k_psi_sum(const T* __restrict__ Y, const T* __restrict__ C0, T* 
 }
 
 // l2,1 on rows of length L at fixed (d, pixel):
-//  mode 0 (dual, Step 7): Z = A + Psi_d^dag Xt, A <- Z min(1, thr*wbar/||Z||);
+//  mode 0 (dual update): Z = A + Psi_d^dag Xt, A <- Z min(1, thr*wbar/||Z||);
 //  mode 1 (prox, eq:prox-L21): Z = A, A <- Z max(||Z|| - thr*wbar, 0)/||Z||;
 //  mode 2 (dual of the per-channel weighted l1 of the SARA variant, eq:min-sara):
 //         Z = A + Psi_d^dag Xt, A <- clip(Z, -thr*wbar, thr*wbar) element by element.

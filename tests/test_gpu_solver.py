@@ -1,4 +1,4 @@
-"""Algorithm 1 (reweighted outer loop) and Algorithm 2 Steps 13-19 (adaptive
+"""Algorithm 1 (reweighted outer loop) and the adaptive bounds of Algorithm 2 (adaptive
 l2 bounds) through the C-ABI, against the FP64 oracle."""
 import numpy as np
 import pytest
@@ -52,7 +52,7 @@ def test_reweighted_solve_vs_oracle(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adaptive_bounds_vs_oracle(dtype):
-    """Steps 13-19 with lam1 large enough and vartheta_bar = 1 so that the bounds
+    """Adaptive bounds with lam1 large enough and vartheta_bar = 1 so that the bounds
     move within a few iterations: eps, rho and X follow the oracle."""
     cfg, inp, op, prob = _fresh("cube64_L5", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)

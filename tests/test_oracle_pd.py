@@ -53,7 +53,7 @@ def test_one_iteration_pieces_and_positivity():
     kap = pd.step_sizes(prob, prm, nrm)
     out = pd.pd_iteration(st, prob, prm, kap, return_parts=True)
     assert np.all(out.X >= 0)
-    # recompute Step 20 with the pieces and an independent U = I-free path check
+    # recompute the primal gradient with the pieces and an independent U = I-free path check
     G = kap[0] * out.P + kap[1] * out.extra["At_sum"] + kap[2] * out.extra["data_adj"]
     assert np.allclose(out.X, np.maximum(st.X - prm.tau * G, 0))
     assert np.allclose(out.Xt, 2 * out.X - st.X)
@@ -120,7 +120,7 @@ def test_constraints_approached_at_convergence():
 
 
 def test_adaptive_eps_update_rule():
-    # Steps 13-19 with constants from Appendix A: force the update conditions
+    # adaptive bounds with constants from Appendix A: force the update conditions
     prob, X0 = _tiny_problem(4)
     prm = pd.Params(mu=0.05, adaptive_eps=True, vartheta_bar=0)
     st = pd.zero_state(prob)
