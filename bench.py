@@ -62,8 +62,8 @@ def algorithmic_bytes(cfg, M: int, r: int = 4):
         # grid read + per visibility: cell(4) frac(2r) theta(r) u(r) y(c) v(c) bin(4) write v(c)
         "degrid": L * Gc * c + M * (4 + 2 * r + r + r + c + c + 4 + c),
         "roots": 0,
-        # v read/write, u, bin
-        "dual_apply": M * (2 * c + r + 4),
+        # v read/write, bin (the factor of each bin comes from the root solver)
+        "dual_apply": M * (2 * c + 4),
         # per visibility cell, frac, v, theta; grid written once
         "grid": M * (4 + 2 * r + c + r) + L * Gc * c,
         "fft_adj": L * (Gc * c + 2 * Hc * c + N * r),

@@ -55,7 +55,6 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.glist, c->h_glist.size() * 4, base);
     k.take(d.gpartial, (size_t)c->npartial * GB * GB * cx, base);
     k.take(d.bin_u, (size_t)c->nbins * 8, base);
-    k.take(d.bin_block, (size_t)c->nbins * 4, base);
     k.take(d.blk_bin_ptr, (size_t)(c->nblk + 1) * 4, base);
     k.take(d.blk_eps, (size_t)c->nblk * 8, base);
     k.take(d.blk_lambda, (size_t)c->nblk * 8, base);
@@ -66,6 +65,7 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.run_slot, (size_t)c->nruns * 4, base);
     k.take(d.chunk_run, c->h_chunk_run.size() * 4, base);
     k.take(d.bin_S, (size_t)c->nbins * 16, base);
+    k.take(d.bin_f, (size_t)c->nbins * 8, base);
     k.take(d.grid, (size_t)c->L * c->Ky * c->Wg * cx, base);
     k.take(d.H, (size_t)c->L * c->ny * c->Hs * cx, base);
     k.take(d.tw_x, (size_t)c->Kx * cx, base);
@@ -135,7 +135,6 @@ static hs_status bind_impl(hs_ctx* c) {
     upload(d.splits, c->splits);
     upload(d.glist, c->h_glist);
     upload(d.bin_u, c->h_bin_u);
-    upload(d.bin_block, c->h_bin_block);
     upload(d.blk_bin_ptr, c->h_blk_bin_ptr);
     upload(d.blk_eps, c->h_blk_eps);
     upload(d.bin_run_ptr, c->h_bin_run_ptr);

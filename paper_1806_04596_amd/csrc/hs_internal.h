@@ -90,7 +90,6 @@ struct Dev {
     void* gpartial = nullptr;      // [npartial][T*T] complex
     // bins / blocks
     double* bin_u = nullptr;       // [nbins]
-    int32_t* bin_block = nullptr;  // [nbins]
     int32_t* blk_bin_ptr = nullptr;// [nblk+1]
     double* blk_eps = nullptr;     // [nblk]
     double* blk_lambda = nullptr;  // [nblk]
@@ -101,6 +100,7 @@ struct Dev {
     int32_t* run_slot = nullptr;   // [nruns] slot of each run's sums in run_sum (grouped by bin)
     int32_t* chunk_run = nullptr;  // [chunks] first run of each DEG_CHUNK-visibility chunk
     double* bin_S = nullptr;       // [nbins][2]
+    double* bin_f = nullptr;       // [nbins] lam/(u + lam) of each bin's visibilities (v = f d)
     // FFT
     void* grid = nullptr;          // [L][Ky][Kx] complex
     void* H = nullptr;             // [L][ny][Kx] complex
@@ -173,7 +173,7 @@ struct hs_ctx {
     int kb_terms = 0;
     std::vector<double> kb_c;          // power-series coefficients
     // host staging of the plan (uploaded at bind)
-    std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_bin_block, h_blk_bin_ptr, h_bin_run_ptr, h_run_slot;
+    std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_blk_bin_ptr, h_bin_run_ptr, h_run_slot;
     std::vector<int32_t> h_chunk_run;
     std::vector<double> h_frac, h_y, h_theta, h_u, h_bin_u, h_blk_eps;
     std::vector<int64_t> h_pos_of;     // caller global index -> grid position

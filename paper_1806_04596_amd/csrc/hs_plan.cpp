@@ -345,7 +345,6 @@ hs_status build_plan(hs_ctx* c) {
     c->h_perm.assign(M, 0);
     c->h_pos_of.assign(M, 0);
     c->h_bin_u.clear();
-    c->h_bin_block.clear();
     c->h_blk_bin_ptr.assign(1, 0);
     c->h_blk_eps.clear();
     c->dunits.clear();
@@ -380,7 +379,6 @@ hs_status build_plan(hs_ctx* c) {
         for (int b = 0; b < ch.nb; ++b) {
             for (int cl = 0; cl < o.C; ++cl) {
                 c->h_bin_u.push_back(o.class_val[cl]);
-                c->h_bin_block.push_back(c->blk_off[l] + b);
             }
             c->h_blk_bin_ptr.push_back((int32_t)(bin_base + (int64_t)(b + 1) * o.C));
             c->h_blk_eps.push_back(ch.eps[b]);

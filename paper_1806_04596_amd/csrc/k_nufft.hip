@@ -649,7 +649,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 // lam = 0, monotone for this convex decreasing f.  Also the residual norms rho
 // and the adaptive l2 bounds of Algorithm 2 (Sec. 3.6) when enabled.
 __global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const double* __restrict__ S,
-                              const double* __restrict__ bin_u, double* __restrict__ eps, double* __restrict__ lam_out,
+                              const double* __restrict__ bin_u, double* __restrict__ bin_f, int u_f32,
+                              double* __restrict__ eps, double* __restrict__ lam_out,
                               double* __restrict__ rho2, int32_t* __restrict__ vartheta, const double* __restrict__ scal,
                               int nblk, int adaptive, double lam1, double lam2, double lam3, int vbar) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -693,6 +694,12 @@ __global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const dou
             }
         }
     }
+    // the projection's factor for each bin of the block, v = d lam/(u + lam), with u as
+    // the visibilities hold it (rounded to FP32 in an FP32 context)
+    for (int k = c0 + lane; k < c1; k += 64) {
+        const double uu = u_f32 ? (double)(float)bin_u[k] : bin_u[k];
+        bin_f[k] = lam == 0.0 ? 0.0 : (isinf(lam) ? 1.0 : lam / (uu + lam));
+    }
     if (lane == 0) {
         lam_out[wave] = lam;
         rho2[wave] = r2;
@@ -709,16 +716,14 @@ __global__ void k_block_roots(const int32_t* __restrict__ blk_bin_ptr, const dou
 }
 
 // Phase 2 (the projection of Algorithm 2): v = d * lam/(u + lam) (= vbar - U q); lam = inf gives v = d.
+// The factor is the same for all visibilities of a bin (one u per bin, one lam per
+// block), so k_block_roots forms it once per bin.
 template <typename T>
-__global__ void k_dual_apply(cplx<T>* __restrict__ v, const T* __restrict__ uprec, const int32_t* __restrict__ vbin,
-                             const int32_t* __restrict__ bin_block, const double* __restrict__ lam, int64_t M) {
+__global__ void k_dual_apply(cplx<T>* __restrict__ v, const int32_t* __restrict__ vbin, const double* __restrict__ bin_f,
+                             int64_t M) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const double la = lam[bin_block[vbin[i]]];
-    T f;
-    if (la == 0.0) f = T(0);
-    else if (isinf(la)) f = T(1);
-    else f = (T)(la / ((double)uprec[i] + la));
+    const T f = (T)bin_f[vbin[i]];
     cplx<T> d = v[i];
     d.re *= f;
     d.im *= f;
@@ -1019,16 +1024,15 @@ void launch_bins_and_roots(hs_ctx* c) {
     k_bin_reduce<<<nblocks(c->nbins * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr, c->d.run_sum,
                                                                        c->d.bin_S, (int)c->nbins);
     k_block_roots<<<nblocks(c->nblk * 64, 256), 256, 0, c->stream>>>(
-        c->d.blk_bin_ptr, c->d.bin_S, c->d.bin_u, c->d.blk_eps, c->d.blk_lambda, c->d.blk_rho2, c->d.blk_vartheta,
+        c->d.blk_bin_ptr, c->d.bin_S, c->d.bin_u, c->d.bin_f, c->dtype == HS_F32 ? 1 : 0, c->d.blk_eps, c->d.blk_lambda,
+        c->d.blk_rho2, c->d.blk_vartheta,
         c->d.scal, (int)c->nblk, c->adaptive ? 1 : 0, c->lam1, c->lam2, c->lam3, c->vartheta_bar);
 }
 
 template <typename T>
 void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
     if (c->Mtot == 0) return;
-    k_dual_apply<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(v, (const T*)c->d.vis_u,
-                                                                    c->d.vis_bin, c->d.bin_block, c->d.blk_lambda,
-                                                                    c->Mtot);
+    k_dual_apply<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(v, c->d.vis_bin, c->d.bin_f, c->Mtot);
 }
 
 template <typename T>
