@@ -113,9 +113,10 @@ def _counter_means(path: str, counter: str):
     return {k: sums[k] / counts[k] for k in sums}, counts
 
 
-def write_traffic(fetch_csv: str, write_csv: str):
-    """profiles/traffic.json: HBM bytes per launch of each phase's kernel, each counter
-    scaled by what it reads for a device-to-device copy of CALIB_BYTES (read once, write once)."""
+def write_traffic(fetch_csv: str, write_csv: str, workload: str):
+    """profiles/traffic.json: HBM bytes per launch of each phase's kernel on `workload`, each
+    counter scaled by what it reads for a device-to-device copy of CALIB_BYTES (read once,
+    write once)."""
     fm, fc = _counter_means(fetch_csv, "FETCH_SIZE")
     wm, wc = _counter_means(write_csv, "WRITE_SIZE")
     if COPY_KERNEL not in fm or COPY_KERNEL not in wm:
@@ -124,6 +125,7 @@ def write_traffic(fetch_csv: str, write_csv: str):
     f_scale = CALIB_BYTES / (fm[COPY_KERNEL] * 1024 * fc[COPY_KERNEL] / 3)
     w_scale = CALIB_BYTES / (wm[COPY_KERNEL] * 1024 * wc[COPY_KERNEL] / 3)
     out = {"_reference": {"kernel": COPY_KERNEL, "bytes": CALIB_BYTES, "fetch_scale": f_scale, "write_scale": w_scale,
+                          "workload": workload,
                           "note": "counter KiB per dispatch x 1024 x scale = HBM bytes per dispatch"}}
     for phase, kern in PHASE_KERNEL.items():
         if kern in fm and kern in wm:
@@ -137,13 +139,16 @@ def write_traffic(fetch_csv: str, write_csv: str):
     print(path)
 
 
-def traffic_from_profiles(kernel_phase: str, src_file: str):
-    """Measured HBM bytes per iteration for a phase from committed rocprofv3
-    counter summaries (profiles/traffic.json); None if absent or stale."""
+def traffic_from_profiles(kernel_phase: str, src_file: str, workload: str):
+    """Measured HBM bytes per launch of a phase's kernel from committed rocprofv3
+    counter summaries (profiles/traffic.json); None if absent, stale (kernel source
+    changed since) or taken on another workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
+        if t.get("_reference", {}).get("workload") != workload:
+            return None
         ent = t.get(kernel_phase)
         if not ent or ent.get("src_hash") != source_hash(src_file):
             return None
@@ -207,7 +212,7 @@ def calib_copy():
 def main():
     args = parse()
     if args.traffic_from:
-        write_traffic(*args.traffic_from)
+        write_traffic(*args.traffic_from, args.workload)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus above 1 is not supported"}))
@@ -286,7 +291,7 @@ def main():
     # work-group, latency-bound, and overlapped with the other branches in the graph)
     dom = max((k for k in phases if ab.get(k, 0) > 0), key=lambda k: phases[k])
     ach = ab[dom] / (phases[dom] * 1e-3) / 1e9 if ab[dom] > 0 else 0.0
-    traffic = traffic_from_profiles(dom, PHASE_SRC[dom])
+    traffic = traffic_from_profiles(dom, PHASE_SRC[dom], cfg.name)
     roofline = {"bound": "hbm", "kernel": f"{PHASE_KERNEL.get(dom, dom)} ({dom} phase)", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes": int(ab[dom]), "avg_ms": round(phases[dom], 4)}
