@@ -39,6 +39,13 @@ def test_order_definition_properties():
             assert np.all(key[seg] == k)
         # regions: offsets within the tile
         assert np.all((cx % T)[reg % 3 == 0] < 3) and np.all((cx % T)[reg % 3 == 2] >= T - 4)
+        # within a (tile, region): by bin, then by the cell's raster position in the
+        # tile, then by input index (strictly increasing tuples)
+        b, _, _ = binning.bins(u, bp, M)
+        for k in range(len(rptr) - 1):
+            seg = perm[rptr[k]:rptr[k + 1]]
+            keys = [(int(b[m]), int((cy[m] % T) * T + cx[m] % T), int(m)) for m in seg]
+            assert all(keys[i] < keys[i + 1] for i in range(len(keys) - 1))
 
 
 def test_region_reaches_neighbour_exactly():
