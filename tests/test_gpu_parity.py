@@ -104,6 +104,26 @@ def test_psi_parity(name, dtype):
     check_rel_pc(Xs, wavelets.psi(Cr), TOL[dtype], "Xs")
 
 
+# Image shapes at the edges of the wavelet kernels' tiling: 16^2 (2 x 2 at the
+# coarsest of 4 levels, smaller than one tile at every level) and strongly
+# non-square images (one tile row or column at the coarse levels).
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(16, 16), (2048, 256), (256, 2048)])
+def test_psi_parity_shapes(shape, dtype):
+    nx, ny = shape
+    over = dict(nx=nx, ny=ny, L=2, m_per_chan=500, n_blocks=1)
+    cfg, inp, _ = oracle_case("cube64_L4", **over)
+    prob, _, _ = gpu_case("cube64_L4", dtype, **over)
+    X = inp["X0"] + 0.05 * _seeded(inp["X0"].shape, 7)
+    C = host(prob.psi_adj(to_dev(prob, X)))
+    ref = wavelets.psi_adj(X)
+    for d in range(9):
+        check_rel_pc(C[d], ref[d], TOL[dtype], "C[d]")
+    Cr = _seeded(ref.shape, 8)
+    Xs = host(prob.psi(to_dev(prob, Cr)))
+    check_rel_pc(Xs, wavelets.psi(Cr), TOL[dtype], "Xs")
+
+
 def test_psi_perfect_reconstruction_f64():
     prob, _, _ = gpu_case("cube128x64_L4", "f64")
     X = _seeded((prob.L, prob.ny, prob.nx), 7)
