@@ -239,7 +239,7 @@ def _run_gpu_iteration(prob, st, prm, w, n=1):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4", "cube128x64_L4"])
 def test_pd_one_iteration_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
