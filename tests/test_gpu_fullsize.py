@@ -1,6 +1,7 @@
-"""Parity at the benchmark size: the 512x512x60 uneven cube (16.3 M
-visibilities, 8 blocks per channel) in FP32, built and launched exactly as
-the benchmark builds it (automatic tile, batched kernels, graph replay).
+"""Parity at full size: the benchmark's 512x512x60 uneven cube (16.3 M
+visibilities, 8 blocks per channel) and the 1024x1024x32 cube (33.5 M
+visibilities, 4 blocks per channel), in FP32, built and launched exactly as the
+benchmark builds them (automatic tile, batched kernels, graph replay).
 
 Channel-separable outputs (Phi, Phi^dagger, Psi^dagger, Psi, the data-fidelity
 dual) are compared element by element with the oracle on sampled channels
@@ -16,12 +17,10 @@ from gpu_cases import TOL, check_rel, host, rel, split, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-CFG = W.CONFIGS["cube512_L60"]
-
-
-@pytest.fixture(scope="module")
-def big():
+@pytest.fixture(scope="module", params=["cube512_L60", "cube1024_L32"])
+def big(request):
     from paper_1806_04596_amd.workload import build_problem
+    CFG = W.CONFIGS[request.param]
     inp = W.make_problem_inputs(CFG)
     counts = np.array([len(u) for u in inp["uv"]])
     S = sorted({int(np.argmin(counts)), CFG.L // 2, int(np.argmax(counts))})
@@ -31,8 +30,9 @@ def big():
     sub = {"X0": inp["X0"][S], "uv": [inp["uv"][l] for l in S], "block_ptr": [inp["block_ptr"][l] for l in S],
            "noise": [inp["noise"][l] for l in S]}
     op, _ = pd.build_problem(CFG.scaled(L=len(S)), sub)
-    print(f"cube512_L60 full size: sampled channels {S}, M = {prob.M}", flush=True)
-    return {"inp": inp, "prob": prob, "S": S, "op": op}
+    print(f"{CFG.name} full size: sampled channels {S}, M = {prob.M}", flush=True)
+    yield {"cfg": CFG, "inp": inp, "prob": prob, "S": S, "op": op}
+    prob.close()
 
 
 def test_phi_full_size(big):
@@ -46,6 +46,7 @@ def test_phi_full_size(big):
 
 
 def test_phi_adj_full_size(big):
+    CFG = big["cfg"]
     prob, S, op = big["prob"], big["S"], big["op"]
     rng = np.random.default_rng(41)
     y = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
@@ -57,6 +58,7 @@ def test_phi_adj_full_size(big):
 
 
 def test_psi_full_size(big):
+    CFG = big["cfg"]
     prob, S = big["prob"], big["S"]
     rng = np.random.default_rng(42)
     X = rng.standard_normal((CFG.L, CFG.ny, CFG.nx))
@@ -73,6 +75,7 @@ def test_psi_full_size(big):
 
 
 def test_dual_nuclear_full_size(big):
+    CFG = big["cfg"]
     prob, inp = big["prob"], big["inp"]
     rng = np.random.default_rng(43)
     X = inp["X0"] + 0.01 * inp["X0"].max() * rng.standard_normal(inp["X0"].shape)
@@ -105,6 +108,7 @@ def test_pd_iteration_full_size_properties(big):
     """Graph replay (as timed by the benchmark) equals the eager iteration bit
     for bit; X >= 0; X~ = 2X - X_prev exactly; beta = ||X - X_prev|| / ||X||;
     the FP32 iteration agrees with the FP64 instantiation to 1e-5."""
+    CFG = big["cfg"]
     import torch
     from paper_1806_04596_amd.workload import build_problem
     prob, inp = big["prob"], big["inp"]

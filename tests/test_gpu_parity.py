@@ -11,7 +11,7 @@ from gpu_cases import TOL, check_rel, check_rel_pc, gpu_case, host, oracle_case,
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["cube32_L3", "cube64_L5", "cube128x64_L4", "cube64_L4"]
+CASES = ["cube32_L3", "cube64_L5", "cube128x64_L4", "cube64_L4", "cube256_L15"]
 DTYPES = ["f64", "f32"]
 
 
@@ -90,7 +90,7 @@ def test_phi_vs_nudft_f64():
 
 # --------------------------------------------------------------- wavelets
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["cube32_L3", "cube128x64_L4", "cube64_L4"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube128x64_L4", "cube64_L4", "cube256_L15"])
 def test_psi_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
@@ -239,7 +239,7 @@ def _run_gpu_iteration(prob, st, prm, w, n=1):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4", "cube128x64_L4"])
+@pytest.mark.parametrize("name", ["cube32_L3", "cube64_L5", "cube64_L4", "cube128x64_L4", "cube256_L15"])
 def test_pd_one_iteration_parity(name, dtype):
     cfg, inp, op = oracle_case(name)
     prob, _, _ = gpu_case(name, dtype)
