@@ -216,13 +216,20 @@ def dirty_cube(prob: Problem) -> np.ndarray:
     return out
 
 
-def mu_hat(prob: Problem) -> float:
-    """mu = ||X_dirty||_* / ||Psi^dag X_dirty||_{2,1} (Sec. 2.3)."""
-    Xd = dirty_cube(prob)
-    nuc = float(np.sum(np.linalg.svd(Xd.reshape(prob.L, -1).T, compute_uv=False)))
-    C = wavelets.psi_adj(Xd, prob.levels, prob.n_db)
+def mu_of_cube(X: np.ndarray, levels: int = 4, n_db: int = 8) -> float:
+    """||X||_* / ||Psi^dag X||_{2,1} of a cube [L][ny][nx] (Sec. 2.3): the nuclear norm of
+    the N x L matrix (column l = channel l) over the sum of the l2 norms of the
+    length-L rows of the coefficients."""
+    L = X.shape[0]
+    nuc = float(np.sum(np.linalg.svd(X.reshape(L, -1).T, compute_uv=False)))
+    C = wavelets.psi_adj(X, levels, n_db)
     l21 = float(np.sum(np.sqrt(np.sum(C * C, axis=1))))
     return nuc / l21 if l21 > 0 else 0.0
+
+
+def mu_hat(prob: Problem) -> float:
+    """mu_hat = ||X_dirty||_* / ||Psi^dag X_dirty||_{2,1} (Sec. 2.3)."""
+    return mu_of_cube(dirty_cube(prob), prob.levels, prob.n_db)
 
 
 def reweight(X: np.ndarray, prob: Problem, gamma: float, gamma_bar: float):

@@ -148,17 +148,120 @@ def test_reweighting_formulas():
     assert np.all(np.diff(w) >= 0)          # non-decreasing: S*_w is then the exact prox
 
 
-def test_mu_hat_definition():
-    prob, X0 = _tiny_problem(6)
+def _rank_two_cube(ny, nx, h1, h2):
+    """X = 1 h1^T + C h2^T with C the checkerboard (-1)^(i+j): the two spatial
+    factors are orthogonal, have norm sqrt(N), and their coefficients in every
+    Daubechies basis are known in closed form (a constant keeps only its coarsest
+    low-pass band, each coefficient 2^levels; the checkerboard keeps only its
+    finest diagonal band, each coefficient 2, since H(pi) = 0 and |G(pi)| = sqrt(2))."""
+    one = np.ones((ny, nx))
+    chk = (-1.0) ** np.add.outer(np.arange(ny), np.arange(nx))
+    return np.einsum("l,yx->lyx", h1, one) + np.einsum("l,yx->lyx", h2, chk)
+
+
+def test_mu_of_cube_closed_form_rank_two():
+    """mu = ||X||_* / ||Psi^dag X||_{2,1} (Sec. 2.3) on a cube whose singular values
+    and coefficient rows are known exactly.  With a = ||h1||, b = ||h2|| (h1 _|_ h2):
+    singular values sqrt(N) a and sqrt(N) b; Dirac rows all have norm sqrt(a^2 + b^2);
+    each of the 8 wavelet bases has N/256 coarse rows of norm 16 a and N/4 diagonal
+    rows of norm 2 b (4 levels)."""
+    ny, nx, L = 32, 64, 5
+    N = ny * nx
+    rng = np.random.default_rng(21)
+    h1 = rng.standard_normal(L)
+    h2 = rng.standard_normal(L)
+    h2 -= h1 * (h1 @ h2) / (h1 @ h1)
+    a, b = np.linalg.norm(h1), np.linalg.norm(h2)
+    X = _rank_two_cube(ny, nx, h1, h2)
+    nuc = np.sqrt(N) * (a + b)
+    l21 = N * np.sqrt(a * a + b * b) + 8 * (N / 256) * 16 * a + 8 * (N / 4) * 2 * b
+    assert pd.mu_of_cube(X) == pytest.approx(nuc / l21, rel=1e-12)
+    # a Frobenius norm in place of the nuclear norm, or the l1 norm of the entries in place
+    # of the l2,1 norm of the rows, would give a different value on this cube
+    assert abs(np.sqrt(N) * np.hypot(a, b) / l21 - nuc / l21) > 1e-3 * nuc / l21
+
+
+def test_dirty_cube_against_brute_force_adjoint():
+    """x_dirty_l = Re Phi_l^dag y_l / max PSF_l (Sec. 4.3).  The exact adjoint of the
+    NUDFT is Re sum_m theta_m y_m e^{+2 pi i u_m . p}, and the PSF of a unit source at
+    the phase centre peaks there at sum_m theta_m^2 (its NUDFT is theta_m): both by
+    brute force, to the interpolation kernel's accuracy."""
+    prob, _ = _tiny_problem(6)
     Xd = pd.dirty_cube(prob)
-    # PSF peak normalisation: Phi^dag Phi delta scaled to peak 1
-    delta = np.zeros((16, 16)); delta[8, 8] = 1
-    psf = nufft.phi_adj(nufft.phi(delta, prob.uv[0], prob.theta[0]), prob.uv[0], prob.theta[0], 16, 16)
-    assert np.allclose(Xd[0], nufft.phi_adj(prob.y[0], prob.uv[0], prob.theta[0], 16, 16) / psf.max())
-    mu = pd.mu_hat(prob)
-    nuc = np.linalg.svd(Xd.reshape(2, -1).T, compute_uv=False).sum()
-    l21 = np.sqrt((wavelets.psi_adj(Xd) ** 2).sum(axis=1)).sum()
-    assert mu == pytest.approx(nuc / l21)
+    py = np.arange(prob.ny) - prob.ny // 2
+    px = np.arange(prob.nx) - prob.nx // 2
+    for l in range(prob.L):
+        uv, th, y = prob.uv[l], prob.theta[l], prob.y[l]
+        ey = np.exp(2j * np.pi * uv[:, 1:2] * py[None, :])
+        ex = np.exp(2j * np.pi * uv[:, 0:1] * px[None, :])
+        adj = np.einsum("m,my,mx->yx", th * y, ey, ex).real
+        ref = adj / np.sum(th * th)
+        assert np.linalg.norm(Xd[l] - ref) <= 2e-6 * np.linalg.norm(ref)
+    # the PSF of a unit source at the phase centre peaks there, at sum theta^2
+    delta = np.zeros((prob.ny, prob.nx)); delta[prob.ny // 2, prob.nx // 2] = 1.0
+    psf = nufft.phi_adj(nufft.phi(delta, prob.uv[0], prob.theta[0]), prob.uv[0], prob.theta[0], prob.ny, prob.nx)
+    assert np.unravel_index(np.argmax(psf), psf.shape) == (prob.ny // 2, prob.nx // 2)
+    assert psf.max() == pytest.approx(np.sum(prob.theta[0] ** 2), rel=1e-6)
+
+
+def test_mu_hat_is_mu_of_the_dirty_cube():
+    prob, _ = _tiny_problem(7)
+    assert pd.mu_hat(prob) == pd.mu_of_cube(pd.dirty_cube(prob), prob.levels, prob.n_db)
+
+
+def test_solve_without_reweights_is_the_plain_iteration():
+    """Algorithm 1 with no reweight is T iterations of Algorithm 2 from the given state."""
+    prob, X0 = _tiny_problem(8)
+    prm = pd.Params(mu=0.02)
+    kap = (1.0, 1.0 / 9.0, 1e-3)
+    st0 = pd.zero_state(prob)
+    st0.X = X0.copy(); st0.Xt = X0.copy()
+    st_ref = st0
+    for _ in range(4):
+        st_ref = pd.pd_iteration(st_ref, prob, prm, kap)
+    st, prm_out, hist = pd.solve(prob, prm, kap, n_reweights=0, iters_per=4, st=st0)
+    for k in ("X", "Xt", "P", "A"):
+        assert np.array_equal(getattr(st, k), getattr(st_ref, k)), k
+    assert prm_out.w is None and prm_out.wbar is None and hist == [st_ref.beta]
+
+
+def test_solve_gamma_sequence_and_weights(monkeypatch):
+    """The weights the k-th reweight hands to the next solve (eq:weights-l21 and
+    eq:weights-n) with gamma = gamma_bar = factor^(k-1), on an estimate X = 1 h^T whose
+    singular values (sqrt(N) ||h||, then zeros) and coefficient rows (Dirac rows
+    ||h||, coarsest low-pass rows 16 ||h|| in each wavelet basis, every other row 0)
+    are known exactly.  The PD iteration is replaced by a stub returning that X."""
+    prob, _ = _tiny_problem(9, L=2)
+    N = prob.nx * prob.ny
+    h = np.array([0.8, 0.3])
+    Xr = _rank_two_cube(prob.ny, prob.nx, h, np.zeros(2))
+    seen = []
+
+    def stub(st, prob_, prm_, kappa, return_parts=False):
+        seen.append((None if prm_.w is None else prm_.w.copy(), None if prm_.wbar is None else prm_.wbar.copy()))
+        out = pd.State(X=Xr.copy(), Xt=Xr.copy(), P=st.P, A=st.A, v=st.v, eps=st.eps, vartheta=st.vartheta,
+                       beta=0.5, t=st.t + 1)
+        return out
+
+    monkeypatch.setattr(pd, "pd_iteration", stub)
+    factor = 0.7
+    pd.solve(prob, pd.Params(mu=0.1), (1.0, 1.0 / 9.0, 1e-3), n_reweights=3, iters_per=2, factor=factor)
+    assert len(seen) == 8
+    assert seen[0][0] is None and seen[1][0] is None          # unit weights before the first reweight
+    hn = np.linalg.norm(h)
+    s1 = np.sqrt(N) * hn
+    coarse = np.zeros((prob.ny, prob.nx), bool)
+    coarse[: prob.ny // 16, : prob.nx // 16] = True
+    for k in (1, 2, 3):
+        g = factor ** (k - 1)
+        for call in (2 * k, 2 * k + 1):
+            w, wbar = seen[call]
+            assert w[0] == pytest.approx(g / (g + s1), rel=1e-12)
+            assert np.allclose(w[1:], 1.0, rtol=0, atol=1e-12)     # zero singular values
+            assert np.allclose(wbar[0], g / (g + hn), rtol=1e-12)      # Dirac rows
+            for d in range(1, 9):
+                assert np.allclose(wbar[d][coarse], g / (g + 16 * hn), rtol=1e-10)
+                assert np.allclose(wbar[d][~coarse], 1.0, rtol=0, atol=1e-10)
 
 
 def test_workload_measurements_and_bounds():
