@@ -53,6 +53,17 @@ enum { HS_NORM_PHI_PRECOND = 0, HS_NORM_PSI = 1 };
 
 typedef struct hs_ctx hs_ctx;
 
+/* Precision of the L x L Gram matrix of the nuclear-norm prox (eq:prox-L*, taken
+ * through the Gram matrix; the eigen-decomposition is FP64 in every mode):
+ *   HS_GRAM_F64        FP64 products of the exactly widened inputs (default);
+ *   HS_GRAM_F32        FP32 products, FP32 accumulation within a slab of pixels,
+ *                      FP64 across slabs;
+ *   HS_GRAM_BF16_SPLIT each input z = z_hi + z_lo with both parts in BF16 and
+ *                      C ~ Z_hi^T Z_hi + Z_hi^T Z_lo + Z_lo^T Z_hi (the correction
+ *                      terms are the one refinement step), FP32 accumulation within
+ *                      a slab, FP64 across slabs. */
+enum { HS_GRAM_F64 = 0, HS_GRAM_F32 = 1, HS_GRAM_BF16_SPLIT = 2 };
+
 /* Problem description (Sec. 2.1 data model, Sec. 2.3 dictionary).
  * nx, ny: image size; powers of two in 16..2048 (and >= 2^levels).
  * L: number of channels (1..64).
@@ -62,7 +73,8 @@ typedef struct hs_ctx hs_ctx;
  *   the dictionary is Dirac + db1..db{n_db} (D = 1 + n_db bases).
  * dtype: HS_F32 or HS_F64.  tile: gridding tile edge (0 = automatic; else a
  *   power of two in 8..32 with 2*nx/tile >= 3 and 2*ny/tile >= 3).
- * device: HIP device ordinal; stream: hipStream_t (NULL = default stream). */
+ * device: HIP device ordinal; stream: hipStream_t (NULL = default stream).
+ * gram_mode: HS_GRAM_F64 / HS_GRAM_F32 / HS_GRAM_BF16_SPLIT (above). */
 typedef struct {
     int32_t nx, ny, L;
     int32_t oversamp;
@@ -73,6 +85,7 @@ typedef struct {
     int32_t tile;
     int32_t device;
     void* stream;
+    int32_t gram_mode;
 } hs_problem_desc;
 
 /* Sizes after hs_plan. */
@@ -92,7 +105,8 @@ typedef struct {
  * kappa1 <= 0 -> 1; kappa2 <= 0 -> 1/D (= 1/||Psi^dagger||_S^2);
  * kappa3 must be > 0 (1/||U^{1/2} Phi||_S^2, see hs_op_norm).
  * tau: primal step, convergence needs tau(k1 + k2 D + k3 ||U^1/2 Phi||^2) < 1.
- * wbar: device real [D][ny][nx] l2,1 weights (NULL = ones), copied.
+ * wbar: device real [D][ny][nx] l2,1 weights, one per coefficient row (NULL = ones),
+ *    copied; for HS_PRIOR_SARA one weight per channel and coefficient, [D][L][ny][nx].
  * w: host double [L] nuclear weights paired with singular values in
  *    decreasing order (NULL = ones), copied.
  * adaptive_eps: nonzero enables the adaptive l2 bounds (Sec. 3.6) with lam1..lam3, vartheta_bar
@@ -103,8 +117,9 @@ typedef struct {
  *    HS_PRIOR_LR     nuclear norm only (eq:min-lr),
  *    HS_PRIOR_JAS    l2,1 norm only (eq:min-js),
  *    HS_PRIOR_SARA   weighted l1 norm of each channel's coefficients, no
- *                    nuclear norm (eq:min-sara; weights wbar shared by the
- *                    channels, so hs_solve does not reweight it).
+ *                    nuclear norm (eq:min-sara: one problem per channel, with
+ *                    weights per channel and coefficient; hs_solve reweights
+ *                    them as SARA's reweighted l1, Sec. 2.3).
  *    A prior that is off leaves its dual (P or A) untouched. */
 enum { HS_PRIOR_LRJAS = 0, HS_PRIOR_LR = 1, HS_PRIOR_JAS = 2, HS_PRIOR_SARA = 3 };
 typedef struct {
@@ -117,35 +132,55 @@ typedef struct {
     int32_t prior;
 } hs_pd_params;
 
-/* Device pointers to a primal-dual state, ctx dtype.  X, Xt, P: [L][ny][nx];
- * A: [D][L][ny][nx]; v: [sum M_l] complex in the caller's visibility order
- * (channel by channel, each in the order given to hs_set_channel).
- * Any member may be NULL (skipped). */
+/* The state of Algorithm 2 (its "Given" line) and the weights of Algorithm 1.
+ * Device pointers, ctx dtype: X, Xt, P: [L][ny][nx]; A: [D][L][ny][nx];
+ * v: [sum M_l] complex in the caller's visibility order (channel by channel,
+ * each in the order given to hs_set_channel); wbar: the sparsity weights
+ * (shape as in hs_pd_params).
+ * Host pointers: eps: double [n_blocks] l2 bounds and vartheta: int32
+ * [n_blocks] iterations of their last update (blocks channel by channel);
+ * scalars: double [2] = (beta, t) of the last iteration; w: double [L]
+ * nuclear weights.
+ * Any member may be NULL: hs_pd_get_state skips it; hs_pd_set_state skips the
+ * arrays and restarts the bookkeeping it is not given (eps from hs_set_data,
+ * vartheta = 0, beta = 1, t = 0) and keeps the current weights. */
 typedef struct {
     void* X;
     void* Xt;
     void* P;
     void* A;
     void* v;
+    double* eps;
+    int32_t* vartheta;
+    double* scalars;
+    void* wbar;
+    double* w;
 } hs_state_ptrs;
 
 /* Outer loop (Algorithm 1).  Each reweight runs iters_per_reweight PD
  * iterations (or stops early when beta < beta_tol, checked every
  * check_every iterations), then updates wbar by eq:weights-l21 and w by
- * eq:weights-n with gamma, gamma_bar starting at 1 and multiplied by
- * gamma_factor after each update.  Warm starts every variable. */
+ * eq:weights-n (SARA: the per-channel l1 weights) with gamma, gamma_bar
+ * starting at gamma0, gamma_bar0 (<= 0 means 1) and multiplied by
+ * gamma_factor after each update.  Warm starts every variable.
+ * reweight_first: nonzero starts with a weight update (from the current X),
+ * which resumes a solve saved after its last block of iterations. */
 typedef struct {
     int32_t n_reweights;
     int32_t iters_per_reweight;
     double gamma_factor;
     double beta_tol;
     int32_t check_every;
+    double gamma0, gamma_bar0;
+    int32_t reweight_first;
 } hs_solve_params;
 
+/* gamma, gamma_bar: the values the next reweight would use (to resume). */
 typedef struct {
     int64_t iterations;
     int32_t reweights;
     double final_beta;
+    double gamma, gamma_bar;
 } hs_report;
 
 /* ---------------------------------------------------------- diagnostics */
@@ -277,10 +312,14 @@ hs_status hs_dirty_mu(hs_ctx* ctx, void* Xd, double* mu);
 /* -------------------------------------------------------------- PD solver */
 /* Sets parameters of Algorithm 2 (does not reset the state). */
 hs_status hs_pd_init(hs_ctx* ctx, const hs_pd_params* params);
-/* Copy a state into / out of the context (device-to-device, on the stream).
- * hs_pd_set_state also restarts Algorithm 2's bookkeeping: iteration count
- * t = 0, beta = 1, the l2 bounds of hs_set_data and their last-update
- * iterations (vartheta) = 0; the eigen-solver warm start is reset too. */
+/* Copy a state into / out of the context (device arrays device-to-device on the
+ * stream; host members synchronously).  hs_pd_set_state restarts the parts of
+ * Algorithm 2's bookkeeping it is not given: iteration count t = 0, beta = 1
+ * (scalars NULL), the l2 bounds of hs_set_data (eps NULL) and their
+ * last-update iterations vartheta = 0 (vartheta NULL); wbar and w replace the
+ * weights of hs_pd_init when given (needs hs_pd_init first).  The
+ * eigen-solver warm start is reset.  Together with hs_report.gamma this saves
+ * and resumes a reweighted solve (Algorithm 1 warm start). */
 hs_status hs_pd_set_state(hs_ctx* ctx, const hs_state_ptrs* st);
 hs_status hs_pd_get_state(hs_ctx* ctx, const hs_state_ptrs* st);
 /* n iterations of Algorithm 2.  The first call captures one

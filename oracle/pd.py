@@ -59,7 +59,7 @@ class Params:
     kappa1: float = 1.0
     kappa2: float | None = None
     kappa3: float | None = None
-    wbar: np.ndarray | None = None   # [D][ny][nx]
+    wbar: np.ndarray | None = None   # [D][ny][nx] ([D][L][ny][nx] for the SARA prior)
     w: np.ndarray | None = None      # [L]
     adaptive_eps: bool = False
     lam1: float = 5e-4
@@ -126,11 +126,59 @@ def step_sizes(prob: Problem, prm: Params, phi_norm2: float):
     return prm.kappa1, k2, k3
 
 
-def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_parts: bool = False) -> State:
-    """One iteration of Algorithm 2."""
+def _map(pool, fn, items):
+    """fn over independent per-channel items, in a process pool when one is given."""
+    return list(pool.map(fn, items)) if pool is not None else [fn(a) for a in items]
+
+
+def _psi_adj_chan(a):
+    x, levels, n_db = a
+    return wavelets.psi_adj(x, levels, n_db)
+
+
+def _psi_chan(a):
+    c, levels = a
+    return wavelets.psi(c, levels)
+
+
+def _data_channel(a):
+    """Data-fidelity dual of one channel (Algorithm 2): dual step, per-block projection
+    (eq:md), residual norms and the adaptive bounds (Sec. 3.6), then the adjoint."""
+    (xt, v, uv, theta, u, y, bp, eps_prev, vth_prev, ny, nx, t, beta_prev, adaptive, lam1, lam2, lam3,
+     vbar_iters) = a
+    Phix = nufft.phi(xt, uv, theta)                               # Theta G F Z x~_l
+    vbar = v + u * Phix                                           # dual step
+    vl = np.empty_like(vbar)
+    eps_new = np.array(eps_prev, dtype=np.float64, copy=True)
+    vth_new = np.array(vth_prev, copy=True)
+    lam_l, rho_l = [], []
+    for b in range(len(bp) - 1):
+        s = slice(bp[b], bp[b + 1])
+        e_prev = eps_prev[b]
+        vl[s], lam = prox.dual_data_block(vbar[s], y[s], u[s], e_prev)   # projection (eq:md)
+        lam_l.append(lam)
+        r = float(np.linalg.norm(y[s] - Phix[s]))                        # residual norm
+        rho_l.append(r)
+        if adaptive and (beta_prev < lam1) and (t - vth_new[b] > vbar_iters) \
+                and (abs(r - e_prev) / e_prev > lam2):                   # bound-update test
+            eps_new[b] = lam3 * r + (1 - lam3) * e_prev                  # new bound
+            vth_new[b] = t                                               # its iteration
+    adj = nufft.phi_adj(vl, uv, theta, ny, nx)                           # adjoint of the data dual
+    return vl, adj, np.array(lam_l), np.array(rho_l), eps_new, vth_new
+
+
+def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_parts: bool = False,
+                 pool=None) -> State:
+    """One iteration of Algorithm 2.  pool: optional executor; the per-channel work
+    (analysis, synthesis, data fidelity) is then mapped over it, channel by channel."""
     k1, k2, k3 = kappa
     L = prob.L
-    wbar = prm.wbar if prm.wbar is not None else np.ones((prob.D, prob.ny, prob.nx))
+    if prm.wbar is not None:
+        wbar = prm.wbar
+    elif prm.prior == "sara":
+        wbar = np.ones((prob.D, L, prob.ny, prob.nx))
+    else:
+        wbar = np.ones((prob.D, prob.ny, prob.nx))
     w = prm.w if prm.w is not None else np.ones(L)
     Xt = st.Xt
     t = st.t + 1
@@ -141,40 +189,28 @@ def pd_iteration(st: State, prob: Problem, prm: Params, kappa: tuple, return_par
     P = prox.dual_nuclear(st.P, Xt, w, method="svd") if use_nuc else st.P
     # joint average sparsity duals (or per-channel l1 for SARA) and their synthesis
     if use_sp:
-        PsiXt = wavelets.psi_adj(Xt, prob.levels, prob.n_db)
+        PsiXt = np.concatenate(_map(pool, _psi_adj_chan, [(Xt[l:l + 1], prob.levels, prob.n_db) for l in range(L)]),
+                               axis=1)
         if prm.prior == "sara":
             A = prox.dual_l1(st.A, PsiXt, wbar, prm.mu, float(prob.D))
         else:
             A = prox.dual_l21(st.A, PsiXt, wbar, prm.mu, float(prob.D))
-        At_sum = wavelets.psi(A, prob.levels)
+        At_sum = np.concatenate(_map(pool, _psi_chan, [(A[:, l:l + 1], prob.levels) for l in range(L)]), axis=0)
     else:
         A, At_sum = st.A, np.zeros_like(Xt)
-    # data fidelity duals, per (l, b)
-    v_new, lams, rho = [], [], []
-    eps_new = [e.copy() for e in st.eps] if st.eps is not None else [np.array(e) for e in prob.eps]
-    vth_new = [t_.copy() for t_ in st.vartheta] if st.vartheta is not None else [np.zeros(len(e), np.int64) for e in prob.eps]
-    data_adj = np.zeros_like(Xt)
-    for l in range(L):
-        Phix = nufft.phi(Xt[l], prob.uv[l], prob.theta[l])        # Theta G F Z x~_l
-        vbar = st.v[l] + prob.u[l] * Phix                           # dual step
-        vl = np.empty_like(vbar)
-        lam_l, rho_l = [], []
-        bp = prob.block_ptr[l]
-        for b in range(len(bp) - 1):
-            s = slice(bp[b], bp[b + 1])
-            e_prev = st.eps[l][b] if st.eps is not None else prob.eps[l][b]
-            vl[s], lam = prox.dual_data_block(vbar[s], prob.y[l][s], prob.u[l][s], e_prev)   # projection (eq:md)
-            lam_l.append(lam)
-            r = float(np.linalg.norm(prob.y[l][s] - Phix[s]))                                # residual norm
-            rho_l.append(r)
-            if prm.adaptive_eps and (st.beta < prm.lam1) and (t - vth_new[l][b] > prm.vartheta_bar) \
-                    and (abs(r - e_prev) / e_prev > prm.lam2):                               # bound-update test
-                eps_new[l][b] = prm.lam3 * r + (1 - prm.lam3) * e_prev                       # new bound
-                vth_new[l][b] = t                                                            # its iteration
-        v_new.append(vl)
-        lams.append(np.array(lam_l))
-        rho.append(np.array(rho_l))
-        data_adj[l] = nufft.phi_adj(vl, prob.uv[l], prob.theta[l], prob.ny, prob.nx)   # adjoint of the data dual
+    # data fidelity duals, per (l, b); channels are independent (Phi is block diagonal)
+    eps_prev = st.eps if st.eps is not None else [np.array(e) for e in prob.eps]
+    vth_prev = st.vartheta if st.vartheta is not None else [np.zeros(len(e), np.int64) for e in prob.eps]
+    args = [(Xt[l], st.v[l], prob.uv[l], prob.theta[l], prob.u[l], prob.y[l], prob.block_ptr[l], eps_prev[l],
+             vth_prev[l], prob.ny, prob.nx, t, st.beta, prm.adaptive_eps, prm.lam1, prm.lam2, prm.lam3,
+             prm.vartheta_bar) for l in range(L)]
+    res = _map(pool, _data_channel, args)
+    v_new = [r_[0] for r_ in res]
+    data_adj = np.stack([r_[1] for r_ in res]) if L else np.zeros_like(Xt)
+    lams = [r_[2] for r_ in res]
+    rho = [r_[3] for r_ in res]
+    eps_new = [r_[4] for r_ in res]
+    vth_new = [r_[5] for r_ in res]
     # primal update
     G = (k1 * P if use_nuc else 0.0) + k2 * At_sum + k3 * data_adj
     X = prox.proj_pos(st.X - prm.tau * G)
@@ -232,9 +268,14 @@ def mu_hat(prob: Problem) -> float:
     return mu_of_cube(dirty_cube(prob), prob.levels, prob.n_db)
 
 
-def reweight(X: np.ndarray, prob: Problem, gamma: float, gamma_bar: float):
-    """eq:weights-l21 and eq:weights-n from the current estimate."""
+def reweight(X: np.ndarray, prob: Problem, gamma: float, gamma_bar: float, prior: str = "lrjas"):
+    """eq:weights-l21 and eq:weights-n from the current estimate.  For the SARA prior
+    (a sequence of weighted l1 problems per channel, Sec. 2.3 and eq:min-sara) the
+    weights are per channel and per coefficient, gamma_bar / (gamma_bar + |coefficient|),
+    and there are no nuclear weights."""
     C = wavelets.psi_adj(X, prob.levels, prob.n_db)
+    if prior == "sara":
+        return gamma_bar / (gamma_bar + np.abs(C)), None   # [D][L][ny][nx]
     rn = np.sqrt(np.sum(C * C, axis=1))                   # [D][ny][nx]
     wbar = gamma_bar / (gamma_bar + rn)
     s = np.linalg.svd(X.reshape(prob.L, -1).T, compute_uv=False)
@@ -245,8 +286,6 @@ def reweight(X: np.ndarray, prob: Problem, gamma: float, gamma_bar: float):
 def solve(prob: Problem, prm: Params, kappa: tuple, n_reweights: int, iters_per: int,
           factor: float = 0.8, st: State | None = None):
     """Algorithm 1: reweighted sequence of Algorithm 2 solves with warm starts."""
-    if prm.prior == "sara" and n_reweights > 0:
-        raise ValueError("reweighting the SARA variant needs per-channel l1 weights, which are not modelled")
     st = zero_state(prob) if st is None else st
     gamma = gamma_bar = 1.0
     prm = Params(**{**prm.__dict__})
@@ -257,13 +296,18 @@ def solve(prob: Problem, prm: Params, kappa: tuple, n_reweights: int, iters_per:
         history.append(st.beta)
         if k == n_reweights:
             break
-        prm.wbar, prm.w = reweight(st.X, prob, gamma, gamma_bar)
+        prm.wbar, prm.w = reweight(st.X, prob, gamma, gamma_bar, prm.prior)
         gamma *= factor
         gamma_bar *= factor
     return st, prm, history
 
 
-def build_problem(cfg, inputs: dict, precond: str = "density") -> Problem:
+def _phi_unit(a):
+    x, uv = a
+    return nufft.phi(x, uv, np.ones(len(uv)))
+
+
+def build_problem(cfg, inputs: dict, precond: str = "density", pool=None) -> Problem:
     """Oracle-side problem from the seeded workload draws: y0 = G F Z X0 (theta = 1),
     noisy data and bounds from ``workloads.make_measurements``, natural weighting
     y = theta * y_raw (Sec. 2.1), preconditioner from the density (or U = I)."""
@@ -271,7 +315,7 @@ def build_problem(cfg, inputs: dict, precond: str = "density") -> Problem:
     from .precond import density_precond
 
     uvs = inputs["uv"]
-    y0 = [nufft.phi(inputs["X0"][l], uvs[l], np.ones(len(uvs[l]))) for l in range(cfg.L)]
+    y0 = _map(pool, _phi_unit, [(inputs["X0"][l], uvs[l]) for l in range(cfg.L)])
     y_raw, theta, eps = make_measurements(y0, inputs["noise"], inputs["block_ptr"], cfg.isnr_db)
     if precond == "density":
         u = [density_precond(uvs[l], cfg.nx, cfg.ny) for l in range(cfg.L)]

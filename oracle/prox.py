@@ -56,11 +56,11 @@ def soft_threshold(Z: np.ndarray, t) -> np.ndarray:
 
 def dual_l1(A: np.ndarray, PsiXt: np.ndarray, wbar: np.ndarray, mu: float, psi_norm2: float) -> np.ndarray:
     """The same dual for the SARA variant: the weighted l1 norm of each channel's
-    coefficients in place of the l2,1 norm (Sec. 4.2).  A, PsiXt: [D][L][ny][nx];
-    wbar: [D][ny][nx] (shared by the channels).  Returns Z - soft(Z) with
-    Z = A + PsiXt and threshold mu * wbar * psi_norm2, element by element."""
+    coefficients in place of the l2,1 norm (Sec. 4.2, eq:min-sara; each channel is its
+    own problem with its own weights).  A, PsiXt, wbar: [D][L][ny][nx].  Returns
+    Z - soft(Z) with Z = A + PsiXt and threshold mu * wbar * psi_norm2, element by element."""
     Z = A + PsiXt
-    return Z - soft_threshold(Z, mu * wbar[:, None] * psi_norm2)
+    return Z - soft_threshold(Z, mu * wbar * psi_norm2)
 
 
 def _as_matrix(X: np.ndarray) -> np.ndarray:

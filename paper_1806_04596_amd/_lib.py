@@ -16,6 +16,7 @@ HS_OK = 0
 HS_F32, HS_F64 = 0, 1
 HS_NORM_PHI_PRECOND, HS_NORM_PSI = 0, 1
 PRIORS = {"lrjas": 0, "lr": 1, "jas": 2, "sara": 3}
+GRAM_MODES = {"f64": 0, "f32": 1, "bf16_split": 2}
 
 STATUS = {0: "HS_OK", -1: "HS_ERR_INVALID_ARG", -2: "HS_ERR_SHAPE", -3: "HS_ERR_DTYPE", -4: "HS_ERR_NOT_PLANNED",
           -5: "HS_ERR_NO_WORKSPACE", -6: "HS_ERR_NONFINITE", -7: "HS_ERR_HIP", -8: "HS_ERR_NOT_CONVERGED"}
@@ -24,7 +25,7 @@ STATUS = {0: "HS_OK", -1: "HS_ERR_INVALID_ARG", -2: "HS_ERR_SHAPE", -3: "HS_ERR_
 class ProblemDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("L", C.c_int32), ("oversamp", C.c_int32), ("J", C.c_int32),
                 ("levels", C.c_int32), ("n_db", C.c_int32), ("dtype", C.c_int32), ("tile", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("gram_mode", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -41,16 +42,20 @@ class PDParams(C.Structure):
 
 
 class StatePtrs(C.Structure):
-    _fields_ = [("X", C.c_void_p), ("Xt", C.c_void_p), ("P", C.c_void_p), ("A", C.c_void_p), ("v", C.c_void_p)]
+    _fields_ = [("X", C.c_void_p), ("Xt", C.c_void_p), ("P", C.c_void_p), ("A", C.c_void_p), ("v", C.c_void_p),
+                ("eps", C.POINTER(C.c_double)), ("vartheta", C.POINTER(C.c_int32)),
+                ("scalars", C.POINTER(C.c_double)), ("wbar", C.c_void_p), ("w", C.POINTER(C.c_double))]
 
 
 class SolveParams(C.Structure):
     _fields_ = [("n_reweights", C.c_int32), ("iters_per_reweight", C.c_int32), ("gamma_factor", C.c_double),
-                ("beta_tol", C.c_double), ("check_every", C.c_int32)]
+                ("beta_tol", C.c_double), ("check_every", C.c_int32), ("gamma0", C.c_double),
+                ("gamma_bar0", C.c_double), ("reweight_first", C.c_int32)]
 
 
 class Report(C.Structure):
-    _fields_ = [("iterations", C.c_int64), ("reweights", C.c_int32), ("final_beta", C.c_double)]
+    _fields_ = [("iterations", C.c_int64), ("reweights", C.c_int32), ("final_beta", C.c_double),
+                ("gamma", C.c_double), ("gamma_bar", C.c_double)]
 
 
 P = C.c_void_p

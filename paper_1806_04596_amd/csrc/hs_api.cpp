@@ -80,7 +80,7 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.A, (size_t)c->D * LN * r, base);
     k.take(d.coef, (size_t)std::max(c->n_db, 1) * LN * r, base);
     k.take(d.wtmp, (size_t)std::max(c->n_db, 1) * LN * r, base);
-    k.take(d.wbar, (size_t)c->D * c->N * r, base);
+    k.take(d.wbar, (size_t)c->D * LN * r, base);   // per channel for the SARA prior
     k.take(d.filt, (size_t)MAX_DB * 32 * r, base);
     k.take(d.gram_part, (size_t)NGRAM * MAX_L * MAX_L * 8, base);
     k.take(d.gram, (size_t)MAX_L * MAX_L * 8, base);
@@ -108,12 +108,20 @@ static void upload(void* dst, const std::vector<V>& src) {
 // Algorithm 2's initial values: t = 0, beta = 1 (the adaptive-bound test cannot fire before a
 // real iteration), the l2 bounds given by hs_set_data and their last-update
 // iterations vartheta = 0.
-static void restart_counters(hs_ctx* c) {
-    launch_fill<double>(c->stream, c->d.scal, 1.0, 1);
-    launch_fill<double>(c->stream, c->d.scal + 1, 0.0, 1);
-    launch_fill<int32_t>(c->stream, c->d.blk_vartheta, 0, c->nblk);
-    if (c->nblk)
+static void restart_counters(hs_ctx* c, bool scalars = true, bool vartheta = true, bool eps = true) {
+    if (scalars) {
+        launch_fill<double>(c->stream, c->d.scal, 1.0, 1);
+        launch_fill<double>(c->stream, c->d.scal + 1, 0.0, 1);
+    }
+    if (vartheta) launch_fill<int32_t>(c->stream, c->d.blk_vartheta, 0, c->nblk);
+    if (eps && c->nblk)
         hipMemcpyAsync(c->d.blk_eps, c->h_blk_eps.data(), (size_t)c->nblk * 8, hipMemcpyHostToDevice, c->stream);
+}
+
+// Elements of the sparsity weights for the current prior: one per coefficient row,
+// or per channel and coefficient (SARA).
+static int64_t wbar_elems(const hs_ctx* c) {
+    return (int64_t)c->D * c->N * (c->prior == HS_PRIOR_SARA ? c->L : 1);
 }
 
 template <typename T>
@@ -182,7 +190,7 @@ static hs_status bind_impl(hs_ctx* c) {
     launch_fill<T>(c->stream, (T*)d.P, T(0), LN);
     launch_fill<T>(c->stream, (T*)d.A, T(0), (int64_t)c->D * LN);
     launch_fill<T>(c->stream, (T*)d.v, T(0), 2 * c->Mtot);
-    launch_fill<T>(c->stream, (T*)d.wbar, T(1), (int64_t)c->D * c->N);
+    launch_fill<T>(c->stream, (T*)d.wbar, T(1), (int64_t)c->D * LN);
     launch_fill<double>(c->stream, d.scal, 0.0, 64);
     restart_counters(c);
     launch_fill<double>(c->stream, d.blk_lambda, 0.0, c->nblk);
@@ -398,7 +406,7 @@ static hs_status dirty_mu_impl(hs_ctx* c, T* Xd, double* mu) {
     launch_chan_scale<T>(c, X, d.chan_nrm);
     if (!mu) return HS_OK;
     // nuclear norm from the FP64 eigen-decomposition of the L x L Gram matrix
-    launch_gram<T>(c, X, (const T*)nullptr);
+    launch_gram<T>(c, X, (const T*)nullptr, true);
     launch_eig(c, 0);
     std::vector<double> sg(MAX_L);
     hipMemcpyAsync(sg.data(), d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
@@ -473,6 +481,10 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
     *out = nullptr;
     const hs_problem_desc& d = *desc;
     if (d.dtype != HS_F32 && d.dtype != HS_F64) return fail(nullptr, HS_ERR_DTYPE, "dtype must be HS_F32 or HS_F64");
+    if (d.gram_mode < HS_GRAM_F64 || d.gram_mode > HS_GRAM_BF16_SPLIT)
+        return fail(nullptr, HS_ERR_INVALID_ARG, "gram_mode must be HS_GRAM_F64, HS_GRAM_F32 or HS_GRAM_BF16_SPLIT");
+    if (d.dtype == HS_F64 && d.gram_mode != HS_GRAM_F64)
+        return fail(nullptr, HS_ERR_DTYPE, "an FP64 context forms its Gram matrix in FP64 (HS_GRAM_F64)");
     if (d.oversamp != 2) return fail(nullptr, HS_ERR_INVALID_ARG, "oversamp must be 2");
     if (d.J != KB_J) return fail(nullptr, HS_ERR_INVALID_ARG, "J must be 8");
     if (d.L < 1 || d.L > MAX_L) return fail(nullptr, HS_ERR_SHAPE, "L must be in 1..64");
@@ -501,6 +513,7 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
     c->D = 1 + d.n_db;
     c->levels = d.levels;
     c->dtype = d.dtype;
+    c->gram_mode = d.gram_mode;
     c->rsz = d.dtype == HS_F32 ? 4 : 8;
     c->stream = (hipStream_t)d.stream;
     c->device = d.device;
@@ -826,8 +839,8 @@ hs_status hs_pd_init(hs_ctx* c, const hs_pd_params* p) {
     c->prior = p->prior;
     s = upload_w(c, p->w);
     if (s) return s;
-    if (p->wbar) hipMemcpyAsync(c->d.wbar, p->wbar, (size_t)c->D * c->N * c->rsz, hipMemcpyDeviceToDevice, c->stream);
-    else HS_DISPATCH(c, launch_fill<T>(c->stream, (T*)c->d.wbar, T(1), (int64_t)c->D * c->N));
+    if (p->wbar) hipMemcpyAsync(c->d.wbar, p->wbar, (size_t)wbar_elems(c) * c->rsz, hipMemcpyDeviceToDevice, c->stream);
+    else HS_DISPATCH(c, launch_fill<T>(c->stream, (T*)c->d.wbar, T(1), (int64_t)c->D * c->L * c->N));
     c->pd_ready = true;
     c->graph_valid = false;
     return launched(c, "hs_pd_init");
@@ -837,14 +850,37 @@ hs_status hs_pd_set_state(hs_ctx* c, const hs_state_ptrs* st) {
     hs_status s = ready(c);
     if (s) return s;
     if (!st) return fail(c, HS_ERR_INVALID_ARG, "null state");
+    if ((st->wbar || st->w) && !c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "weights need hs_pd_init first");
+    if (st->eps)
+        for (int64_t b = 0; b < c->nblk; ++b)
+            if (!std::isfinite(st->eps[b]) || st->eps[b] < 0) return fail(c, HS_ERR_NONFINITE, "eps must be >= 0");
+    if (st->scalars && !(std::isfinite(st->scalars[0]) && st->scalars[1] >= 0))
+        return fail(c, HS_ERR_INVALID_ARG, "scalars: beta finite and t >= 0");
     const size_t LN = (size_t)c->L * c->N * c->rsz;
     if (st->X) hipMemcpyAsync(c->d.X, st->X, LN, hipMemcpyDeviceToDevice, c->stream);
     if (st->Xt) hipMemcpyAsync(c->d.Xt, st->Xt, LN, hipMemcpyDeviceToDevice, c->stream);
     if (st->P) hipMemcpyAsync(c->d.P, st->P, LN, hipMemcpyDeviceToDevice, c->stream);
     if (st->A) hipMemcpyAsync(c->d.A, st->A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
     if (st->v) HS_DISPATCH(c, launch_gather_user<T>(c, (const cplx<T>*)st->v, (cplx<T>*)c->d.v, false));
+    if (st->wbar) hipMemcpyAsync(c->d.wbar, st->wbar, (size_t)wbar_elems(c) * c->rsz, hipMemcpyDeviceToDevice, c->stream);
     launch_eig_reset(c);   // a new state starts the eigen-solver history afresh (reproducible runs)
-    restart_counters(c);
+    restart_counters(c, !st->scalars, !st->vartheta, !st->eps);
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_pd_set_state");
+    if (s) return s;
+    if (st->eps && c->nblk)
+        s = hip_check(c, hipMemcpy(c->d.blk_eps, st->eps, (size_t)c->nblk * 8, hipMemcpyHostToDevice), "eps");
+    if (!s && st->vartheta && c->nblk)
+        s = hip_check(c, hipMemcpy(c->d.blk_vartheta, st->vartheta, (size_t)c->nblk * 4, hipMemcpyHostToDevice),
+                      "vartheta");
+    if (!s && st->scalars) {
+        s = hip_check(c, hipMemcpy(c->d.scal, st->scalars, 2 * 8, hipMemcpyHostToDevice), "scalars");
+        c->t_iter = (int64_t)st->scalars[1];
+    }
+    if (s) return s;
+    if (st->w) {
+        s = upload_w(c, st->w);
+        if (s) return s;
+    }
     return launched(c, "hs_pd_set_state");
 }
 
@@ -858,6 +894,18 @@ hs_status hs_pd_get_state(hs_ctx* c, const hs_state_ptrs* st) {
     if (st->P) hipMemcpyAsync(st->P, c->d.P, LN, hipMemcpyDeviceToDevice, c->stream);
     if (st->A) hipMemcpyAsync(st->A, c->d.A, LN * c->D, hipMemcpyDeviceToDevice, c->stream);
     if (st->v) HS_DISPATCH(c, launch_scatter_user<T>(c, (const cplx<T>*)c->d.v, (cplx<T>*)st->v));
+    if (st->wbar) hipMemcpyAsync(st->wbar, c->d.wbar, (size_t)wbar_elems(c) * c->rsz, hipMemcpyDeviceToDevice, c->stream);
+    if (st->eps || st->vartheta || st->scalars) {
+        s = hip_check(c, hipStreamSynchronize(c->stream), "hs_pd_get_state");
+        if (!s && st->eps && c->nblk)
+            s = hip_check(c, hipMemcpy(st->eps, c->d.blk_eps, (size_t)c->nblk * 8, hipMemcpyDeviceToHost), "eps");
+        if (!s && st->vartheta && c->nblk)
+            s = hip_check(c, hipMemcpy(st->vartheta, c->d.blk_vartheta, (size_t)c->nblk * 4, hipMemcpyDeviceToHost),
+                          "vartheta");
+        if (!s && st->scalars) s = hip_check(c, hipMemcpy(st->scalars, c->d.scal, 2 * 8, hipMemcpyDeviceToHost), "scalars");
+        if (s) return s;
+    }
+    if (st->w) std::copy(c->w_host.begin(), c->w_host.begin() + c->L, st->w);
     return launched(c, "hs_pd_get_state");
 }
 
@@ -971,19 +1019,49 @@ hs_status hs_get_diag(hs_ctx* c, double* out, int32_t n) {
     return HS_OK;
 }
 
+// Algorithm 1's weight update from the current estimate: eq:weights-l21 and eq:weights-n
+// (SARA: the per-channel reweighted l1).
+static hs_status solve_reweight(hs_ctx* c, double gamma, double gamma_bar) {
+    const bool sara = c->prior == HS_PRIOR_SARA;
+    HS_DISPATCH(c, {
+        launch_psi_adj<T>(c, (const T*)c->d.X, nullptr);
+        if (sara) {
+            launch_reweight_l1<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
+        } else {
+            launch_reweight_l21<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
+            launch_gram<T>(c, (const T*)c->d.X, nullptr, true);
+            launch_eig(c, 0);
+        }
+    });
+    hs_status s = launched(c, "hs_solve reweight");
+    if (s || sara) return s;
+    std::vector<double> sg(MAX_L);
+    hipMemcpyAsync(sg.data(), c->d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_solve");
+    if (s) return s;
+    std::vector<double> w(c->L);
+    for (int l = 0; l < c->L; ++l) w[l] = gamma / (gamma + sg[l]);
+    return upload_w(c, w.data());
+}
+
 hs_status hs_solve(hs_ctx* c, const hs_solve_params* p, void* X_out, hs_report* rep) {
     hs_status s = ready(c);
     if (s) return s;
     if (!p || p->iters_per_reweight < 1 || p->n_reweights < 0 || !(p->gamma_factor > 0))
         return fail(c, HS_ERR_INVALID_ARG, "bad solve parameters");
     if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
-    if (c->prior == HS_PRIOR_SARA && p->n_reweights > 0)
-        return fail(c, HS_ERR_INVALID_ARG, "reweighting the SARA prior needs per-channel weights (not modelled)");
-    double gamma = 1.0, gamma_bar = 1.0, beta = 0.0;
+    double gamma = p->gamma0 > 0 ? p->gamma0 : 1.0, gamma_bar = p->gamma_bar0 > 0 ? p->gamma_bar0 : 1.0, beta = 0.0;
     int64_t total = 0;
+    int nrw = 0;
     const int check = p->check_every > 0 ? p->check_every : p->iters_per_reweight;
-    int k = 0;
-    for (k = 0; k <= p->n_reweights; ++k) {
+    if (p->reweight_first) {
+        s = solve_reweight(c, gamma, gamma_bar);
+        if (s) return s;
+        gamma *= p->gamma_factor;
+        gamma_bar *= p->gamma_factor;
+        ++nrw;
+    }
+    for (int k = 0; k <= p->n_reweights; ++k) {
         int done = 0;
         while (done < p->iters_per_reweight) {
             const int n = std::min(check, p->iters_per_reweight - done);
@@ -996,33 +1074,21 @@ hs_status hs_solve(hs_ctx* c, const hs_solve_params* p, void* X_out, hs_report* 
             if (p->beta_tol > 0 && beta < p->beta_tol) break;
         }
         if (k == p->n_reweights) break;
-        // eq:weights-l21 and eq:weights-n from the current estimate
-        HS_DISPATCH(c, {
-            launch_psi_adj<T>(c, (const T*)c->d.X, nullptr);
-            launch_reweight_l21<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
-            launch_gram<T>(c, (const T*)c->d.X, nullptr);
-            launch_eig(c, 0);
-        });
-        s = launched(c, "hs_solve reweight");
-        if (s) return s;
-        std::vector<double> sg(MAX_L);
-        hipMemcpyAsync(sg.data(), c->d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
-        s = hip_check(c, hipStreamSynchronize(c->stream), "hs_solve");
-        if (s) return s;
-        std::vector<double> w(c->L);
-        for (int l = 0; l < c->L; ++l) w[l] = gamma / (gamma + sg[l]);
-        s = upload_w(c, w.data());
+        s = solve_reweight(c, gamma, gamma_bar);
         if (s) return s;
         gamma *= p->gamma_factor;
         gamma_bar *= p->gamma_factor;
+        ++nrw;
     }
     if (X_out) hipMemcpyAsync(X_out, c->d.X, (size_t)c->L * c->N * c->rsz, hipMemcpyDeviceToDevice, c->stream);
     s = hip_check(c, hipStreamSynchronize(c->stream), "hs_solve");
     if (s) return s;
     if (rep) {
         rep->iterations = total;
-        rep->reweights = std::min(k, p->n_reweights);
+        rep->reweights = nrw;
         rep->final_beta = beta;
+        rep->gamma = gamma;
+        rep->gamma_bar = gamma_bar;
     }
     return HS_OK;
 }

@@ -117,7 +117,7 @@ struct Dev {
     void* A = nullptr;             // [D][L][N]
     void* coef = nullptr;          // [n_db][L][N]
     void* wtmp = nullptr;          // [n_db][L][N]
-    void* wbar = nullptr;          // [D][N]
+    void* wbar = nullptr;          // [D][N] ([D][L][N] for the SARA prior)
     void* filt = nullptr;          // [n_db][2][16] real (h, g)
     // nuclear norm
     double* gram_part = nullptr;   // [ngram][64][64]
@@ -150,6 +150,7 @@ struct hs_ctx {
     int nx = 0, ny = 0, L = 0, Kx = 0, Ky = 0, D = 0, n_db = 0, levels = 0;
     int64_t N = 0;
     int dtype = HS_F32;
+    int gram_mode = HS_GRAM_F64;
     size_t rsz = 4;  // sizeof(real)
     hipStream_t stream = nullptr;
     int device = 0;
@@ -233,7 +234,8 @@ template <typename T> void launch_psi_sum(hs_ctx* c, const T* Cdb /*[n_db][L][N]
 template <typename T> void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T* coef, const T* wbar, double thr, int mode);
 
 // nuclear (k_nuclear.hip)
-template <typename T> void launch_gram(hs_ctx* c, const T* P, const T* Xt);
+// Gram of P + Xt (Xt may be null) in the context's Gram precision, or in FP64 when force64.
+template <typename T> void launch_gram(hs_ctx* c, const T* P, const T* Xt, bool force64 = false);
 void launch_eig(hs_ctx* c, int mode);
 void launch_eig_reset(hs_ctx* c);
 template <typename T> void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2);
@@ -246,5 +248,6 @@ template <typename T> void launch_set_center(hs_ctx* c, T* X);
 template <typename T> int launch_l21_norm(hs_ctx* c, const T* X, const T* coef);
 template <typename T> void launch_chan_scale(hs_ctx* c, T* X, const double* nrm);
 template <typename T> void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);
+template <typename T> void launch_reweight_l1(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);
 
 }  // namespace hs

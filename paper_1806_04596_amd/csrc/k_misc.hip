@@ -216,6 +216,17 @@ __global__ void k_reweight_l21(const T* __restrict__ X, const T* __restrict__ co
     wbar[(size_t)d * N + p] = (T)(gb / (gb + sqrt(n2)));
 }
 
+// SARA's reweighted l1 (Sec. 2.3): wbar[d][l][p] = gb / (gb + |(Psi_d^dag x_l)_p|), per channel.
+template <typename T>
+__global__ void k_reweight_l1(const T* __restrict__ X, const T* __restrict__ coef, T* __restrict__ wbar, double gb,
+                              int L, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int d = blockIdx.y, l = blockIdx.z;
+    const T v = (d == 0) ? X[(size_t)l * N + p] : coef[((size_t)(d - 1) * L + l) * N + p];
+    wbar[((size_t)d * L + l) * N + p] = (T)(gb / (gb + fabs((double)v)));
+}
+
 template <typename T>
 void launch_fill(hipStream_t s, T* p, T v, int64_t n) {
     if (n > 0) k_fill<T><<<nb(n, 256), 256, 0, s>>>(p, v, n);
@@ -286,7 +297,14 @@ void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double g
     k_reweight_l21<T><<<g, 256, 0, c->stream>>>(X, coef, wbar, gb, c->L, c->N);
 }
 
+template <typename T>
+void launch_reweight_l1(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb) {
+    dim3 g(nb(c->N, 256), c->D, c->L);
+    k_reweight_l1<T><<<g, 256, 0, c->stream>>>(X, coef, wbar, gb, c->L, c->N);
+}
+
 #define HS_INST(T)                                                                 \
+    template void launch_reweight_l1<T>(hs_ctx*, const T*, const T*, T*, double);  \
     template void launch_fill<T>(hipStream_t, T*, T, int64_t);                     \
     template void launch_axpby<T>(hipStream_t, T*, const T*, T, T, int64_t);       \
     template void launch_primal<T>(hs_ctx*, const T*, const T*, bool);             \

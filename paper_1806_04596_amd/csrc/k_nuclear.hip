@@ -86,6 +86,109 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* 
     }
 }
 
+// Gram partials in FP32 products (MODE 1) or BF16 split products (MODE 2) of an FP32
+// Z = P + Xt, accumulated in FP32 over the work-group's pixels; the partials are
+// summed in FP64 by k_gram_reduce.
+//  MODE 1: v_mfma_f32_16x16x4f32, lane (i, kq) supplies Z[pixel kk + kq][channel i].
+//  MODE 2: z = hi + lo with hi = bf16(z), lo = bf16(z - hi) (round to nearest even);
+//          C ~ hi^T hi + hi^T lo + lo^T hi (lo^T lo, of relative size 2^-16, dropped)
+//          on v_mfma_f32_16x16x16bf16_1k, lane (i, kq) supplying pixels kk + 4 kq .. + 3
+//          of channel i for both operands (a Gram needs only that A and B index the
+//          pixels alike).
+// D layout of both (FP32 accumulators): lane holds column (lane & 15), rows 4 (lane >> 4) + r.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    const unsigned int b = __float_as_uint(x);
+    return (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+__device__ __forceinline__ void bf16_split4(const float* z, bf16x4_t& hi, bf16x4_t& lo) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const unsigned short h = bf16_rne(z[j]);
+        hi[j] = (short)h;
+        lo[j] = (short)bf16_rne(z[j] - bf16_to_f32(h));
+    }
+}
+
+template <int MODE, bool HAS2>
+__global__ __launch_bounds__(256) void k_gram_lp(const float* __restrict__ P, const float* __restrict__ Xt,
+                                                 double* __restrict__ part, int L, int64_t N, int64_t chunk) {
+    __shared__ float S[MAX_L][GR_SLAB + 4];
+    constexpr int PER = MAX_L * GR_SLAB / 256;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t p_end = min(N, p_begin + chunk);
+    f32x4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    float nv[PER], nv2[PER];
+    bool nin[PER];
+    auto load = [&](int64_t p0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            const int64_t pix = p0 + pp;
+            nin[k] = ch < L && pix < p_end;
+            const size_t idx = (size_t)min(ch, L - 1) * N + (size_t)min(pix, p_end - 1);
+            nv[k] = P[idx];
+            if (HAS2) nv2[k] = Xt[idx];
+        }
+    };
+    load(p_begin);
+    const int i = lane & 15, kq = lane >> 4;
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += GR_SLAB) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            float z = nv[k];
+            if (HAS2) z += nv2[k];
+            S[ch][pp] = nin[k] ? z : 0.f;
+        }
+        __syncthreads();
+        if (p0 + GR_SLAB < p_end) load(p0 + GR_SLAB);
+        if constexpr (MODE == 1) {
+#pragma unroll 4
+            for (int kk = 0; kk < GR_SLAB; kk += 4) {
+                const float a = S[wave * 16 + i][kk + kq];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb)
+                    acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, S[jb * 16 + i][kk + kq], acc[jb], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < GR_SLAB; kk += 16) {
+                bf16x4_t ahi, alo;
+                bf16_split4(&S[wave * 16 + i][kk + 4 * kq], ahi, alo);
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    bf16x4_t bhi, blo;
+                    bf16_split4(&S[jb * 16 + i][kk + 4 * kq], bhi, blo);
+                    acc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc[jb], 0, 0, 0);
+                    acc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc[jb], 0, 0, 0);
+                    acc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc[jb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double* out = part + (size_t)blockIdx.x * MAX_L * MAX_L;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + 4 * (lane >> 4) + r;
+            const int col = jb * 16 + (lane & 15);
+            out[row * MAX_L + col] = (double)acc[jb][r];
+        }
+    }
+}
+
 // C[e] = sum of the partial Grams in a fixed order: 8 interleaved groups of
 // partials (group g takes partials g, g + 8, ...), then a fixed combine.
 constexpr int GRR_E = 32;   // Gram entries per reduction work-group
@@ -371,11 +474,26 @@ __global__ void k_eye(double* V) {
 void launch_eig_reset(hs_ctx* c) { k_eye<<<(MAX_L * MAX_L + 255) / 256, 256, 0, c->stream>>>(c->d.eigV); }
 
 template <typename T>
-void launch_gram(hs_ctx* c, const T* P, const T* Xt) {
+static void gram_lp(hs_ctx*, const T*, const T*, int64_t, int, int) {}   // FP64 contexts: FP64 Gram only
+template <>
+void gram_lp<float>(hs_ctx* c, const float* P, const float* Xt, int64_t chunk, int nparts, int mode) {
+    if (mode == HS_GRAM_F32) {
+        if (Xt) k_gram_lp<1, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+        else k_gram_lp<1, false><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    } else {
+        if (Xt) k_gram_lp<2, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+        else k_gram_lp<2, false><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    }
+}
+
+template <typename T>
+void launch_gram(hs_ctx* c, const T* P, const T* Xt, bool force64) {
     int64_t chunk = (c->N + NGRAM - 1) / NGRAM;
     chunk = (chunk + GR_SLAB - 1) / GR_SLAB * GR_SLAB;
     const int nparts = (int)((c->N + chunk - 1) / chunk);
-    if (Xt) k_gram<T, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
+    const int mode = force64 ? HS_GRAM_F64 : c->gram_mode;
+    if (mode != HS_GRAM_F64 && sizeof(T) == 4) gram_lp<T>(c, P, Xt, chunk, nparts, mode);
+    else if (Xt) k_gram<T, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
     else k_gram<T, false><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.gram_part, c->L, c->N, chunk);
     k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
 }
@@ -398,8 +516,8 @@ void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2) {
     else k_backproject<T, false><<<nb, 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L, c->N);
 }
 
-template void launch_gram<float>(hs_ctx*, const float*, const float*);
-template void launch_gram<double>(hs_ctx*, const double*, const double*);
+template void launch_gram<float>(hs_ctx*, const float*, const float*, bool);
+template void launch_gram<double>(hs_ctx*, const double*, const double*, bool);
 template void launch_backproject<float>(hs_ctx*, float*, const float*, const float*);
 template void launch_backproject<double>(hs_ctx*, double*, const double*, const double*);
 

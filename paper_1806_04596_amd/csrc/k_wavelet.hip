@@ -362,7 +362,8 @@ __global__ void k_psi_sum(const T* __restrict__ Y, const T* __restrict__ C0, T* 
 //  mode 0 (dual update): Z = A + Psi_d^dag Xt, A <- Z min(1, thr*wbar/||Z||);
 //  mode 1 (prox, eq:prox-L21): Z = A, A <- Z max(||Z|| - thr*wbar, 0)/||Z||;
 //  mode 2 (dual of the per-channel weighted l1 of the SARA variant, eq:min-sara):
-//         Z = A + Psi_d^dag Xt, A <- clip(Z, -thr*wbar, thr*wbar) element by element.
+//         Z = A + Psi_d^dag Xt, A <- clip(Z, -thr*wbar, thr*wbar) element by element,
+//         one weight per channel and coefficient (wbar [D][L][N]).
 template <typename T, bool HAS_S>
 __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restrict__ Xt, const T* __restrict__ coef,
                       const T* __restrict__ wbar, double thr, int L, int64_t N, int mode) {
@@ -372,9 +373,10 @@ __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restr
     T* Ad = A + (size_t)d * L * N + p;
     const T* Sd = HAS_S ? ((d == 0) ? Xt + p : coef + (size_t)(d - 1) * L * N + p) : nullptr;
     if (mode == 2) {
-        // SARA variant: weighted l1 per channel, Z - soft(Z) = clip(Z, -t, t) element by element
-        const T t = (T)(thr * (wbar ? (double)wbar[(size_t)d * N + p] : 1.0));
+        // SARA variant: weighted l1 per channel (weights wbar[d][l][p]), Z - soft(Z) =
+        // clip(Z, -t, t) element by element
         for (int l = 0; l < L; ++l) {
+            const T t = (T)(thr * (wbar ? (double)wbar[((size_t)d * L + l) * N + p] : 1.0));
             const T v = Ad[(size_t)l * N] + (HAS_S ? Sd[(size_t)l * N] : T(0));
             Ad[(size_t)l * N] = v > t ? t : (v < -t ? -t : v);
         }

@@ -32,7 +32,7 @@ class Problem:
     """
 
     def __init__(self, nx: int, ny: int, channels, dtype: str = "f32", levels: int = 4, n_db: int = 8,
-                 tile: int = 0, device: int = 0, stream=None):
+                 tile: int = 0, device: int = 0, stream=None, gram_mode: str = "f64"):
         torch = _require_gpu()
         self.torch = torch
         self.lib = L.load()
@@ -46,12 +46,14 @@ class Problem:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         desc = L.ProblemDesc(nx=nx, ny=ny, L=self.L, oversamp=2, J=8, levels=levels, n_db=n_db,
                              dtype=L.HS_F32 if dtype == "f32" else L.HS_F64, tile=tile, device=device,
-                             stream=C.c_void_p(self.stream.cuda_stream))
+                             stream=C.c_void_p(self.stream.cuda_stream), gram_mode=L.GRAM_MODES[gram_mode])
+        self.gram_mode = gram_mode
         ctx = C.c_void_p()
         L.check(self.lib.hs_create(C.byref(desc), C.byref(ctx)), None, "hs_create")
         self.ctx = ctx
         self.counts = []
         self.nblocks = []
+        self._block_ptrs = []
         for l, ch in enumerate(channels):
             uv = np.ascontiguousarray(ch["uv"], dtype=np.float64)
             M = uv.shape[0]
@@ -65,6 +67,7 @@ class Problem:
                                               L.as_dptr(th), L.as_dptr(pre), L.as_dptr(eps)), "hs_set_channel")
             self.counts.append(M)
             self.nblocks.append(len(bp) - 1)
+            self._block_ptrs.append(bp.copy())
         ws = C.c_size_t()
         self._chk(self.lib.hs_plan(ctx, C.byref(ws)), "hs_plan")
         self.ws_bytes = ws.value
@@ -160,12 +163,16 @@ class Problem:
 
     def prox_l21(self, A, t, wbar=None):
         self._check_cube(A, (self.D, self.L, self.ny, self.nx))
+        if wbar is not None:
+            self._check_cube(wbar, (self.D, self.ny, self.nx))
         self._call("hs_prox_l21", self.lib.hs_prox_l21, self._p(A), self._p(wbar), float(t))
         return A
 
     def dual_l21(self, A, Xt, mu, wbar=None, want_sum=False):
         self._check_cube(A, (self.D, self.L, self.ny, self.nx))
         self._check_cube(Xt)
+        if wbar is not None:
+            self._check_cube(wbar, (self.D, self.ny, self.nx))
         S = self.empty_cube() if want_sum else None
         self._call("hs_dual_l21", self.lib.hs_dual_l21, self._p(A), self._p(Xt), self._p(wbar), float(mu), self._p(S))
         return (A, S) if want_sum else A
@@ -198,6 +205,11 @@ class Problem:
         return (v, adj) if want_adj else v
 
     def proj_ellipsoid(self, l, b, z):
+        if not (0 <= l < self.L and 0 <= b < self.nblocks[l]):
+            raise L.HSError(f"no block {b} in channel {l}")
+        mb = int(self._block_ptrs[l][b + 1] - self._block_ptrs[l][b])
+        if z.dtype != self.cdtype or z.numel() != mb or not z.is_contiguous() or z.device != self.device:
+            raise L.HSError(f"expected contiguous {self.cdtype} [{mb}] on {self.device}")
         self._call("hs_proj_ellipsoid", self.lib.hs_proj_ellipsoid, int(l), int(b), self._p(z))
         return z
 
@@ -223,7 +235,11 @@ class Problem:
     # ----------------------------------------------------------------- PD
     def pd_init(self, mu, tau, kappa3, kappa1=1.0, kappa2=0.0, wbar=None, w=None, adaptive_eps=False,
                 lam1=5e-4, lam2=0.01, lam3=0.618, vartheta_bar=100, prior="lrjas"):
+        if wbar is not None:
+            self._check_cube(wbar, self.wbar_shape(prior))
         self._wkeep = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        if self._wkeep is not None and self._wkeep.shape != (self.L,):
+            raise L.HSError(f"nuclear weights: expected [{self.L}]")
         prm = L.PDParams(mu=mu, tau=tau, kappa1=kappa1, kappa2=kappa2, kappa3=kappa3,
                          wbar=None if wbar is None else wbar.data_ptr(),
                          w=None if self._wkeep is None else L.as_dptr(self._wkeep),
@@ -231,20 +247,69 @@ class Problem:
                          vartheta_bar=vartheta_bar, prior=L.PRIORS[prior])
         self._call("hs_pd_init", self.lib.hs_pd_init, C.byref(prm))
 
-    def _state(self, X=None, Xt=None, P=None, A=None, v=None):
-        f = lambda t: None if t is None else t.data_ptr()
-        return L.StatePtrs(X=f(X), Xt=f(Xt), P=f(P), A=f(A), v=f(v))
+    def wbar_shape(self, prior="lrjas"):
+        """Shape of the sparsity weights: one per coefficient row [D][ny][nx], or per
+        channel [D][L][ny][nx] for the SARA prior."""
+        if prior == "sara":
+            return (self.D, self.L, self.ny, self.nx)
+        return (self.D, self.ny, self.nx)
 
-    def set_state(self, X=None, Xt=None, P=None, A=None, v=None):
-        st = self._state(X, Xt, P, A, v)
+    def _state(self, X=None, Xt=None, P=None, A=None, v=None, eps=None, vartheta=None, scalars=None, wbar=None,
+               w=None):
+        f = lambda t: None if t is None else t.data_ptr()
+        return L.StatePtrs(X=f(X), Xt=f(Xt), P=f(P), A=f(A), v=f(v),
+                           eps=None if eps is None else L.as_dptr(eps),
+                           vartheta=None if vartheta is None else vartheta.ctypes.data_as(C.POINTER(C.c_int32)),
+                           scalars=None if scalars is None else L.as_dptr(scalars), wbar=f(wbar),
+                           w=None if w is None else L.as_dptr(w))
+
+    def set_state(self, X=None, Xt=None, P=None, A=None, v=None, eps=None, vartheta=None, beta=None, t=None,
+                  wbar=None, w=None, prior="lrjas"):
+        """Restores a state of Algorithm 2.  eps, vartheta (per block), beta and t, and the
+        weights wbar and w are optional: the bookkeeping not given restarts (the data's
+        bounds, vartheta = 0, beta = 1, t = 0) and the weights not given are kept."""
+        for tt in (X, Xt, P):
+            if tt is not None:
+                self._check_cube(tt)
+        if A is not None:
+            self._check_cube(A, (self.D, self.L, self.ny, self.nx))
+        if v is not None:
+            self._check_vis(v)
+        if wbar is not None:
+            self._check_cube(wbar, self.wbar_shape(prior))
+        nb = int(sum(self.nblocks))
+        ep = None if eps is None else np.ascontiguousarray(eps, dtype=np.float64)
+        vt = None if vartheta is None else np.ascontiguousarray(vartheta, dtype=np.int32)
+        if (ep is not None and ep.shape != (nb,)) or (vt is not None and vt.shape != (nb,)):
+            raise L.HSError(f"eps and vartheta: expected [{nb}]")
+        if (beta is None) != (t is None):
+            raise L.HSError("give beta and t together")
+        sc = None if beta is None else np.array([beta, t], dtype=np.float64)
+        wa = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        if wa is not None and wa.shape != (self.L,):
+            raise L.HSError(f"nuclear weights: expected [{self.L}]")
+        st = self._state(X, Xt, P, A, v, ep, vt, sc, wbar, wa)
         self._call("hs_pd_set_state", self.lib.hs_pd_set_state, C.byref(st))
 
-    def get_state(self):
+    def get_state(self, full=False, prior="lrjas"):
+        """The state of Algorithm 2; with full=True also eps, vartheta, beta, t and the
+        weights wbar and w."""
         X, Xt, P = self.empty_cube(), self.empty_cube(), self.empty_cube()
         A, v = self.empty_coef(), self.empty_vis()
-        st = self._state(X, Xt, P, A, v)
+        out = {"X": X, "Xt": Xt, "P": P, "A": A, "v": v}
+        if full:
+            nb = int(sum(self.nblocks))
+            out.update(eps=np.zeros(nb), vartheta=np.zeros(nb, np.int32), scalars=np.zeros(2),
+                       wbar=self.torch.empty(self.wbar_shape(prior), dtype=self.tdtype, device=self.device),
+                       w=np.zeros(self.L))
+            st = self._state(X, Xt, P, A, v, out["eps"], out["vartheta"], out["scalars"], out["wbar"], out["w"])
+        else:
+            st = self._state(X, Xt, P, A, v)
         self._call("hs_pd_get_state", self.lib.hs_pd_get_state, C.byref(st))
-        return {"X": X, "Xt": Xt, "P": P, "A": A, "v": v}
+        if full:
+            sc = out.pop("scalars")
+            out["beta"], out["t"] = float(sc[0]), int(sc[1])
+        return out
 
     def iterate(self, n=1):
         self._call("hs_pd_iterate", self.lib.hs_pd_iterate, int(n))
@@ -267,13 +332,16 @@ class Problem:
         self._call("hs_pd_stats", self.lib.hs_pd_stats, C.byref(beta), L.as_dptr(rho), L.as_dptr(eps))
         return beta.value, rho, eps
 
-    def solve(self, n_reweights, iters_per_reweight, gamma_factor=0.8, beta_tol=0.0, check_every=0):
+    def solve(self, n_reweights, iters_per_reweight, gamma_factor=0.8, beta_tol=0.0, check_every=0, gamma0=1.0,
+              gamma_bar0=1.0, reweight_first=False):
         X = self.empty_cube()
         prm = L.SolveParams(n_reweights=n_reweights, iters_per_reweight=iters_per_reweight,
-                            gamma_factor=gamma_factor, beta_tol=beta_tol, check_every=check_every)
+                            gamma_factor=gamma_factor, beta_tol=beta_tol, check_every=check_every, gamma0=gamma0,
+                            gamma_bar0=gamma_bar0, reweight_first=1 if reweight_first else 0)
         rep = L.Report()
         self._call("hs_solve", self.lib.hs_solve, C.byref(prm), self._p(X), C.byref(rep))
-        return X, {"iterations": rep.iterations, "reweights": rep.reweights, "final_beta": rep.final_beta}
+        return X, {"iterations": rep.iterations, "reweights": rep.reweights, "final_beta": rep.final_beta,
+                   "gamma": rep.gamma, "gamma_bar": rep.gamma_bar}
 
     def close(self):
         if getattr(self, "ctx", None):

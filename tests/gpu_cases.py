@@ -1,7 +1,9 @@
 """Shared builders for the GPU parity tests.
 
-Each side builds its own problem from the same seeded draws (workloads):
-the oracle with its own Phi and density count, the library with its own.
+Both sides start from the same seeded draws (workloads).  The data y_raw,
+theta and eps are formed once, by the oracle (its FP64 Phi and the noise
+recipe), and handed to the library, so both sides solve the same problem;
+each side computes its own density preconditioner and visibility order.
 """
 from __future__ import annotations
 
@@ -26,23 +28,35 @@ def rel_per_channel(a, b) -> float:
     return max(rel(a[l], b[l]) for l in range(len(b)))
 
 
+_yraw = {}
+
+
 @functools.lru_cache(maxsize=None)
 def oracle_case(name: str, precond: str = "density", **over):
     cfg = W.CONFIGS[name].scaled(**over) if over else W.CONFIGS[name]
     inp = W.make_problem_inputs(cfg)
     oprob, y_raw = pd.build_problem(cfg, inp, precond)
+    _yraw[(name, precond, tuple(sorted(over.items())))] = y_raw
     return cfg, inp, oprob
+
+
+def oracle_data(name: str, precond: str = "density", **over):
+    """The oracle's y_raw, theta and eps of a case (to hand to the library)."""
+    _, _, op = oracle_case(name, precond, **over)
+    y_raw = _yraw[(name, precond, tuple(sorted(over.items())))]
+    return {"y_raw": y_raw, "theta": op.theta, "eps": op.eps}
 
 
 _gpu_cache = {}
 
 
-def gpu_case(name: str, dtype: str, precond: str = "density", tile: int = 0, **over):
-    key = (name, dtype, precond, tile, tuple(sorted(over.items())))
+def gpu_case(name: str, dtype: str, precond: str = "density", tile: int = 0, gram_mode: str = "f64", **over):
+    key = (name, dtype, precond, tile, gram_mode, tuple(sorted(over.items())))
     if key not in _gpu_cache:
         from paper_1806_04596_amd.workload import build_problem
         cfg, inp, _ = oracle_case(name, precond, **over)
-        prob, X0, host = build_problem(cfg, inp, W.make_measurements, dtype=dtype, precond=precond, tile=tile)
+        prob, X0, host = build_problem(cfg, inp, W.make_measurements, dtype=dtype, precond=precond, tile=tile,
+                                       data=oracle_data(name, precond, **over), gram_mode=gram_mode)
         _gpu_cache[key] = (prob, X0, host)
     return _gpu_cache[key]
 

@@ -75,7 +75,7 @@ def test_loss_gradient_vs_oracle(dtype):
     nr = np.sqrt(np.sum(Cr * Cr, axis=1, keepdims=True))
     ref = op.phi_adj(res) + lam * wavelets.psi(Cr / nr, 4)
     err = rel(g, ref)
-    assert err <= TOL[dtype] * (10 if dtype == "f32" else 1), err
+    assert err <= TOL[dtype], err
 
 
 @pytest.mark.slow
@@ -92,8 +92,11 @@ def test_full_cube_finite_differences():
     cfg = W.CONFIGS["cube512_L60_autograd"]
     inp = W.make_problem_inputs(cfg)
     grads = {}
+    data = None
     for dtype in ("f64", "f32"):
-        prob, X0, hd = build_problem(cfg, inp, W.make_measurements, dtype=dtype)
+        # the FP32 problem takes the data the FP64 build formed: one problem, two precisions
+        prob, X0, hd = build_problem(cfg, inp, W.make_measurements, dtype=dtype, data=data)
+        data = {"y_raw": hd["y_raw"], "theta": hd["theta"], "eps": hd["eps"]}
         y = to_dev(prob, np.concatenate([t * yr for t, yr in zip(hd["theta"], hd["y_raw"])]), complex_=True)
         if dtype == "f64":
             # mu_hat = ||X_dirty||_* / ||Psi^dag X_dirty||_{2,1}; X_dirty = Re Phi^dag y over the PSF peak
@@ -124,4 +127,4 @@ def test_full_cube_finite_differences():
         prob.close()
         del prob, X0, y, X, Xg
     err = float((grads["f32"] - grads["f64"]).norm() / grads["f64"].norm())
-    assert err <= 10 * TOL["f32"], err
+    assert err <= TOL["f32"], err

@@ -3,11 +3,17 @@ visibilities, 8 blocks per channel) and the 1024x1024x32 cube (33.5 M
 visibilities, 4 blocks per channel), in FP32, built and launched exactly as the
 benchmark builds them (automatic tile, batched kernels, graph replay).
 
+The data y_raw, theta and eps of every channel are formed once by the oracle
+(FP64) and handed to the library, so both sides solve the same problem.
 Channel-separable outputs (Phi, Phi^dagger, Psi^dagger, Psi, the data-fidelity
 dual) are compared element by element with the oracle on sampled channels
-(the smallest, a middle and the largest); the channel-coupled nuclear dual is
-compared on the whole cube; the full PD iteration is checked through
-properties that hold at any size and against the FP64 instantiation."""
+(the smallest, a middle and the largest); the channel-coupled nuclear dual and
+one whole PD iteration are compared on the whole cube.  The oracle's
+per-channel work runs in a process pool (channels are independent)."""
+import multiprocessing
+import os
+from concurrent.futures import ProcessPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -17,21 +23,29 @@ from gpu_cases import TOL, check_rel, host, rel, split, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+
+def _workers():
+    return max(1, min(12, (os.cpu_count() or 2) - 1))
+
+
+@pytest.fixture(scope="module")
+def pool():
+    with ProcessPoolExecutor(max_workers=_workers(), mp_context=multiprocessing.get_context("spawn")) as ex:
+        yield ex
+
+
 @pytest.fixture(scope="module", params=["cube512_L60", "cube1024_L32"])
-def big(request):
+def big(request, pool):
     from paper_1806_04596_amd.workload import build_problem
     CFG = W.CONFIGS[request.param]
     inp = W.make_problem_inputs(CFG)
     counts = np.array([len(u) for u in inp["uv"]])
     S = sorted({int(np.argmin(counts)), CFG.L // 2, int(np.argmax(counts))})
-    prob, X0, hd = build_problem(CFG, inp, W.make_measurements, dtype="f32")
-    # the oracle's own problem for the sampled channels (each channel's data,
-    # weights, bounds and preconditioner depend on that channel only)
-    sub = {"X0": inp["X0"][S], "uv": [inp["uv"][l] for l in S], "block_ptr": [inp["block_ptr"][l] for l in S],
-           "noise": [inp["noise"][l] for l in S]}
-    op, _ = pd.build_problem(CFG.scaled(L=len(S)), sub)
+    op, y_raw = pd.build_problem(CFG, inp, pool=pool)
+    prob, X0, hd = build_problem(CFG, inp, W.make_measurements, dtype="f32",
+                                 data={"y_raw": y_raw, "theta": op.theta, "eps": op.eps})
     print(f"{CFG.name} full size: sampled channels {S}, M = {prob.M}", flush=True)
-    yield {"cfg": CFG, "inp": inp, "prob": prob, "S": S, "op": op}
+    yield {"cfg": CFG, "inp": inp, "prob": prob, "S": S, "op": op, "y_raw": y_raw}
     prob.close()
 
 
@@ -40,8 +54,8 @@ def test_phi_full_size(big):
     rng = np.random.default_rng(40)
     X = inp["X0"] + 0.05 * inp["X0"].max() * rng.standard_normal(inp["X0"].shape)
     Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
-    for j, l in enumerate(S):
-        ref = nufft.phi(X[l], op.uv[j], op.theta[j])
+    for l in S:
+        ref = nufft.phi(X[l], op.uv[l], op.theta[l])
         check_rel(Y[l], ref, TOL["f32"], f"Phi channel {l}")
 
 
@@ -52,8 +66,8 @@ def test_phi_adj_full_size(big):
     y = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
     X = host(prob.phi_adj(to_dev(prob, y, complex_=True)))
     ys = split(y, prob.counts)
-    for j, l in enumerate(S):
-        ref = nufft.phi_adj(ys[l], op.uv[j], op.theta[j], CFG.ny, CFG.nx)
+    for l in S:
+        ref = nufft.phi_adj(ys[l], op.uv[l], op.theta[l], CFG.ny, CFG.nx)
         check_rel(X[l], ref, TOL["f32"], f"Phi^dag channel {l}")
 
 
@@ -94,14 +108,56 @@ def test_dual_data_full_size(big):
     v = 0.05 * (rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M))
     vd = host(prob.dual_data(to_dev(prob, v, complex_=True), to_dev(prob, Xt)))
     vg, vs = split(vd, prob.counts), split(v, prob.counts)
-    for j, l in enumerate(S):
-        vbar = vs[l] + op.u[j] * nufft.phi(Xt[l], op.uv[j], op.theta[j])
-        bp = op.block_ptr[j]
+    for l in S:
+        vbar = vs[l] + op.u[l] * nufft.phi(Xt[l], op.uv[l], op.theta[l])
+        bp = op.block_ptr[l]
         vr = np.empty_like(vbar)
         for b in range(len(bp) - 1):
             sl = slice(bp[b], bp[b + 1])
-            vr[sl], _ = prox.dual_data_block(vbar[sl], op.y[j][sl], op.u[j][sl], op.eps[j][b])
-        check_rel(vg[l], vr, 10 * TOL["f32"], f"v channel {l}")
+            vr[sl], _ = prox.dual_data_block(vbar[sl], op.y[l][sl], op.u[l][sl], op.eps[l][b])
+        check_rel(vg[l], vr, TOL["f32"], f"v channel {l}")
+
+
+def _kappa3(op):
+    return 1.0 / (max(len(t) for t in op.theta) * max(float(np.max(t)) for t in op.theta if len(t)) ** 2)
+
+
+def test_pd_iteration_full_size_vs_oracle(big, pool):
+    """One graph-replayed FP32 iteration of Algorithm 2 on the whole cube, from a shared
+    state, against one oracle iteration: X, X~, P, A element by element per channel, v per
+    channel, and the residual norms rho of every block."""
+    CFG = big["cfg"]
+    prob, op, inp = big["prob"], big["op"], big["inp"]
+    st = W.make_state(CFG, inp["X0"], prob.counts)
+    w = np.linspace(0.2, 1.0, CFG.L)
+    k3 = _kappa3(op)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=k3, w=w)
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    ref = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, k3), pool=pool)
+    prob.set_state(X=to_dev(prob, st["X"]), Xt=to_dev(prob, st["Xt"]), P=to_dev(prob, st["P"]),
+                   A=to_dev(prob, st["A"]), v=to_dev(prob, np.concatenate(st["v"]), complex_=True))
+    prob.pd_init(mu=0.01, tau=0.33, kappa3=k3, kappa2=1.0 / 9.0, w=w)
+    prob.iterate(1)
+    g = prob.get_state()
+    tol = TOL["f32"]
+    for k in ("X", "Xt", "P"):
+        a = host(g[k])
+        err = max(rel(a[l], getattr(ref, k)[l]) for l in range(CFG.L))
+        print(f"{CFG.name} one iteration {k}: max per-channel rel err {err:.2e}", flush=True)
+        assert err <= tol, (k, err)
+    A = host(g["A"])
+    err = max(rel(A[d, l], ref.A[d, l]) for d in range(9) for l in range(CFG.L))
+    print(f"{CFG.name} one iteration A: max per-(basis, channel) rel err {err:.2e}", flush=True)
+    assert err <= tol
+    vg = split(host(g["v"]), prob.counts)
+    err = max(rel(vg[l], ref.v[l]) for l in range(CFG.L))
+    print(f"{CFG.name} one iteration v: max per-channel rel err {err:.2e}", flush=True)
+    assert err <= tol
+    _, rho, _ = prob.stats()
+    err = rel(rho, np.concatenate(ref.extra["rho"]))
+    print(f"{CFG.name} one iteration rho: rel err {err:.2e}", flush=True)
+    assert err <= tol
 
 
 def test_pd_iteration_full_size_properties(big):
@@ -111,7 +167,7 @@ def test_pd_iteration_full_size_properties(big):
     CFG = big["cfg"]
     import torch
     from paper_1806_04596_amd.workload import build_problem
-    prob, inp = big["prob"], big["inp"]
+    prob, inp, op = big["prob"], big["inp"], big["op"]
     amp = float(inp["X0"].max())
     g = torch.Generator(device="cpu").manual_seed(45)
 
@@ -142,7 +198,8 @@ def test_pd_iteration_full_size_properties(big):
     assert torch.equal(a["Xt"], 2 * a["X"] - Xp)
     bref = float((a["X"].double() - Xp.double()).norm() / a["X"].double().norm())
     assert abs(beta_a - bref) <= 1e-6 * bref
-    p64, _, _ = build_problem(CFG, inp, W.make_measurements, dtype="f64")
+    p64, _, _ = build_problem(CFG, inp, W.make_measurements, dtype="f64",
+                              data={"y_raw": big["y_raw"], "theta": op.theta, "eps": op.eps})
     c, _, _ = run(p64, eager=False)
     for k in ("X", "Xt", "P", "A"):
         err = rel(host(a[k]), host(c[k]))

@@ -189,9 +189,31 @@ def test_dual_data_parity(name, dtype):
         for b in range(len(bp) - 1):
             s = slice(bp[b], bp[b + 1])
             vr[s], _ = prox.dual_data_block(vbar[s], op.y[l][s], op.u[l][s], op.eps[l][b])
-        check_rel(vg[l], vr, TOL[dtype] * (10 if dtype == "f32" else 1), f"v[{l}]")
+        check_rel(vg[l], vr, TOL[dtype], f"v[{l}]")
         adj_ref[l] = nufft.phi_adj(vr, op.uv[l], op.theta[l], cfg.ny, cfg.nx)
-    check_rel_pc(host(adj), adj_ref, (1e-4 if dtype == "f32" else TOL[dtype]), "host(adj)")
+    check_rel_pc(host(adj), adj_ref, TOL[dtype], "host(adj)")
+
+
+@pytest.mark.parametrize("gram_mode", ["f32", "bf16_split"])
+@pytest.mark.parametrize("name", ["cube64_L5", "cube64_L4"])
+def test_nuclear_parity_low_precision_gram(name, gram_mode):
+    """The nuclear prox and dual of an FP32 context whose Gram matrix is formed in FP32
+    or as a BF16 split (hi/lo parts, FP32 accumulation), the eigen-decomposition in
+    FP64: against the oracle's SVD route at the FP32 bar."""
+    cfg, inp, op = oracle_case(name)
+    prob, _, _ = gpu_case(name, "f32", gram_mode=gram_mode)
+    rng = np.random.default_rng(9)
+    X = inp["X0"] + 0.01 * rng.standard_normal(inp["X0"].shape)
+    s_ref = np.linalg.svd(X.reshape(cfg.L, -1).T, compute_uv=False)
+    w = np.sort(rng.uniform(0.0, 0.5 * s_ref[0], cfg.L))
+    Xd, sig = prob.prox_nuclear(to_dev(prob, X), w)
+    ref, s = prox.prox_nuclear_svd(X, w)
+    e_sig = check_rel(sig, s, TOL["f32"], "sig")
+    e_x = check_rel(host(Xd), ref, TOL["f32"], "host(Xd)")
+    P = 0.05 * rng.standard_normal(X.shape)
+    Pd = prob.dual_nuclear(to_dev(prob, P), to_dev(prob, X), w)
+    e_p = check_rel(host(Pd), prox.dual_nuclear(P, X, w, "svd"), TOL["f32"], "host(Pd)")
+    print(f"{name} gram {gram_mode}: sigma {e_sig:.2e}, prox {e_x:.2e}, dual {e_p:.2e}")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -258,10 +280,10 @@ def test_pd_one_iteration_parity(name, dtype):
     check_rel(g["A"], ref.A, tol, "g['A']")
     vg = split(g["v"], prob.counts)
     for l in range(cfg.L):
-        check_rel(vg[l], ref.v[l], tol * (10 if dtype == "f32" else 1), "vg[l]")
-    assert abs(beta - ref.beta) <= tol * max(ref.beta, 1e-30) * 10
+        check_rel(vg[l], ref.v[l], tol, "vg[l]")
+    assert abs(beta - ref.beta) <= tol * max(ref.beta, 1e-30)
     rho_ref = np.concatenate(ref.extra["rho"])
-    check_rel(rho, rho_ref, tol * 10, "rho")
+    check_rel(rho, rho_ref, tol, "rho")
 
 
 def test_pd_twenty_iterations_f64():

@@ -17,8 +17,9 @@ def _kappa3(op):
 def _fresh(name, dtype):
     # a problem of its own: these tests change the bounds and the weights
     from paper_1806_04596_amd.workload import build_problem
+    from gpu_cases import oracle_data
     cfg, inp, op = oracle_case(name)
-    prob, _, _ = build_problem(cfg, inp, W.make_measurements, dtype=dtype)
+    prob, _, _ = build_problem(cfg, inp, W.make_measurements, dtype=dtype, data=oracle_data(name))
     return cfg, inp, op, prob
 
 
@@ -32,22 +33,28 @@ def _set(prob, st):
                    A=to_dev(prob, st["A"]), v=to_dev(prob, np.concatenate(st["v"]), complex_=True))
 
 
+@pytest.mark.parametrize("prior", ["lrjas", "sara"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_reweighted_solve_vs_oracle(dtype):
-    """Two reweights (eq:weights-l21, eq:weights-n) between three runs of 6 PD
-    iterations each, warm-started, gamma factor 0.8."""
+def test_reweighted_solve_vs_oracle(dtype, prior):
+    """Two reweights (eq:weights-l21 and eq:weights-n; for SARA the per-channel
+    reweighted l1) between three runs of 6 PD iterations each, warm-started, gamma
+    factor 0.8."""
     cfg, inp, op, prob = _fresh("cube32_L3", dtype)
     st = W.make_state(cfg, inp["X0"], prob.counts)
-    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op))
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), prior=prior)
     ost, oprm, hist = pd.solve(op, prm, (1.0, 1.0 / 9.0, prm.kappa3), n_reweights=2, iters_per=6, factor=0.8,
                                st=_oracle_state(st, op))
     _set(prob, st)
-    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0)
+    prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0, prior=prior)
     X, rep = prob.solve(2, 6, gamma_factor=0.8)
+    assert rep["gamma"] == pytest.approx(0.64) and rep["gamma_bar"] == pytest.approx(0.64)
+    wbar = host(prob.get_state(full=True, prior=prior)["wbar"])
+    tolw = 1e-11 if dtype == "f64" else TOL["f32"]
+    check_rel(wbar, oprm.wbar, tolw, "wbar")
     assert rep["iterations"] == 18 and rep["reweights"] == 2
-    tol = 1e-11 if dtype == "f64" else 10 * TOL["f32"]
+    tol = 1e-11 if dtype == "f64" else TOL["f32"]
     check_rel(host(X), ost.X, tol, "X")
-    assert abs(rep["final_beta"] - hist[-1]) <= tol * 10 * hist[-1]
+    assert abs(rep["final_beta"] - hist[-1]) <= tol * hist[-1]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -69,7 +76,7 @@ def test_adaptive_bounds_vs_oracle(dtype):
                  lam2=0.01, lam3=0.618, vartheta_bar=1)
     prob.iterate(5)
     beta, rho, eps = prob.stats()
-    tol = TOL[dtype] * (1 if dtype == "f64" else 10)
+    tol = TOL[dtype]
     check_rel(eps, eps_ref, tol, "eps")
     check_rel(rho, np.concatenate(ost.extra["rho"]), tol, "rho")
     check_rel(host(prob.get_state()["X"]), ost.X, tol, "X")
@@ -106,7 +113,61 @@ def test_prior_variants_one_iteration_vs_oracle(prior, dtype):
     prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0, prior=prior)
     prob.iterate(3)
     g = {k: host(v) for k, v in prob.get_state().items()}
-    tol = TOL[dtype] * (1 if dtype == "f64" else 10)
+    tol = TOL[dtype]
     for k in ("X", "Xt", "P", "A"):
         check_rel(g[k], getattr(ost, k), tol, k)
     prob.pd_init(mu=prm.mu, tau=prm.tau, kappa3=prm.kappa3, kappa2=1.0 / 9.0)   # back to the default prior
+
+
+def test_state_view_checkpoint_and_resume():
+    """A checkpoint of the whole state (X, X~, P, A, v, the adaptive bounds eps and
+    their iterations vartheta, beta, t, and the weights wbar, w) taken in the middle of
+    a run and restored into a fresh context continues the run: 3 + 3 iterations with
+    adaptive bounds equal 6 iterations; a reweighted solve saved after its second block
+    and resumed with reweight_first and the reported gamma equals the uninterrupted
+    solve (Algorithm 1's warm start)."""
+    cfg, inp, op, A = _fresh("cube32_L3", "f64")
+    st = W.make_state(cfg, inp["X0"], A.counts)
+    rng = np.random.default_rng(50)
+    wbar = to_dev(A, rng.uniform(0.3, 1.0, (9, cfg.ny, cfg.nx)))
+    w = np.linspace(0.3, 1.0, cfg.L)
+    kw = dict(mu=0.01, tau=0.33, kappa3=_kappa3(op), kappa2=1.0 / 9.0, adaptive_eps=True, lam1=10.0, lam2=0.01,
+              lam3=0.618, vartheta_bar=1)
+    _set(A, st)
+    A.pd_init(wbar=wbar, w=w, **kw)
+    A.iterate(6)
+    ref = A.get_state(full=True)
+    _set(A, st)
+    A.pd_init(wbar=wbar, w=w, **kw)
+    A.iterate(3)
+    mid = A.get_state(full=True)
+    assert mid["t"] == 3 and np.any(mid["vartheta"] > 0)
+    _, _, _, B = _fresh("cube32_L3", "f64")
+    B.pd_init(**kw)                                  # unit weights: the checkpoint brings its own
+    B.set_state(**mid)
+    back = B.get_state(full=True)
+    for k in ("X", "Xt", "P", "A", "v", "wbar"):
+        assert bool((back[k] == mid[k]).all()), k
+    assert np.array_equal(back["eps"], mid["eps"]) and np.array_equal(back["vartheta"], mid["vartheta"])
+    assert (back["beta"], back["t"]) == (mid["beta"], mid["t"]) and np.array_equal(back["w"], w)
+    B.iterate(3)
+    got = B.get_state(full=True)
+    for k in ("X", "Xt", "P", "A"):
+        check_rel(host(got[k]), host(ref[k]), 1e-12, k)
+    check_rel(got["eps"], ref["eps"], 1e-12, "eps")
+    assert np.array_equal(got["vartheta"], ref["vartheta"]) and got["t"] == 6
+    # Algorithm 1: solve(2 reweights) = solve(1 reweight) + checkpoint + resume
+    kw2 = dict(mu=0.01, tau=0.33, kappa3=_kappa3(op), kappa2=1.0 / 9.0)
+    _set(A, st)
+    A.pd_init(**kw2)
+    X2, rep2 = A.solve(2, 6, gamma_factor=0.8)
+    _set(A, st)
+    A.pd_init(**kw2)
+    _, rep1 = A.solve(1, 6, gamma_factor=0.8)
+    ck = A.get_state(full=True)
+    B.pd_init(**kw2)
+    B.set_state(**ck)
+    Xr, repr_ = B.solve(0, 6, gamma_factor=0.8, gamma0=rep1["gamma"], gamma_bar0=rep1["gamma_bar"],
+                        reweight_first=True)
+    assert repr_["reweights"] == 1 and repr_["gamma"] == pytest.approx(rep2["gamma"])
+    check_rel(host(Xr), host(X2), 1e-11, "resumed solve")

@@ -119,3 +119,54 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     libs = set(re.findall(r"/\S*libamdhip64\S*", maps))
     assert len(libs) == 1, libs
+
+
+def _bare_problem():
+    """A Problem with its shape fields set and no context: the binding's argument checks
+    run before any library call, so they can be exercised without a GPU."""
+    import torch
+    from paper_1806_04596_amd.problem import Problem
+    p = Problem.__new__(Problem)
+    p.torch = torch
+    p.nx, p.ny, p.L, p.D, p.M = 8, 8, 2, 9, 5
+    p.tdtype, p.cdtype = torch.float64, torch.complex128
+    p.device = torch.device("cpu")
+    p.nblocks = [1, 1]
+    p._block_ptrs = [np.array([0, 3]), np.array([0, 2])]
+    p.ctx = None
+
+    def no_call(*a, **k):
+        raise AssertionError("the library was called")
+    p._call = no_call
+    return p
+
+
+def test_binding_rejects_bad_state_and_weights_before_calling_the_library():
+    import torch
+    from paper_1806_04596_amd._lib import HSError
+    p = _bare_problem()
+    cube = torch.zeros(2, 8, 8, dtype=torch.float64)
+    bad = [dict(X=torch.zeros(2, 8, 8, dtype=torch.float32)),            # dtype
+           dict(Xt=torch.zeros(2, 8, 7, dtype=torch.float64)),            # shape
+           dict(P=torch.zeros(8, 2, 8, dtype=torch.float64).transpose(0, 1)),  # not contiguous
+           dict(A=torch.zeros(8, 2, 8, 8, dtype=torch.float64)),          # D
+           dict(v=torch.zeros(4, dtype=torch.complex128)),                # M
+           dict(v=torch.zeros(5, dtype=torch.complex64)),                 # complex dtype
+           dict(wbar=torch.zeros(9, 8, 8, dtype=torch.float64), prior="sara"),   # SARA weights per channel
+           dict(eps=np.ones(3)), dict(vartheta=np.zeros(1)), dict(beta=0.5),
+           dict(w=np.ones(3))]
+    for kw in bad:
+        with pytest.raises(HSError):
+            p.set_state(X=cube, **kw) if "X" not in kw else p.set_state(**kw)
+    with pytest.raises(HSError):
+        p.pd_init(mu=0.1, tau=0.3, kappa3=1.0, wbar=torch.zeros(9, 2, 8, 8, dtype=torch.float64))
+    with pytest.raises(HSError):
+        p.pd_init(mu=0.1, tau=0.3, kappa3=1.0, w=np.ones(3))
+    with pytest.raises(HSError):
+        p.prox_l21(torch.zeros(9, 2, 8, 8, dtype=torch.float64), 0.1, wbar=torch.zeros(9, 8, 9, dtype=torch.float64))
+    with pytest.raises(HSError):
+        p.proj_ellipsoid(0, 0, torch.zeros(2, dtype=torch.complex128))     # block 0 of channel 0 has 3
+    with pytest.raises(HSError):
+        p.proj_ellipsoid(1, 1, torch.zeros(2, dtype=torch.complex128))     # no block 1 in channel 1
+    with pytest.raises(HSError):
+        p.proj_ellipsoid(0, 0, torch.zeros(3, dtype=torch.complex64))

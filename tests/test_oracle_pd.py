@@ -306,5 +306,57 @@ def test_prior_variants_reduce_to_special_cases():
     sara = pd.pd_iteration(st1, prob1, pd.Params(mu=0.3, prior="sara"), k)
     jas1 = pd.pd_iteration(st1, prob1, pd.Params(mu=0.3, prior="jas"), k)
     assert np.allclose(sara.X, jas1.X, rtol=0, atol=1e-14) and np.allclose(sara.A, jas1.A, rtol=0, atol=1e-14)
-    with pytest.raises(ValueError):
-        pd.solve(prob, pd.Params(mu=0.3, prior="sara"), k, 1, 1)
+
+
+def test_sara_is_each_channel_on_its_own():
+    """SARA (eq:min-sara) is one weighted-l1 problem per channel: one iteration of the
+    two-channel SARA problem equals the two one-channel iterations, each with its own
+    weights (channel 1's weights differ from channel 0's)."""
+    prob, _ = _tiny_problem(3)
+    st = _variant_state(prob, 7)
+    k = (1.0, 1.0 / 9.0, 1e-3)
+    rng = np.random.default_rng(12)
+    wbar = rng.uniform(0.2, 1.0, (9, prob.L, prob.ny, prob.nx))
+    both = pd.pd_iteration(st, prob, pd.Params(mu=0.3, prior="sara", wbar=wbar), k)
+    for l in range(prob.L):
+        one = pd.Problem(nx=prob.nx, ny=prob.ny, uv=[prob.uv[l]], y=[prob.y[l]], theta=[prob.theta[l]],
+                         u=[prob.u[l]], eps=[prob.eps[l]], block_ptr=[prob.block_ptr[l]])
+        s1 = pd.State(X=st.X[l:l + 1], Xt=st.Xt[l:l + 1], P=st.P[l:l + 1], A=st.A[:, l:l + 1], v=[st.v[l]])
+        r1 = pd.pd_iteration(s1, one, pd.Params(mu=0.3, prior="sara", wbar=wbar[:, l:l + 1]), k)
+        assert np.allclose(both.X[l], r1.X[0], rtol=0, atol=1e-14)
+        assert np.allclose(both.A[:, l], r1.A[:, 0], rtol=0, atol=1e-14)
+
+
+def test_sara_reweighting_closed_form():
+    """SARA's reweighted l1 (Sec. 2.3): weight gamma_bar / (gamma_bar + |coefficient|) per
+    channel, on X = 1 h^T: Dirac coefficients h_l, coarsest low-pass 16 h_l, others 0."""
+    prob, _ = _tiny_problem(4, L=2)
+    h = np.array([0.9, -0.4])
+    X = _rank_two_cube(prob.ny, prob.nx, h, np.zeros(2))
+    wbar, w = pd.reweight(X, prob, 1.0, 0.5, prior="sara")
+    assert w is None and wbar.shape == (9, 2, prob.ny, prob.nx)
+    coarse = np.zeros((prob.ny, prob.nx), bool)
+    coarse[: prob.ny // 16, : prob.nx // 16] = True
+    for l in range(2):
+        assert np.allclose(wbar[0, l], 0.5 / (0.5 + abs(h[l])), rtol=1e-12)
+        for d in range(1, 9):
+            assert np.allclose(wbar[d, l][coarse], 0.5 / (0.5 + 16 * abs(h[l])), rtol=1e-10)
+            assert np.allclose(wbar[d, l][~coarse], 1.0, rtol=0, atol=1e-10)
+
+
+def test_pooled_iteration_is_the_same_iteration():
+    """Mapping the per-channel work over a process pool changes nothing."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    prob, X0 = _tiny_problem(10, L=2)
+    st = pd.zero_state(prob)
+    st.X = X0.copy(); st.Xt = X0 + 0.01
+    prm = pd.Params(mu=0.02)
+    kap = (1.0, 1.0 / 9.0, 1e-3)
+    ref = pd.pd_iteration(st, prob, prm, kap)
+    with ProcessPoolExecutor(max_workers=2, mp_context=multiprocessing.get_context("spawn")) as ex:
+        got = pd.pd_iteration(st, prob, prm, kap, pool=ex)
+    for k in ("X", "Xt", "P", "A"):
+        assert np.array_equal(getattr(got, k), getattr(ref, k)), k
+    for l in range(prob.L):
+        assert np.array_equal(got.v[l], ref.v[l]) and np.array_equal(got.extra["rho"][l], ref.extra["rho"][l])

@@ -186,10 +186,10 @@ def test_l1_dual_is_projection_onto_linf_ball():
     rng = np.random.default_rng(31)
     A = rng.standard_normal((3, 2, 8, 8))
     S = rng.standard_normal((3, 2, 8, 8))
-    wbar = rng.uniform(0.1, 1.0, (3, 8, 8))
+    wbar = rng.uniform(0.1, 1.0, (3, 2, 8, 8))     # one weight per channel and coefficient
     mu, D = 0.2, 3.0
     out = prox.dual_l1(A, S, wbar, mu, D)
-    t = mu * wbar[:, None] * D
+    t = mu * wbar * D
     assert np.allclose(out, np.clip(A + S, -t, t), rtol=0, atol=1e-15)
     # and soft thresholding by hand on one element
     z, tt = 1.7, 0.5
