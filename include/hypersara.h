@@ -270,6 +270,20 @@ hs_status hs_prox_l21(hs_ctx* ctx, void* A, const void* wbar, double t);
  * and, when At_sum is not NULL, At_sum = sum_d Psi_d A_d (real [L][ny][nx]). */
 hs_status hs_dual_l21(hs_ctx* ctx, void* A, const void* Xt, const void* wbar, double mu, void* At_sum);
 
+/* hs_prox_nuclear without a context and without allocating: for callers that cannot
+ * allocate device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  X: device real (dtype HS_F32 or HS_F64) [L][N], replaced in
+ * place by S*_w(X) as in hs_prox_nuclear (FP64 Gram and eigen-decomposition, cold
+ * start); w: host double [L] (NULL = ones); sigma_out: host double [L] or NULL;
+ * stream: hipStream_t (NULL = default); device: HIP device ordinal, made current.
+ * The scratch is a fixed device array of the library, 4.29 MB per device, kept until
+ * the process ends; it bounds L to 1..64 (HS_ERR_SHAPE beyond).  N >= 1.  Every call
+ * on a device shares that device's array: calls that overlap on one device (other
+ * threads, other streams) race.  Synchronising.  Errors: HS_ERR_INVALID_ARG,
+ * HS_ERR_SHAPE, HS_ERR_NONFINITE (w), HS_ERR_HIP. */
+hs_status hs_prox_nuclear_noalloc(void* X, int32_t dtype, int64_t N, int32_t L, const double* w,
+                                  double* sigma_out, void* stream, int32_t device);
+
 /* eq:prox-L* in place on the N x L matrix X (column l = channel l):
  * singular values soft-thresholded by w (host [L], paired with decreasing
  * singular values; NULL = ones).  sigma_out (host [L], may be NULL) receives

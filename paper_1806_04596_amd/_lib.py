@@ -85,6 +85,7 @@ SIGNATURES = {
     "hs_dual_l21": (C.c_int32, [ctxp, P, P, P, C.c_double, P]),
     "hs_prox_nuclear": (C.c_int32, [ctxp, P, dptr, dptr]),
     "hs_dual_nuclear": (C.c_int32, [ctxp, P, P, dptr]),
+    "hs_prox_nuclear_noalloc": (C.c_int32, [P, C.c_int32, C.c_int64, C.c_int32, dptr, dptr, P, C.c_int32]),
     "hs_dual_data": (C.c_int32, [ctxp, P, P, P]),
     "hs_proj_ellipsoid": (C.c_int32, [ctxp, C.c_int32, C.c_int32, P]),
     "hs_op_norm": (C.c_int32, [ctxp, C.c_int32, C.c_int32, C.c_double, P, dptr, dptr, C.POINTER(C.c_int32)]),

@@ -11,6 +11,10 @@
 //  * W = V diag(f(sigma)) V^T with sigma_j = sqrt(lambda_j) sorted in decreasing
 //    order and f = min(1, w_j/sigma_j) (dual form I - S*_w) or 1 - that (prox).
 //  * Back-projection out = Z W (every pixel's length-L row times W).
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -522,3 +526,99 @@ template void launch_backproject<float>(hs_ctx*, float*, const float*, const flo
 template void launch_backproject<double>(hs_ctx*, double*, const double*, const double*);
 
 }  // namespace hs
+
+// ------------------------------------------------ nuclear prox without allocation
+// hs_prox_nuclear_noalloc: the nuclear-norm prox of hs_prox_nuclear for callers that
+// cannot allocate device memory.  Its scratch (Gram partials, the Gram matrix, the
+// eigenvectors and values, the weights and W) is the file-scope device array below,
+// one copy per device, held until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+namespace hs {
+
+constexpr int NA_PARTS = 128;                       // Gram partials (split over pixels)
+constexpr size_t NA_MAT = (size_t)MAX_L * MAX_L;    // one 64 x 64 matrix
+// doubles: partials, C, V, W, sigma, w
+constexpr size_t NA_DOUBLES = NA_PARTS * NA_MAT + 3 * NA_MAT + 2 * MAX_L;
+constexpr size_t NA_SCRATCH_BYTES = NA_DOUBLES * sizeof(double);   // 4.29 MB
+
+__device__ __align__(256) double scratch[NA_DOUBLES];
+
+struct NAWeights {
+    double w[MAX_L];
+};
+
+__global__ void k_na_set_w(NAWeights w, double* dst) {
+    const int j = threadIdx.x;
+    if (j < MAX_L) dst[j] = w.w[j];
+}
+
+static double* na_scratch_ptr(int device, std::string& err) {
+    static std::mutex mu;
+    static void* ptr[64] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= 64) {
+        err = "device ordinal out of range";
+        return nullptr;
+    }
+    if (!ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptr[device] = p;
+    }
+    return (double*)ptr[device];
+}
+
+template <typename T>
+static void na_launch(double* base, T* X, int64_t N, int L, hipStream_t st) {
+    double* part = base;
+    double* C = part + NA_PARTS * NA_MAT;
+    double* V = C + NA_MAT;
+    double* Wm = V + NA_MAT;
+    double* sig = Wm + NA_MAT;
+    double* w = sig + MAX_L;
+    int64_t chunk = (N + NA_PARTS - 1) / NA_PARTS;
+    chunk = (chunk + GR_SLAB - 1) / GR_SLAB * GR_SLAB;
+    const int nparts = (int)((N + chunk - 1) / chunk);
+    k_gram<T, false><<<nparts, 256, 0, st>>>(X, nullptr, part, L, N, chunk);
+    k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, st>>>(part, C, nparts);
+    k_eig<T><<<1, 256, 0, st>>>(C, V, sig, w, (T*)Wm, L, 1, 0, nullptr);
+    const int64_t nt = (N + 15) / 16;
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(BP_WAVES, nt) / 4);
+    k_backproject<T, false><<<nb, 256, 0, st>>>(X, nullptr, (const T*)Wm, X, L, N);
+}
+
+}  // namespace hs
+
+extern "C" hs_status hs_prox_nuclear_noalloc(void* X, int32_t dtype, int64_t N, int32_t L, const double* w,
+                                             double* sigma_out, void* stream, int32_t device) {
+    using namespace hs;
+    static thread_local std::string err;
+    if (!X || (dtype != HS_F32 && dtype != HS_F64) || N < 1) return HS_ERR_INVALID_ARG;
+    if (L < 1 || L > MAX_L) return HS_ERR_SHAPE;   // the scratch holds 64 x 64 matrices
+    NAWeights wv;
+    for (int j = 0; j < MAX_L; ++j) wv.w[j] = 1.0;
+    if (w)
+        for (int j = 0; j < L; ++j) {
+            if (!std::isfinite(w[j]) || w[j] < 0) return HS_ERR_NONFINITE;
+            wv.w[j] = w[j];
+        }
+    if (hipSetDevice(device) != hipSuccess) return HS_ERR_HIP;
+    double* base = na_scratch_ptr(device, err);
+    if (!base) return HS_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    double* sig = base + NA_PARTS * NA_MAT + 3 * NA_MAT;
+    k_na_set_w<<<1, MAX_L, 0, st>>>(wv, sig + MAX_L);
+    if (dtype == HS_F32) na_launch<float>(base, (float*)X, N, L, st);
+    else na_launch<double>(base, (double*)X, N, L, st);
+    if (hipGetLastError() != hipSuccess) return HS_ERR_HIP;
+    double sg[MAX_L];
+    if (hipMemcpyAsync(sg, sig, MAX_L * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return HS_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HS_ERR_HIP;
+    if (sigma_out)
+        for (int j = 0; j < L; ++j) sigma_out[j] = sg[j];
+    return HS_OK;
+}
