@@ -236,7 +236,7 @@ def main():
     prob, X0, _ = build_problem(cfg, inputs, W.make_measurements, dtype="f32", data=data)
     info = prob.info()
     x0 = torch.as_tensor(W.synth.power_start(cfg), dtype=prob.tdtype, device=prob.device).contiguous()
-    nrm, _, it_norm = prob.op_norm(x0, max_it=30, tol=1e-6)
+    nrm, _, it_norm = prob.op_norm(x0, max_it=1000, tol=1e-10)   # FP64 power iteration
     kappa3 = 1.0 / nrm
     mu, tau = 0.01, 0.33
     prob.pd_init(mu=mu, tau=tau, kappa3=kappa3)

@@ -92,7 +92,7 @@ typedef struct {
 typedef struct {
     int64_t n_vis;          /* sum of M_l */
     int64_t n_blocks;       /* sum of B_l */
-    int64_t n_bins;         /* (block, preconditioner value) classes */
+    int64_t n_bins;         /* (block, preconditioner value) pairs that occur (<= n_vis + n_blocks) */
     int64_t n_runs;         /* segmented-reduction runs */
     int64_t n_degrid_units; /* degridding work units */
     int64_t n_grid_units;   /* gridding work units */
@@ -309,6 +309,8 @@ hs_status hs_proj_ellipsoid(hs_ctx* ctx, int32_t l, int32_t b, void* z);
  *   x -> Re Phi_l^dagger U_l Phi_l x over real images, started from x0
  *   (device real [L][ny][nx], caller-drawn), stopping at relative change
  *   < tol or max_it iterations; per-channel values in per_channel (host [L], may be NULL).
+ *   An FP32 context runs the FP64 operators on FP64 copies of its plan's
+ *   arrays (kept in its workspace) from x0 widened exactly.
  * which = HS_NORM_PSI: ||Psi^dagger||_S^2 = D (orthonormal bases), exact.
  * *iters receives the iterations used (may be NULL).  Synchronising. */
 hs_status hs_op_norm(hs_ctx* ctx, int32_t which, int32_t max_it, double tol, const void* x0,

@@ -16,8 +16,9 @@ for bit.  For channel l with oversampled grid Kx x Ky and square tile T:
 * region (0..8) = 3 * row_class + col_class, where for the in-tile offset o,
   class 0 if o < J/2 - 1, class 2 if o >= T - J/2, else 1 -- the visibilities
   whose kernel footprint reaches into the previous / next tile;
-* bin = block * C + class_of(U), with C the number of distinct preconditioner
-  values of the channel and class_of the rank of U_m among them (ascending);
+* bins: the (block, preconditioner value) pairs that occur; bin = the number
+  of such pairs in the earlier blocks + the rank of U_m among the distinct
+  values of its own block (ascending), so there are at most M + B of them;
 * order = stable sort by (tile, region, bin, cell within the tile in raster
   order), ties kept in input order.
 """
@@ -49,14 +50,20 @@ def region_class(o: np.ndarray, T: int) -> np.ndarray:
 
 
 def bins(u: np.ndarray | None, block_ptr: np.ndarray, M: int):
-    blk = np.zeros(M, dtype=np.int64)
+    """Bin of every visibility, the bin pointer of each block and each bin's value."""
+    out = np.zeros(M, dtype=np.int64)
+    ptr, vals = [0], []
     for b in range(len(block_ptr) - 1):
-        blk[block_ptr[b]:block_ptr[b + 1]] = b
-    if u is None:
-        return blk, 1, np.array([1.0])
-    vals, cls = np.unique(u, return_inverse=True)
-    C = len(vals)
-    return blk * C + cls, C, vals
+        s = slice(block_ptr[b], block_ptr[b + 1])
+        if u is None:
+            v, cls = (np.array([1.0]), np.zeros(block_ptr[b + 1] - block_ptr[b], np.int64)) \
+                if block_ptr[b + 1] > block_ptr[b] else (np.zeros(0), np.zeros(0, np.int64))
+        else:
+            v, cls = np.unique(u[s], return_inverse=True)
+        out[s] = ptr[-1] + cls
+        ptr.append(ptr[-1] + len(v))
+        vals.append(v)
+    return out, np.array(ptr, dtype=np.int64), (np.concatenate(vals) if vals else np.zeros(0))
 
 
 def order(uv: np.ndarray, u: np.ndarray | None, block_ptr: np.ndarray, nx: int, ny: int, T: int):

@@ -91,6 +91,21 @@ static size_t carve(hs_ctx* c, char* base) {
     k.take(d.red_part, (size_t)std::max<int64_t>(NRED * 4, 64 * MAX_L) * 8, base);
     k.take(d.scal, 64 * 8, base);
     k.take(d.chan_nrm, (size_t)MAX_L * 8, base);
+    if (c->dtype == HS_F32) {   // FP64 copies for the power iteration
+        Dev64& e = c->d64;
+        k.take(e.vis_frac, M * 16, base);
+        k.take(e.vis_theta, M * 8, base);
+        k.take(e.vis_u, M * 8, base);
+        k.take(e.vwork, M * 16, base);
+        k.take(e.gpartial, (size_t)c->npartial * GB * GB * 16, base);
+        k.take(e.grid, (size_t)c->L * c->Ky * c->Wg * 16, base);
+        k.take(e.H, (size_t)c->L * c->ny * c->Hs * 16, base);
+        k.take(e.tw_x, (size_t)c->Kx * 16, base);
+        k.take(e.tw_y, (size_t)c->Ky * 16, base);
+        k.take(e.sx, (size_t)c->nx * 8, base);
+        k.take(e.sy, (size_t)c->ny * 8, base);
+        k.take(e.x, LN * 8, base);
+    }
     return (k.off + 255) & ~(size_t)255;
 }
 
@@ -150,6 +165,7 @@ static hs_status bind_impl(hs_ctx* c) {
     upload(d.chunk_run, c->h_chunk_run);
     // FFT twiddles exp(-2 pi i k / K) and deapodisation 1/phihat(p/K)
     const long double pi = 3.141592653589793238462643383279502884L;
+    const bool shadow = c->dtype == HS_F32;
     for (int dim = 0; dim < 2; ++dim) {
         const int K = dim == 0 ? c->Kx : c->Ky;
         std::vector<double> tw(2 * (size_t)K);
@@ -159,10 +175,17 @@ static hs_status bind_impl(hs_ctx* c) {
             tw[2 * k + 1] = (double)(-std::sin(a));
         }
         upload_real<T>(c, dim == 0 ? d.tw_x : d.tw_y, tw);
+        if (shadow) upload_real<double>(c, dim == 0 ? c->d64.tw_x : c->d64.tw_y, tw);
         const int n = dim == 0 ? c->nx : c->ny;
         std::vector<double> s(n);
         for (int i = 0; i < n; ++i) s[i] = 1.0 / kb_ft((double)(i - n / 2) / (double)K);
         upload_real<T>(c, dim == 0 ? d.sx : d.sy, s);
+        if (shadow) upload_real<double>(c, dim == 0 ? c->d64.sx : c->d64.sy, s);
+    }
+    if (shadow) {
+        upload_real<double>(c, c->d64.vis_frac, c->h_frac);
+        upload_real<double>(c, c->d64.vis_theta, c->h_theta);
+        upload_real<double>(c, c->d64.vis_u, c->h_u);
     }
     {
         std::vector<double> f((size_t)MAX_DB * 32, 0.0);
@@ -353,7 +376,7 @@ static hs_status op_norm_impl(hs_ctx* c, int max_it, double tol, const T* x0, do
     Dev& d = c->d;
     const int64_t LN = (int64_t)c->L * c->N;
     T* x = (T*)d.img1;
-    hipMemcpyAsync(x, x0, LN * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+    if ((const void*)x != (const void*)x0) hipMemcpyAsync(x, x0, LN * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
     launch_chan_norms<T>(c, x, d.chan_nrm);
     launch_chan_scale<T>(c, x, d.chan_nrm);
     std::vector<double> lam(c->L, 0.0), prev(c->L, 0.0);
@@ -609,6 +632,7 @@ hs_status hs_set_data(hs_ctx* c, int32_t l, const double* y_raw, const double* t
         std::vector<float> yy(c->h_y.begin() + 2 * base, c->h_y.begin() + 2 * (base + n));
         hipMemcpy((float*)c->d.vis_theta + base, th.data(), n * 4, hipMemcpyHostToDevice);
         hipMemcpy((float*)c->d.vis_y + 2 * base, yy.data(), 2 * n * 4, hipMemcpyHostToDevice);
+        hipMemcpy((double*)c->d64.vis_theta + base, c->h_theta.data() + base, n * 8, hipMemcpyHostToDevice);
     } else {
         hipMemcpy((double*)c->d.vis_theta + base, c->h_theta.data() + base, n * 8, hipMemcpyHostToDevice);
         hipMemcpy((double*)c->d.vis_y + 2 * base, c->h_y.data() + 2 * base, 2 * n * 8, hipMemcpyHostToDevice);
@@ -804,8 +828,24 @@ hs_status hs_op_norm(hs_ctx* c, int32_t which, int32_t max_it, double tol, const
     if (which != HS_NORM_PHI_PRECOND || !x0 || max_it < 1 || !(tol >= 0))
         return fail(c, HS_ERR_INVALID_ARG, "bad op_norm arguments");
     c->graph_valid = false;  // scratch buffers are reused
-    if (c->dtype == HS_F32) s = op_norm_impl<float>(c, max_it, tol, (const float*)x0, out, per_channel, iters);
-    else s = op_norm_impl<double>(c, max_it, tol, (const double*)x0, out, per_channel, iters);
+    if (c->dtype == HS_F32) {
+        // the FP64 operators on the FP64 copies of the plan's arrays (Sec. 3.4: the
+        // step-size norm stays in FP64); the caller's FP32 start is widened exactly
+        const Dev saved = c->d;
+        const std::vector<double> kb_saved = c->kb_c;
+        Dev& d = c->d;
+        const Dev64& e = c->d64;
+        d.vis_frac = e.vis_frac; d.vis_theta = e.vis_theta; d.vis_u = e.vis_u; d.vwork = e.vwork;
+        d.gpartial = e.gpartial; d.grid = e.grid; d.H = e.H; d.tw_x = e.tw_x; d.tw_y = e.tw_y;
+        d.sx = e.sx; d.sy = e.sy; d.img1 = e.x;
+        c->kb_c = c->kb_c64;
+        launch_convert<float, double>(c->stream, (double*)e.x, (const float*)x0, (int64_t)c->L * c->N);
+        s = op_norm_impl<double>(c, max_it, tol, (const double*)e.x, out, per_channel, iters);
+        c->d = saved;
+        c->kb_c = kb_saved;
+    } else {
+        s = op_norm_impl<double>(c, max_it, tol, (const double*)x0, out, per_channel, iters);
+    }
     if (s) return s;
     return launched(c, "hs_op_norm");
 }

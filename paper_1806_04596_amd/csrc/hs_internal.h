@@ -132,6 +132,23 @@ struct Dev {
     double* chan_nrm = nullptr;    // [64] per-channel norms
 };
 
+// FP64 copies of what the measurement operator reads, for the FP64 power iteration
+// of an FP32 context (the step-size norm stays in FP64, Sec. 3.4).
+struct Dev64 {
+    void* vis_frac = nullptr;      // [M][2] double
+    void* vis_theta = nullptr;     // [M] double
+    void* vis_u = nullptr;         // [M] double
+    void* vwork = nullptr;         // [M] complex double
+    void* gpartial = nullptr;      // [npartial][GB*GB] complex double
+    void* grid = nullptr;          // [L][Ky][Wg] complex double
+    void* H = nullptr;             // [L][ny][Hs] complex double
+    void* tw_x = nullptr;
+    void* tw_y = nullptr;
+    void* sx = nullptr;
+    void* sy = nullptr;
+    void* x = nullptr;             // [L][N] double, the iterate
+};
+
 struct Channel {
     bool set = false;
     int64_t M = 0;
@@ -173,6 +190,7 @@ struct hs_ctx {
     std::vector<hs::SplitTile> splits;
     int kb_terms = 0;
     std::vector<double> kb_c;          // power-series coefficients
+    std::vector<double> kb_c64;        // FP64 coefficients (the FP64 power iteration of an FP32 context)
     // host staging of the plan (uploaded at bind)
     std::vector<int32_t> h_cell, h_bin, h_perm, h_glist, h_blk_bin_ptr, h_bin_run_ptr, h_run_slot;
     std::vector<int32_t> h_chunk_run;
@@ -181,6 +199,7 @@ struct hs_ctx {
     size_t ws_bytes = 0;
     void* ws = nullptr;
     hs::Dev d;
+    hs::Dev64 d64;                     // FP32 contexts only
     // PD
     bool pd_ready = false;
     double mu = 0, tau = 0.33, k1 = 1, k2 = 0, k3 = 0;
@@ -210,6 +229,7 @@ void daubechies_host(int K, double* h);
 
 // ------------------------------------------------------------ kernel launchers
 template <typename T> void launch_fill(hipStream_t s, T* p, T v, int64_t n);
+template <typename S, typename D> void launch_convert(hipStream_t s, D* dst, const S* src, int64_t n);
 template <typename T> void launch_axpby(hipStream_t s, T* y, const T* x, T a, T b, int64_t n);   // y = a*x + b*y
 
 // NUFFT (k_nufft.hip)

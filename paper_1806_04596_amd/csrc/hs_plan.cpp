@@ -196,8 +196,8 @@ struct ChanOrder {
     std::vector<int32_t> cx, cy;      // per input index (half-plane cell)
     std::vector<int32_t> refl;        // per input index: reflected to -t
     std::vector<double> fx, fy;       // per input index
-    std::vector<double> class_val;    // distinct preconditioner values (ascending)
-    int C = 1;
+    std::vector<double> bin_val;      // value of every bin, block by block (ascending within a block)
+    std::vector<int64_t> blk_bin_ptr; // [nb + 1]: bins of block b are [ptr[b], ptr[b + 1])
 };
 
 // Cell, fraction and reflection of one visibility in the Hermitian half plane:
@@ -254,32 +254,35 @@ static void order_channel(int64_t M, const double* uv, const double* u, int nb, 
         key[m] = tile * 9 + reg;
         loc[m] = (h.cy % T) * T + (h.cx % T);
     }
-    // bins: block * C + rank of the preconditioner value
+    // bins: the (block, preconditioner value) pairs that occur, block by block; a
+    // visibility's bin is its block's first bin + the rank of its value among the
+    // block's distinct values.  At most M + nb bins, whatever the values.
     o.bin_local.assign(M, 0);
-    std::vector<int32_t> blk(M, 0);
-    for (int b = 0; b < nb; ++b)
-        for (int64_t m = bp[b]; m < bp[b + 1]; ++m) blk[m] = b;
-    if (u) {
-        std::vector<double> vals(u, u + M);
-        std::sort(vals.begin(), vals.end());
-        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
-        o.class_val = vals;
-        o.C = (int)vals.size();
-        for (int64_t m = 0; m < M; ++m) {
-            const int cls = (int)(std::lower_bound(vals.begin(), vals.end(), u[m]) - vals.begin());
-            o.bin_local[m] = blk[m] * o.C + cls;
+    o.bin_val.clear();
+    o.blk_bin_ptr.assign(1, 0);
+    for (int b = 0; b < nb; ++b) {
+        const int64_t m0 = bp[b], m1 = bp[b + 1];
+        std::vector<double> vals;
+        if (u) {
+            vals.assign(u + m0, u + m1);
+            std::sort(vals.begin(), vals.end());
+            vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        } else if (m1 > m0) {
+            vals.assign(1, 1.0);
         }
-    } else {
-        o.class_val.assign(1, 1.0);
-        o.C = 1;
-        for (int64_t m = 0; m < M; ++m) o.bin_local[m] = blk[m];
+        const int64_t off = o.blk_bin_ptr.back();
+        for (int64_t m = m0; m < m1; ++m) {
+            const int64_t cls = u ? (int64_t)(std::lower_bound(vals.begin(), vals.end(), u[m]) - vals.begin()) : 0;
+            o.bin_local[m] = (int32_t)(off + cls);
+        }
+        o.bin_val.insert(o.bin_val.end(), vals.begin(), vals.end());
+        o.blk_bin_ptr.push_back(off + (int64_t)vals.size());
     }
-    if (M == 0) o.C = std::max(o.C, 1);
     // stable counting sorts: by cell within the tile, then by bin, then by (tile,
     // region).  Within a (tile, region, bin) group the visibilities come in raster
     // order of their cells, so neighbouring lanes of the degridding read
     // neighbouring grid cells.
-    const int64_t nbins = (int64_t)std::max(nb, 1) * o.C;
+    const int64_t nbins = std::max<int64_t>(o.blk_bin_ptr.back(), 1);
     const int64_t nloc = (int64_t)T * T;
     std::vector<int64_t> cnt(std::max<int64_t>(std::max<int64_t>(nbins, ntr), nloc) + 1, 0);
     std::vector<int64_t> tmp0(M), tmp(M);
@@ -376,14 +379,13 @@ hs_status build_plan(hs_ctx* c) {
             c->h_pos_of[base + m] = g;
         }
         // bins and blocks
+        c->h_bin_u.insert(c->h_bin_u.end(), o.bin_val.begin(), o.bin_val.end());
         for (int b = 0; b < ch.nb; ++b) {
-            for (int cl = 0; cl < o.C; ++cl) {
-                c->h_bin_u.push_back(o.class_val[cl]);
-            }
-            c->h_blk_bin_ptr.push_back((int32_t)(bin_base + (int64_t)(b + 1) * o.C));
+            c->h_blk_bin_ptr.push_back((int32_t)(bin_base + o.blk_bin_ptr[b + 1]));
             c->h_blk_eps.push_back(ch.eps[b]);
         }
-        const int64_t nbins_l = (int64_t)ch.nb * o.C;
+        const int64_t nbins_l = o.blk_bin_ptr.back();
+        if (bin_base + nbins_l >= (int64_t)INT32_MAX) return fail(c, HS_ERR_SHAPE, "hs_plan: too many bins");
         // degridding units and their runs
         for (int t = 0; t < c->ntiles; ++t) {
             const int64_t s = o.region_ptr[(int64_t)t * 9], e = o.region_ptr[(int64_t)t * 9 + 9];
@@ -487,6 +489,7 @@ hs_status build_plan(hs_ctx* c) {
     // kernel polynomial (Chebyshev interpolant, rounding-level accurate)
     c->kb_terms = c->dtype == HS_F64 ? KBTerms<double>::n : KBTerms<float>::n;
     kb_chebyshev(c->kb_terms, c->kb_c);
+    if (c->dtype == HS_F32) kb_chebyshev(KBTerms<double>::n, c->kb_c64);
     return HS_OK;
 }
 

@@ -13,6 +13,18 @@ __global__ void k_fill(T* p, T v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
+template <typename S, typename D>
+__global__ void k_convert(D* __restrict__ dst, const S* __restrict__ src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (D)src[i];
+}
+
+template <typename S, typename D>
+void launch_convert(hipStream_t s, D* dst, const S* src, int64_t n) {
+    if (n > 0) k_convert<S, D><<<nb(n, 256), 256, 0, s>>>(dst, src, n);
+}
+template void launch_convert<float, double>(hipStream_t, double*, const float*, int64_t);
+
 template <typename T>
 __global__ void k_axpby(T* y, const T* x, T a, T b, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

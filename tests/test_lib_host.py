@@ -46,13 +46,17 @@ def test_density_precond_bit_exact():
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,tile,pre", [("cube32_L3", 8, True), ("cube64_L5", 16, True), ("cube64_L5", 32, False), ("cube128x64_L4", 16, True)])
+@pytest.mark.parametrize("name,tile,pre", [("cube32_L3", 8, True), ("cube64_L5", 16, True), ("cube64_L5", 32, False),
+                                           ("cube128x64_L4", 16, True), ("cube64_L5", 16, "continuous")])
 def test_visibility_order_bit_exact(name, tile, pre):
     from paper_1806_04596_amd import visibility_order
     cfg = W.CONFIGS[name]
     uvs, bps = W.synth.make_uv(cfg)
+    rng = np.random.default_rng(3)
     for uv, bp in zip(uvs, bps):
         u = precond.density_precond(uv, cfg.nx, cfg.ny) if pre else None
+        if pre == "continuous":       # a distinct value for almost every visibility
+            u = u * rng.uniform(0.5, 1.0, len(u))
         perm, rp = visibility_order(uv, u, bp, cfg.nx, cfg.ny, tile)
         perm_o, rp_o = binning.order(uv, u, bp, cfg.nx, cfg.ny, tile)
         assert np.array_equal(perm, perm_o)
