@@ -34,76 +34,61 @@ static long double i0_of_beta() {
     return s;
 }
 
-int kb_terms_needed(int mantissa_bits) {
-    std::vector<long double> t;
-    i0_terms(kb_beta_ld(), t, 200);
-    const long double I0 = i0_of_beta();
-    const long double tol = std::ldexp(1.0L, -(mantissa_bits + 2));
-    for (int n = 1; n < KB_MAX_TERMS; ++n) {
-        long double tail = 0.0L;
-        for (int k = n; k < 200; ++k) tail += t[k];
-        if (tail / I0 <= tol) return n;
-    }
-    return KB_MAX_TERMS;
-}
-
-void kb_series(int terms, std::vector<double>& coef, double& beta) {
-    std::vector<long double> t;
-    const long double b = kb_beta_ld();
-    i0_terms(b, t, terms);
-    const long double I0 = i0_of_beta();
-    coef.resize(terms);
-    for (int k = 0; k < terms; ++k) coef[k] = (double)(t[k] / I0);
-    beta = (double)b;
-}
-
-// Chebyshev interpolant of phi as a function of s = 2w - 1 on [-1, 1]
-// (w = 1 - (2d/J)^2), converted to monomial coefficients in s.  phi is the
-// entire function I0(beta sqrt(w))/I0(beta) of w, so the interpolant converges
-// geometrically; every coefficient comes out positive (stable Horner).
-void kb_chebyshev(int terms, std::vector<double>& coef) {
+// Chebyshev interpolant of phi(f + 3 - j) for f in [0, 1] (tap j), converted to
+// monomial coefficients in t = f - 1/2 (coefficients below 1 in magnitude, so the
+// Horner evaluation is well conditioned).  phi is the entire function
+// I0(beta sqrt(w))/I0(beta) of w = 1 - (2d/J)^2, so the interpolant converges
+// faster than geometrically.
+void kb_taps(int deg, std::vector<double>& coef) {
     const long double pi = 3.141592653589793238462643383279502884L;
     const long double b = kb_beta_ld();
     std::vector<long double> t;
     i0_terms(b, t, 200);
     const long double I0 = i0_of_beta();
-    auto phi_w = [&](long double w) {
+    auto phi = [&](long double d) {
+        const long double w = 1.0L - (2.0L * d / KB_J) * (2.0L * d / KB_J);
+        if (w < 0) return 0.0L;
         long double acc = 0.0L;
         for (int k = 199; k >= 0; --k) acc = acc * w + t[k];
         return acc / I0;
     };
-    const int n = terms;
-    std::vector<long double> cc(n, 0.0L);
-    for (int j = 0; j < n; ++j) {
-        long double sum = 0.0L;
-        for (int k = 0; k < n; ++k) {
-            const long double th = pi * ((long double)k + 0.5L) / (long double)n;
-            const long double sk = std::cos(th);
-            sum += phi_w(0.5L * (sk + 1.0L)) * std::cos((long double)j * th);
+    const int n = deg + 1;
+    coef.assign((size_t)4 * n, 0.0);
+    for (int j = 0; j < 4; ++j) {
+        // Chebyshev coefficients in u = 2t on [-1, 1]
+        std::vector<long double> cc(n, 0.0L);
+        for (int q = 0; q < n; ++q) {
+            long double sum = 0.0L;
+            for (int k = 0; k < n; ++k) {
+                const long double th = pi * ((long double)k + 0.5L) / (long double)n;
+                const long double u = std::cos(th);
+                sum += phi(0.5L * (u + 1.0L) + 3.0L - j) * std::cos((long double)q * th);
+            }
+            cc[q] = sum * 2.0L / (long double)n;
         }
-        cc[j] = sum * 2.0L / (long double)n;
-    }
-    cc[0] *= 0.5L;
-    // Chebyshev -> monomial in s: T_0 = 1, T_1 = s, T_{j+1} = 2 s T_j - T_{j-1}
-    std::vector<long double> m(n, 0.0L), Tm1(n, 0.0L), T0(n, 0.0L), T1(n, 0.0L);
-    T0[0] = 1.0L;
-    m[0] += cc[0];
-    if (n > 1) {
-        T1[1] = 1.0L;
-        m[1] += cc[1];
-    }
-    for (int j = 2; j < n; ++j) {
-        std::vector<long double> Tn(n, 0.0L);
-        for (int k = 0; k < n; ++k) {
-            if (k + 1 < n) Tn[k + 1] += 2.0L * T1[k];
-            Tn[k] -= T0[k];
+        cc[0] *= 0.5L;
+        // Chebyshev -> monomial in u: T_0 = 1, T_1 = u, T_{q+1} = 2 u T_q - T_{q-1}
+        std::vector<long double> m(n, 0.0L), T0(n, 0.0L), T1(n, 0.0L);
+        T0[0] = 1.0L;
+        m[0] += cc[0];
+        if (n > 1) {
+            T1[1] = 1.0L;
+            m[1] += cc[1];
         }
-        for (int k = 0; k < n; ++k) m[k] += cc[j] * Tn[k];
-        T0 = T1;
-        T1 = Tn;
+        for (int q = 2; q < n; ++q) {
+            std::vector<long double> Tn(n, 0.0L);
+            for (int k = 0; k < n; ++k) {
+                if (k + 1 < n) Tn[k + 1] += 2.0L * T1[k];
+                Tn[k] -= T0[k];
+            }
+            for (int k = 0; k < n; ++k) m[k] += cc[q] * Tn[k];
+            T0 = T1;
+            T1 = Tn;
+        }
+        // u = 2t
+        long double p2 = 1.0L;
+        for (int k = 0; k < n; ++k, p2 *= 2.0L) coef[(size_t)j * n + k] = (double)(m[k] * p2);
     }
-    coef.assign(n, 0.0);
-    for (int k = 0; k < n; ++k) coef[k] = (double)m[k];
 }
 
 // Continuous Fourier transform of the normalised kernel (closed form).
@@ -486,10 +471,10 @@ hs_status build_plan(hs_ctx* c) {
         std::vector<int32_t> fillp(c->h_bin_run_ptr.begin(), c->h_bin_run_ptr.end() - 1);
         for (auto& pr : run_bin) c->h_run_slot[pr.second] = fillp[pr.first]++;
     }
-    // kernel polynomial (Chebyshev interpolant, rounding-level accurate)
-    c->kb_terms = c->dtype == HS_F64 ? KBTerms<double>::n : KBTerms<float>::n;
-    kb_chebyshev(c->kb_terms, c->kb_c);
-    if (c->dtype == HS_F32) kb_chebyshev(KBTerms<double>::n, c->kb_c64);
+    // kernel polynomials per tap (Chebyshev interpolants, rounding-level accurate)
+    c->kb_terms = (c->dtype == HS_F64 ? KBDeg<double>::n : KBDeg<float>::n) + 1;
+    kb_taps(c->kb_terms - 1, c->kb_c);
+    if (c->dtype == HS_F32) kb_taps(KBDeg<double>::n, c->kb_c64);
     return HS_OK;
 }
 

@@ -443,24 +443,27 @@ void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
 }
 
 // ------------------------------------------------------------- KB kernel
-// phi(d) = I0(beta sqrt(1 - (d/4)^2)) / I0(beta) through its Chebyshev
-// interpolant in s = 1 - d^2/8 (coefficients from the plan, all positive),
-// evaluated by Horner with a compile-time number of terms so the coefficients
-// stay in scalar registers.
-template <typename T>
-__device__ __forceinline__ T kb_eval(T d, const KBPoly<T>& P) {
-    constexpr int NT = KBTerms<T>::n;
-    const T s = T(1) - d * d * T(0.125);
-    T acc = P.c[NT - 1];
-#pragma unroll
-    for (int k = NT - 2; k >= 0; --k) acc = acc * s + P.c[k];
-    return acc;
-}
-
+// The eight kernel values phi(f + 3 - j), j = 0..7, of a fractional offset f from
+// the per-tap polynomials of the plan (taps 0..3; tap 7 - j is tap j at -t):
+// 2 x (the even and odd Horner chains in t^2) per pair of taps, the coefficients
+// uniform across lanes (scalar operands).
 template <typename T>
 __device__ __forceinline__ void kb_weights(T f, const KBPoly<T>& P, T* w) {
+    constexpr int NE = KBPoly<T>::NE, NO = KBPoly<T>::NO;
+    const T t = f - T(0.5);
+    const T t2 = t * t;
 #pragma unroll
-    for (int j = 0; j < KB_J; ++j) w[j] = kb_eval(f + T(3 - j), P);
+    for (int j = 0; j < 4; ++j) {
+        T e = P.e[j][NE - 1];
+#pragma unroll
+        for (int k = NE - 2; k >= 0; --k) e = e * t2 + P.e[j][k];
+        T o = P.o[j][NO - 1];
+#pragma unroll
+        for (int k = NO - 2; k >= 0; --k) o = o * t2 + P.o[j][k];
+        const T to = t * o;
+        w[j] = e + to;
+        w[KB_J - 1 - j] = e - to;
+    }
 }
 
 // ------------------------------------------------------------- degridding
@@ -974,11 +977,15 @@ __global__ __launch_bounds__(256) void k_proj_block(cplx<T>* __restrict__ z, con
 }
 
 // ------------------------------------------------------------------ launchers
+// Kernel-argument form of the plan's per-tap coefficients ([4][deg + 1] in t).
 template <typename T>
 static KBPoly<T> kbpoly(const hs_ctx* c) {
     KBPoly<T> p{};
-    p.n = KBTerms<T>::n;
-    for (int k = 0; k < p.n; ++k) p.c[k] = (T)c->kb_c[k];
+    constexpr int n = KBDeg<T>::n + 1;
+    for (int j = 0; j < 4; ++j) {
+        for (int k = 0; k < KBPoly<T>::NE; ++k) p.e[j][k] = (T)c->kb_c[(size_t)j * n + 2 * k];
+        for (int k = 0; k < KBPoly<T>::NO; ++k) p.o[j][k] = (T)c->kb_c[(size_t)j * n + 2 * k + 1];
+    }
     return p;
 }
 
