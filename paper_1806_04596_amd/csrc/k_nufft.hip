@@ -775,7 +775,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int GR_WS = KB_J + 1;   // staged kernel values per entry (odd stride)
+// Staged operands of one entry: its eight kernel values with a zero on each side,
+// so that an operand is a single LDS read at a clamped index (no masks).
+constexpr int GR_WS = KB_J + 2;
+constexpr int GR_BATCH = 32;   // entries staged per batch (two lanes per entry)
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
@@ -783,69 +786,98 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
     cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int nbx, KBPoly<T> kb) {
     typedef typename GridAcc<T>::type acc_t;
-    __shared__ T swx[64 * GR_WS], swy[64 * GR_WS];
-    __shared__ T svr[64], svi[64];
-    __shared__ int sdx[64], sdy[64];   // offsets of the first tap from the block origin
+    // entry e: sA[e][1 + j] = wy_e(j), sB[e][1 + j] = wx_e(j) v_e, zeros at 0 and KB_J + 1;
+    // sd[e] = (dy, dx), the offsets of its first tap from the block origin
+    __shared__ T sA[GR_BATCH * GR_WS];
+    __shared__ cplx<T> sB[GR_BATCH * GR_WS];
+    __shared__ int sd[2 * GR_BATCH];
     const GridUnit u = units[blockIdx.x];
     const int lane = threadIdx.x, il = lane & 15, kq = lane >> 4;
+    // staging: lane (e, dim) = (lane % 32, lane / 32) evaluates one dimension of entry e
+    const int se = lane & (GR_BATCH - 1), dim = lane / GR_BATCH;
     const int bx0 = (u.tile % nbx - 1) * GB, by0 = (u.tile / nbx) * GB;   // bx0 = -GB for the margin block
     const int32_t* gl = glist + u.g0;
     const int n = u.gn;
+    if (dim) {
+        sA[se * GR_WS] = T(0);
+        sA[se * GR_WS + KB_J + 1] = T(0);
+    } else {
+        sB[se * GR_WS] = cplx<T>{T(0), T(0)};
+        sB[se * GR_WS + KB_J + 1] = cplx<T>{T(0), T(0)};
+    }
     // two accumulator pairs (even and odd groups of four entries), so that
     // consecutive products do not wait on each other
     acc_t are0{}, aim0{}, are1{}, aim1{};
-    // the next batch's list positions are loaded while this batch is gridded
-    int posn = lane < n ? gl[lane] : -1;
-    for (int base = 0; base < n; base += 64) {
-        const int pos = posn;
-        posn = base + 64 + lane < n ? gl[base + 64 + lane] : -1;
-        int dx = 64, dy = 64;   // an empty slot: every tap falls outside the block
-        T vr = T(0), vi = T(0);
-        T wx8[KB_J], wy8[KB_J];
-        if (pos >= 0) {
-            const int cc = cell[pos];
-            const cplx<T> f = frac[pos];
-            cplx<T> val = vals[pos];
-            if (weight) {
-                const T w = weight[pos];
-                val.re *= w;
-                val.im *= w;
+    // software pipeline: the next batch's entry data are loaded while this batch
+    // is gridded, and the list positions of the one after
+    int cc_n = 0;
+    T f_n = T(0);
+    cplx<T> val_n{T(0), T(0)};
+    T w_n = T(1);
+    auto fetch = [&](int p) {
+        if (p >= 0) {
+            cc_n = cell[p];
+            const T* fp = reinterpret_cast<const T*>(frac + p);
+            f_n = fp[dim];
+            if (!dim) {
+                val_n = vals[p];
+                if (weight) w_n = weight[p];
             }
-            dx = (cc & 0x7FFF) - 3 - bx0;   // the half plane has no wrap in x
-            dy = (cc >> 16) - 3 - by0;
-            if (dy < -(KB_J - 1)) dy += Ky;
-            if (dy > GB - 1) dy -= Ky;
-            kb_weights(f.re, kb, wx8);
-            kb_weights(f.im, kb, wy8);
-            vr = val.re;
-            vi = (cc & 0x8000) ? -val.im : val.im;   // reflected: conjugate value
+        }
+    };
+    int pos_n = se < n ? gl[se] : -1;
+    fetch(pos_n);
+    int pos_nn = GR_BATCH + se < n ? gl[GR_BATCH + se] : -1;
+    for (int base = 0; base < n; base += GR_BATCH) {
+        const int pos = pos_n;
+        const int cc = cc_n;
+        const T f = f_n;
+        cplx<T> val = val_n;
+        const T wt = w_n;
+        pos_n = pos_nn;
+        fetch(pos_n);
+        pos_nn = base + 2 * GR_BATCH + se < n ? gl[base + 2 * GR_BATCH + se] : -1;
+        int d0 = 2 * GB;   // an empty slot: every tap falls outside the block
+        T w8[KB_J];
+        if (pos >= 0) {
+            if (dim) {
+                d0 = (cc >> 16) - 3 - by0;
+                if (d0 < -(KB_J - 1)) d0 += Ky;
+                if (d0 > GB - 1) d0 -= Ky;
+            } else {
+                d0 = (cc & 0x7FFF) - 3 - bx0;   // the half plane has no wrap in x
+            }
+            kb_weights(f, kb, w8);
         } else {
 #pragma unroll
-            for (int j = 0; j < KB_J; ++j) wx8[j] = wy8[j] = T(0);
+            for (int j = 0; j < KB_J; ++j) w8[j] = T(0);
         }
+        if (dim) {
 #pragma unroll
-        for (int j = 0; j < KB_J; ++j) {
-            swx[lane * GR_WS + j] = wx8[j];
-            swy[lane * GR_WS + j] = wy8[j];
+            for (int j = 0; j < KB_J; ++j) sA[se * GR_WS + 1 + j] = w8[j];
+        } else {
+            if (weight) {
+                val.re *= wt;
+                val.im *= wt;
+            }
+            const T vr = val.re, vi = (cc & 0x8000) ? -val.im : val.im;   // reflected: conjugate value
+#pragma unroll
+            for (int j = 0; j < KB_J; ++j) sB[se * GR_WS + 1 + j] = cplx<T>{w8[j] * vr, w8[j] * vi};
         }
-        svr[lane] = vr;
-        svi[lane] = vi;
-        sdx[lane] = dx;
-        sdy[lane] = dy;
+        sd[2 * se + (dim ^ 1)] = d0;   // (dy, dx)
         wave_lds_sync();
-        const int ng = (min(64, n - base) + 3) >> 2;
-        // the staged reads are unconditional (indices wrapped into the entry's
-        // row) and masked afterwards, so they carry no branches and the reads
-        // of later groups overlap the products of earlier ones
+        const int ng = (min(GR_BATCH, n - base) + 3) >> 2;
+        // row il of A is wy_e(il - dy_e) and column il of B is wx_e(il - dx_e) v_e:
+        // the tap index clamped to [-1, KB_J] reads a zero outside the footprint
         auto step = [&](int q, acc_t& are, acc_t& aim) {
             const int e = 4 * q + kq;
-            const int ty = il - sdy[e], tx = il - sdx[e];
-            const T ay = swy[e * GR_WS + (ty & (KB_J - 1))];
-            const T wx = swx[e * GR_WS + (tx & (KB_J - 1))];
-            const T a = ((unsigned)ty < (unsigned)KB_J) ? ay : T(0);
-            const T w = ((unsigned)tx < (unsigned)KB_J) ? wx : T(0);
-            are = grid_mfma(a, w * svr[e], are);
-            aim = grid_mfma(a, w * svi[e], aim);
+            const int2 d = *reinterpret_cast<const int2*>(&sd[2 * e]);
+            const int iy = min(max(il - d.x, -1), KB_J) + 1;
+            const int ix = min(max(il - d.y, -1), KB_J) + 1;
+            const T a = sA[e * GR_WS + iy];
+            const cplx<T> b = sB[e * GR_WS + ix];
+            are = grid_mfma(a, b.re, are);
+            aim = grid_mfma(a, b.im, aim);
         };
         int q = 0;
         for (; q + 1 < ng; q += 2) {
