@@ -34,6 +34,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-channels", type=int, default=3, help="channels of the oracle's CPU sample")
     p.add_argument("--phase-iters", type=int, default=5)
+    p.add_argument("--norm-iters", type=int, default=1000,
+                   help="power iterations for the step-size norm (relative tolerance 1e-10)")
     p.add_argument("--phases-only", action="store_true",
                    help="only the eager per-phase timing (for rocprofv3 kernel traces and counters)")
     p.add_argument("--calib-copy", action="store_true",
@@ -236,7 +238,7 @@ def main():
     prob, X0, _ = build_problem(cfg, inputs, W.make_measurements, dtype="f32", data=data)
     info = prob.info()
     x0 = torch.as_tensor(W.synth.power_start(cfg), dtype=prob.tdtype, device=prob.device).contiguous()
-    nrm, _, it_norm = prob.op_norm(x0, max_it=1000, tol=1e-10)   # FP64 power iteration
+    nrm, _, it_norm = prob.op_norm(x0, max_it=args.norm_iters, tol=1e-10)   # FP64 power iteration
     kappa3 = 1.0 / nrm
     mu, tau = 0.01, 0.33
     prob.pd_init(mu=mu, tau=tau, kappa3=kappa3)

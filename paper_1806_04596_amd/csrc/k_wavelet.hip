@@ -27,6 +27,14 @@ constexpr int WV_HALO = 14; // 2 * 8 - 2
 constexpr int WV_W = WV_TO / 2 + 8;   // synthesis coefficient window per subband
 constexpr int64_t IDWT_MIN_WG = 2048;  // smallest synthesis grid worth looping bases for
 
+// Tile of work item t (of n): work-groups are dispatched round-robin over the 8
+// XCDs, each with its own L2, so t mod 8 names the XCD; when n is a multiple of 8
+// each XCD takes a contiguous band of n/8 tiles (whole tile rows), so the halo a
+// tile shares with its neighbours is read through the same L2.
+__device__ __forceinline__ int xcd_band(int t, int n) {
+    return (n & 7) ? t : (t & 7) * (n >> 3) + (t >> 3);
+}
+
 // k mod n for 0 <= k < 2n + W (one subtraction in the usual case; small
 // coarse levels fall back to the remainder).
 __device__ __forceinline__ int wrap_idx(int k, int n) {
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
     const int nitems = ntiles * L * (lev0 ? 1 : n_db);
     T win[NW];
     auto fetch = [&](int item) {
-        const int tile = item % ntiles, rest = item / ntiles;
+        const int tile = xcd_band(item % ntiles, ntiles), rest = item / ntiles;
         const int l = rest % L, b = rest / L;
         const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
         const T* src = lev0 ? X + (size_t)l * N : llin + ((size_t)b * L + l) * (size_t)my * mx;
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
     int item = blockIdx.x;
     if (item < nitems) fetch(item);
     for (; item < nitems; item += gridDim.x) {
-        const int tile = item % ntiles, rest = item / ntiles;
+        const int tile = xcd_band(item % ntiles, ntiles), rest = item / ntiles;
         const int l = rest % L;
         const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
         const int b_first = lev0 ? 0 : rest / L;
@@ -248,7 +256,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
     __shared__ T Tm[2][TO][W + 1];         // after the column inverse, per x-subband
     const int hx = mx >> 1, hy = my >> 1;
     const int ntx = (mx + TO - 1) / TO;
-    const int m0y = (blockIdx.x / ntx) * TO, m0x = (blockIdx.x % ntx) * TO;
+    const int tile = xcd_band(blockIdx.x, gridDim.x);
+    const int m0y = (tile / ntx) * TO, m0x = (tile % ntx) * TO;
     const int l = blockIdx.y;
     const size_t N = (size_t)nx * ny;
     const int tid = threadIdx.x;
