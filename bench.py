@@ -34,6 +34,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-channels", type=int, default=3, help="channels of the oracle's CPU sample")
     p.add_argument("--phase-iters", type=int, default=5)
+    p.add_argument("--tune-cache", default=None,
+                   help="autotuner cache (JSON lines); default: the package's tuning_cache.jsonl")
+    p.add_argument("--gram-mode", default="f64", choices=["f64", "f32", "bf16_split"])
     p.add_argument("--norm-iters", type=int, default=1000,
                    help="power iterations for the step-size norm (relative tolerance 1e-10)")
     p.add_argument("--phases-only", action="store_true",
@@ -235,7 +238,8 @@ def main():
     if args.no_fp64:
         p64.close()
         p64 = None
-    prob, X0, _ = build_problem(cfg, inputs, W.make_measurements, dtype="f32", data=data)
+    prob, X0, _ = build_problem(cfg, inputs, W.make_measurements, dtype="f32", data=data, autotune=True,
+                                tune_cache=args.tune_cache, gram_mode=args.gram_mode)
     info = prob.info()
     x0 = torch.as_tensor(W.synth.power_start(cfg), dtype=prob.tdtype, device=prob.device).contiguous()
     nrm, _, it_norm = prob.op_norm(x0, max_it=args.norm_iters, tol=1e-10)   # FP64 power iteration
@@ -250,7 +254,8 @@ def main():
         torch.cuda.synchronize()
         if args.calib_copy:
             calib_copy()
-        print(json.dumps({"phases_ms": {k: round(v, 4) for k, v in phases.items()}, "workload": cfg.name}), flush=True)
+        print(json.dumps({"phases_ms": {k: round(v, 4) for k, v in phases.items()}, "workload": cfg.name,
+                          "tuning": prob.tuning(), "setup_s": round(setup_s, 1)}), flush=True)
         return
 
     # warm-up (the first call captures one iteration into a HIP graph)
@@ -344,7 +349,7 @@ def main():
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} image, L={cfg.L} channels, "
                                f"{prob.M} visibilities (uneven per channel), {cfg.n_blocks} blocks/channel, "
                                f"Dirac+db1-db8 x 4 levels, KB 8x8 2x oversampled, FP32 batched graph replay",
-                   "n_vis": prob.M, "tile": info["tile"]},
+                   "n_vis": prob.M, "gram_mode": args.gram_mode, "tuning": prob.tuning()},
         "phi_vis_per_s": round(prob.M / t_phi, 1), "phi_adj_vis_per_s": round(prob.M / t_adj, 1),
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "iteration_algorithmic_GB": round(iter_bytes / 1e9, 3),

@@ -97,7 +97,7 @@ typedef struct {
     int64_t n_degrid_units; /* degridding work units */
     int64_t n_grid_units;   /* gridding work units */
     int32_t tile;           /* tile edge used */
-    int32_t kb_terms;       /* terms of the kernel's power series */
+    int32_t kb_terms;       /* coefficients of the kernel's per-tap polynomials */
     size_t workspace_bytes;
 } hs_info;
 
@@ -226,6 +226,48 @@ hs_status hs_plan(hs_ctx* ctx, size_t* workspace_bytes);
 hs_status hs_bind_workspace(hs_ctx* ctx, void* dev, size_t bytes);
 
 hs_status hs_get_info(const hs_ctx* ctx, hs_info* info);
+
+/* ---------------------------------------------------------------- tuning */
+/* The work decomposition of the batched operators (all channels per launch):
+ *   tile:           visibility tile edge of the degridding (8, 16 or 32);
+ *   grid_split:     entries per gridding work unit (a 16 x 16 output block with
+ *                   more entries is split and its partial blocks summed);
+ *   degrid_batches: batches of 256 visibilities per degridding work unit;
+ *   fft_col_tile:   columns per work-group of the FFT column passes (2..16);
+ *   ms:             measured time of this choice (0: not measured).
+ * A 0 field means the library's default. */
+typedef struct {
+    int32_t tile;
+    int32_t grid_split;
+    int32_t degrid_batches;
+    int32_t fft_col_tile;
+    double ms;
+} hs_tuning;
+
+/* The decomposition in use (after hs_plan). */
+hs_status hs_get_tuning(const hs_ctx* ctx, hs_tuning* out);
+
+/* Sets the decomposition (validated); re-plans when the context is planned, after
+ * which a workspace must be bound again (hs_plan reports its size). */
+hs_status hs_set_tuning(hs_ctx* ctx, const hs_tuning* t);
+
+/* Bytes of the temporary workspace hs_autotune needs (the largest plan among the
+ * candidates).  After hs_plan. */
+hs_status hs_autotune_bytes(hs_ctx* ctx, size_t* bytes);
+
+/* Autotuner of the batching (Algorithm 2's operators batched over channels): times
+ * the data-fidelity branch of one iteration (forward FFT, degridding with the dual
+ * step, projection, gridding, adjoint FFT) on the GPU for candidate
+ * decompositions (coordinate descent over
+ * the tile edge, the gridding split, the degridding unit size and the FFT column
+ * tile), keeps the fastest and re-plans with it.  dev/bytes: a caller-allocated
+ * temporary workspace of at least hs_autotune_bytes bytes, free to reuse after the
+ * call.  cache_path (may be NULL): a JSON-lines file of earlier choices keyed by the
+ * problem shape (nx, ny, L, visibilities, dtype); a hit skips the timing, a miss
+ * appends the new choice.  chosen (may be NULL) receives the choice.  Leaves the
+ * context planned and unbound: bind a workspace of the size hs_plan reports; the
+ * primal-dual state starts at zero.  Synchronising. */
+hs_status hs_autotune(hs_ctx* ctx, void* dev, size_t bytes, const char* cache_path, hs_tuning* chosen);
 
 /* ------------------------------------------------ host utilities (no GPU) */
 /* Density preconditioner (Sec. 3.3): out[m] = 1/n_m with n_m the number of

@@ -11,6 +11,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhypersara.so")
+TUNING_CACHE = os.path.join(HERE, "tuning_cache.jsonl")
 
 HS_OK = 0
 HS_F32, HS_F64 = 0, 1
@@ -32,6 +33,11 @@ class Info(C.Structure):
     _fields_ = [("n_vis", C.c_int64), ("n_blocks", C.c_int64), ("n_bins", C.c_int64), ("n_runs", C.c_int64),
                 ("n_degrid_units", C.c_int64), ("n_grid_units", C.c_int64), ("tile", C.c_int32),
                 ("kb_terms", C.c_int32), ("workspace_bytes", C.c_size_t)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("grid_split", C.c_int32), ("degrid_batches", C.c_int32),
+                ("fft_col_tile", C.c_int32), ("ms", C.c_double)]
 
 
 class PDParams(C.Structure):
@@ -73,6 +79,10 @@ SIGNATURES = {
     "hs_plan": (C.c_int32, [ctxp, C.POINTER(C.c_size_t)]),
     "hs_bind_workspace": (C.c_int32, [ctxp, P, C.c_size_t]),
     "hs_get_info": (C.c_int32, [ctxp, C.POINTER(Info)]),
+    "hs_get_tuning": (C.c_int32, [ctxp, C.POINTER(Tuning)]),
+    "hs_set_tuning": (C.c_int32, [ctxp, C.POINTER(Tuning)]),
+    "hs_autotune_bytes": (C.c_int32, [ctxp, C.POINTER(C.c_size_t)]),
+    "hs_autotune": (C.c_int32, [ctxp, P, C.c_size_t, C.c_char_p, C.POINTER(Tuning)]),
     "hs_density_precond": (C.c_int32, [C.c_int64, dptr, C.c_int32, C.c_int32, dptr]),
     "hs_visibility_order": (C.c_int32, [C.c_int64, dptr, dptr, C.c_int32, i64p, C.c_int32, C.c_int32, C.c_int32,
                                         i64p, i64p]),

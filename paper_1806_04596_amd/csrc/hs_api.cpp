@@ -1,8 +1,11 @@
 // C ABI entry points: lifecycle, workspace, operators, proxes and the PD solver.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <exception>
+#include <fstream>
+#include <sstream>
 
 #include "hs_internal.h"
 
@@ -531,6 +534,7 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
     c->L = d.L;
     c->Kx = 2 * d.nx;
     c->Ky = 2 * d.ny;
+    c->Kh = d.nx;
     c->N = (int64_t)d.nx * d.ny;
     c->n_db = d.n_db;
     c->D = 1 + d.n_db;
@@ -1131,6 +1135,267 @@ hs_status hs_solve(hs_ctx* c, const hs_solve_params* p, void* X_out, hs_report* 
         rep->gamma_bar = gamma_bar;
     }
     return HS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+namespace hs {
+
+// A candidate replaces the best one only when it is faster by more than the
+// run-to-run spread of the timing.
+constexpr double TUNE_MARGIN = 0.98;
+
+static hs_tuning tuning_of(const hs_ctx* c) {
+    hs_tuning t{};
+    t.tile = c->T;
+    t.grid_split = c->grid_split;
+    t.degrid_batches = c->deg_batches;
+    t.fft_col_tile = fft_col_tile(c);
+    t.ms = c->tune_ms;
+    return t;
+}
+
+static bool tile_ok(const hs_ctx* c, int T) {
+    return T >= 8 && T <= 32 && (T & (T - 1)) == 0 && c->Kx % T == 0 && c->Ky % T == 0 && c->Kx / T >= 3 &&
+           c->Ky / T >= 3;
+}
+
+static hs_status apply_tuning(hs_ctx* c, const hs_tuning& t) {
+    if (t.tile && !tile_ok(c, t.tile)) return fail(c, HS_ERR_INVALID_ARG, "tuning: tile must be 8, 16 or 32 (>= 3 tiles per dimension)");
+    if (t.grid_split && (t.grid_split < 64 || t.grid_split > (1 << 20)))
+        return fail(c, HS_ERR_INVALID_ARG, "tuning: grid_split in 64..2^20");
+    if (t.degrid_batches && (t.degrid_batches < 1 || t.degrid_batches > 64))
+        return fail(c, HS_ERR_INVALID_ARG, "tuning: degrid_batches in 1..64");
+    if (t.fft_col_tile && !fft_col_tile_ok(c, t.fft_col_tile))
+        return fail(c, HS_ERR_INVALID_ARG, "tuning: fft_col_tile must be a power of two that fits the column passes");
+    c->tune_tile = t.tile;
+    c->grid_split = t.grid_split ? t.grid_split : GRID_SPLIT;
+    c->deg_batches = t.degrid_batches ? t.degrid_batches : DEG_BATCHES;
+    c->fft_ct = t.fft_col_tile;
+    c->tune_ms = t.ms;
+    return HS_OK;
+}
+
+// Plans with the context's tunables; the workspace size is recomputed and the
+// context left unbound.
+static hs_status replan(hs_ctx* c) {
+    hs_status s = build_plan(c);
+    if (s) return s;
+    c->ws_bytes = carve(c, nullptr);
+    c->planned = true;
+    c->bound = false;
+    c->pd_ready = false;
+    c->graph_valid = false;
+    return HS_OK;
+}
+
+static std::string tune_key(const hs_ctx* c) {
+    std::ostringstream k;
+    k << c->nx << "x" << c->ny << "x" << c->L << "_M" << c->Mtot << "_" << (c->dtype == HS_F32 ? "f32" : "f64");
+    return k.str();
+}
+
+static bool cache_lookup(const char* path, const std::string& key, hs_tuning& t) {
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (std::getline(in, line)) {
+        if (line.find(pat) == std::string::npos) continue;
+        hs_tuning u{};
+        auto num = [&](const char* name, double& v) {
+            const std::string f = std::string("\"") + name + "\": ";
+            const size_t p = line.find(f);
+            if (p == std::string::npos) return false;
+            v = std::atof(line.c_str() + p + f.size());
+            return true;
+        };
+        double a, b, d, e, ms = 0;
+        if (num("tile", a) && num("grid_split", b) && num("degrid_batches", d) && num("fft_col_tile", e)) {
+            num("ms", ms);
+            u.tile = (int)a;
+            u.grid_split = (int)b;
+            u.degrid_batches = (int)d;
+            u.fft_col_tile = (int)e;
+            u.ms = ms;
+            t = u;
+            found = true;   // the last entry of the key wins
+        }
+    }
+    return found;
+}
+
+static void cache_append(const char* path, const std::string& key, const hs_tuning& t) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"tile\": %d, \"grid_split\": %d, \"degrid_batches\": %d, \"fft_col_tile\": %d, \"ms\": %.5f}\n",
+                 key.c_str(), t.tile, t.grid_split, t.degrid_batches, t.fft_col_tile, t.ms);
+    std::fclose(f);
+}
+
+// Fastest of 8 runs (after one warm-up) of the data-fidelity branch of one PD
+// iteration on the bound workspace (F Z, the degridding and dual step, the
+// projection roots and update, the gridding, F^H Z^T): the operators the
+// decomposition shapes.  It starts from the zero state the workspace was bound with.
+template <typename T>
+static hs_status time_ops(hs_ctx* c, double& ms) {
+    hipEvent_t e0, e1;
+    hs_status s = hip_check(c, hipEventCreate(&e0), "hipEventCreate");
+    if (s) return s;
+    s = hip_check(c, hipEventCreate(&e1), "hipEventCreate");
+    if (s) { (void)hipEventDestroy(e0); return s; }
+    std::vector<double> t;
+    for (int r = 0; r < 9 && !s; ++r) {
+        (void)hipEventRecord(e0, c->stream);
+        dual_data_impl<T>(c, (cplx<T>*)c->d.v, (const T*)c->d.Xt, (T*)c->d.img0);
+        (void)hipEventRecord(e1, c->stream);
+        s = hip_check(c, hipEventSynchronize(e1), "autotune timing");
+        float m = 0.f;
+        if (!s) s = hip_check(c, hipEventElapsedTime(&m, e0, e1), "hipEventElapsedTime");
+        if (r > 0) t.push_back(m);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    ms = *std::min_element(t.begin(), t.end());
+    return launched(c, "autotune timing");
+}
+
+}  // namespace hs
+
+extern "C" {
+
+hs_status hs_get_tuning(const hs_ctx* c, hs_tuning* out) {
+    if (!c || !out) return HS_ERR_INVALID_ARG;
+    if (!c->planned) return HS_ERR_NOT_PLANNED;
+    *out = tuning_of(c);
+    return HS_OK;
+}
+
+hs_status hs_set_tuning(hs_ctx* c, const hs_tuning* t) {
+    HS_TRY_BEGIN
+    if (!c || !t) return HS_ERR_INVALID_ARG;
+    hs_status s = apply_tuning(c, *t);
+    if (s) return s;
+    if (c->planned) return replan(c);
+    return HS_OK;
+    HS_TRY_END(c)
+}
+
+hs_status hs_autotune_bytes(hs_ctx* c, size_t* bytes) {
+    HS_TRY_BEGIN
+    if (!c || !bytes) return HS_ERR_INVALID_ARG;
+    if (!c->planned) return fail(c, HS_ERR_NOT_PLANNED, "call hs_plan first");
+    const hs_tuning keep = tuning_of(c);
+    const int keep_tile = c->tune_tile, keep_ct = c->fft_ct;
+    size_t mx = c->ws_bytes;
+    hs_status s = HS_OK;
+    // the largest plan: each tile edge with the smallest units
+    for (int T : {8, 16, 32}) {
+        if (!tile_ok(c, T)) continue;
+        hs_tuning t{T, 512, 2, 0, 0.0};
+        s = apply_tuning(c, t);
+        if (!s) s = build_plan(c);
+        if (s) break;
+        mx = std::max(mx, carve(c, nullptr));
+    }
+    hs_tuning back = keep;
+    back.tile = keep_tile;
+    back.fft_col_tile = keep_ct;
+    hs_status s2 = apply_tuning(c, back);
+    if (!s2) s2 = build_plan(c);
+    if (s) return s;
+    if (s2) return s2;
+    *bytes = mx;
+    return HS_OK;
+    HS_TRY_END(c)
+}
+
+hs_status hs_autotune(hs_ctx* c, void* dev, size_t bytes, const char* cache_path, hs_tuning* chosen) {
+    HS_TRY_BEGIN
+    if (!c) return HS_ERR_INVALID_ARG;
+    if (!c->planned) return fail(c, HS_ERR_NOT_PLANNED, "call hs_plan first");
+    const std::string key = tune_key(c);
+    hs_tuning best{};
+    hs_status s = HS_OK;
+    if (cache_path && cache_lookup(cache_path, key, best)) {
+        s = apply_tuning(c, best);
+        if (!s) s = replan(c);
+        if (!s && chosen) *chosen = tuning_of(c);
+        return s;
+    }
+    if (!dev || ((uintptr_t)dev & 255)) return fail(c, HS_ERR_INVALID_ARG, "autotune workspace: 256-byte aligned device memory");
+    s = hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    if (s) return s;
+    fft_init_attrs();
+    // evaluate one decomposition: plan, lay out in the temporary workspace, upload, time
+    auto eval = [&](const hs_tuning& t, double& ms) -> hs_status {
+        hs_status r = apply_tuning(c, t);
+        if (!r) r = build_plan(c);
+        if (r) return r;
+        const size_t need = carve(c, nullptr);
+        if (need > bytes) return fail(c, HS_ERR_NO_WORKSPACE, "autotune workspace too small (see hs_autotune_bytes)");
+        carve(c, (char*)dev);
+        c->planned = true;
+        r = c->dtype == HS_F32 ? bind_impl<float>(c) : bind_impl<double>(c);
+        if (r) return r;
+        c->bound = true;
+        r = c->dtype == HS_F32 ? time_ops<float>(c, ms) : time_ops<double>(c, ms);
+        c->bound = false;
+        return r;
+    };
+    best = hs_tuning{0, GRID_SPLIT, DEG_BATCHES, 0, 0.0};
+    double best_ms = 1e30;
+    // coordinate descent: tile edge, gridding split, degridding unit, FFT column tile
+    for (int T : {32, 16, 8}) {
+        if (!tile_ok(c, T)) continue;
+        hs_tuning t = best;
+        t.tile = T;
+        double ms;
+        if ((s = eval(t, ms))) return s;
+        if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = t; }
+    }
+    for (int g : {512, 2048}) {
+        hs_tuning t = best;
+        t.grid_split = g;
+        double ms;
+        if ((s = eval(t, ms))) return s;
+        if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = t; }
+    }
+    for (int b : {2, 8}) {
+        hs_tuning t = best;
+        t.degrid_batches = b;
+        double ms;
+        if ((s = eval(t, ms))) return s;
+        if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = t; }
+    }
+    {
+        // the column tile needs no new plan: time it on the best plan
+        hs_tuning base = best;
+        double ms;
+        if ((s = eval(base, ms))) return s;
+        best_ms = std::min(best_ms, ms);
+        base.fft_col_tile = fft_col_tile(c);
+        best = base;
+        for (int ct : {2, 4, 8, 16}) {
+            if (ct == base.fft_col_tile || !fft_col_tile_ok(c, ct)) continue;
+            c->fft_ct = ct;
+            if ((s = (c->dtype == HS_F32 ? [&] { carve(c, (char*)dev); c->bound = true; return time_ops<float>(c, ms); }()
+                                         : [&] { carve(c, (char*)dev); c->bound = true; return time_ops<double>(c, ms); }())))
+                return s;
+            c->bound = false;
+            if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = base; best.fft_col_tile = ct; }
+        }
+    }
+    best.ms = best_ms;
+    s = apply_tuning(c, best);
+    if (!s) s = replan(c);
+    if (s) return s;
+    if (cache_path) cache_append(cache_path, key, tuning_of(c));
+    if (chosen) *chosen = tuning_of(c);
+    return HS_OK;
+    HS_TRY_END(c)
 }
 
 }  // extern "C"

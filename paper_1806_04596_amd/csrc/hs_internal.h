@@ -15,8 +15,8 @@ constexpr int KB_J = 8;             // kernel support per dimension (taps)
 constexpr int KB_MAX_TERMS = 40;    // power-series terms of the kernel (upper bound)
 constexpr int MAX_L = 64;           // channels (Gram matrix edge)
 constexpr int DEG_THREADS = 256;    // degridding workgroup = one batch of visibilities
-constexpr int DEG_BATCHES = 4;      // batches per degridding work unit
-constexpr int GRID_SPLIT = 1024;    // entries per gridding work unit
+constexpr int DEG_BATCHES = 4;      // default batches per degridding work unit (tunable)
+constexpr int GRID_SPLIT = 1024;    // default entries per gridding work unit (tunable)
 constexpr int MAX_DB = 8;
 constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
 
@@ -186,6 +186,10 @@ struct hs_ctx {
     // negative kx are reflected); visibility tiles cover [0, Kx/2 + T), gridding
     // blocks [-GB, Kx/2 + GB) of the Wg columns of a grid row (column = kx + GR_MARGIN).
     int T = 32, tiles_x = 0, tiles_y = 0, ntiles = 0;   // visibility tiles
+    // tunables (hs_set_tuning / hs_autotune): tile edge (0 = rule), entries per gridding
+    // unit, batches per degridding unit, columns per FFT column tile (0 = rule)
+    int tune_tile = 0, grid_split = hs::GRID_SPLIT, deg_batches = hs::DEG_BATCHES, fft_ct = 0;
+    double tune_ms = 0.0;
     int gtiles_x = 0, ngtiles = 0;                      // gridding blocks (GB x GB) in x, in all
     int Kh = 0, Wh = 0, Wg = 0, Hs = 0;                 // Kx/2, Kx/2 + 1, Kx/2 + 2 GR_MARGIN, Kx/2 + 16
     int64_t Mtot = 0;
@@ -240,6 +244,8 @@ template <typename T> void launch_axpby(hipStream_t s, T* y, const T* x, T a, T 
 
 // NUFFT (k_nufft.hip)
 void fft_init_attrs();
+int fft_col_tile(const hs_ctx* c);              // columns per column-pass tile in use
+bool fft_col_tile_ok(const hs_ctx* c, int ct);  // ct fits the column passes of c
 template <typename T> void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L);
 template <typename T> void launch_fft_cols_fwd(hs_ctx* c, int L);
 template <typename T> void launch_fft_cols_adj(hs_ctx* c, int L);

@@ -296,7 +296,7 @@ hs_status build_plan(hs_ctx* c) {
     const int L = c->L;
     for (int l = 0; l < L; ++l)
         if (!c->ch[l].set) return fail(c, HS_ERR_INVALID_ARG, "hs_plan: channel " + std::to_string(l) + " not set");
-    int T = c->desc.tile;
+    int T = c->tune_tile ? c->tune_tile : c->desc.tile;
     if (T == 0) {
         T = 32;
         while (T > 8 && (c->Kx / T < 3 || c->Ky / T < 3 || c->Kx % T || c->Ky % T)) T /= 2;
@@ -343,7 +343,7 @@ hs_status build_plan(hs_ctx* c) {
     std::vector<std::pair<int32_t, int32_t>> run_bin;  // (bin, run)
     int64_t nruns = 0, npartial = 0;
     int64_t bin_base = 0;
-    const int unit_max = DEG_THREADS * DEG_BATCHES;
+    const int unit_max = DEG_THREADS * c->deg_batches;
     for (int l = 0; l < L; ++l) {
         const Channel& ch = c->ch[l];
         ChanOrder o;
@@ -437,7 +437,7 @@ hs_status build_plan(hs_ctx* c) {
             }
             for (int t = 0; t < nbx * nby; ++t) {
                 const int64_t s0 = bcnt[t], e0 = bcnt[t + 1], En = e0 - s0;
-                const int nsplit = (int)std::max<int64_t>(1, (En + GRID_SPLIT - 1) / GRID_SPLIT);
+                const int nsplit = (int)std::max<int64_t>(1, (En + c->grid_split - 1) / c->grid_split);
                 for (int sp = 0; sp < nsplit; ++sp) {
                     GridUnit gu{};
                     gu.l = l;

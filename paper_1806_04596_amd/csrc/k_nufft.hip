@@ -363,14 +363,24 @@ static int row_group(const hs_ctx* c) {
     while (4 * p <= c->ny && (c->ny % (4 * p)) == 0 && c->Kx * p * 2 <= 8192) p *= 2;
     return p;
 }
-// Columns per tile for the column passes (16 elements per thread, <= 512 threads, LDS <= 128 KiB).
+// Columns per tile for the column passes (16 elements per thread, <= 512 threads, LDS <= 128 KiB):
+// the tuned value when set, else the widest that fits.
+static bool col_tile_fits(const hs_ctx* c, int ct, size_t csz) {
+    return ct >= 1 && ct <= 16 && (ct & (ct - 1)) == 0 && ct <= c->Kh && (size_t)c->Ky * ct * csz <= 131072 &&
+           c->Ky * ct <= 8192;
+}
 template <typename T>
 static int col_group(const hs_ctx* c) {
-    const int maxE = (int)(131072 / sizeof(cplx<T>));
+    if (c->fft_ct > 0 && col_tile_fits(c, c->fft_ct, sizeof(cplx<T>))) return c->fft_ct;
     int ct = 1;
-    while (ct * 2 <= c->Kh && c->Ky * ct * 2 <= maxE && c->Ky * ct * 2 <= 8192 && ct < 16)
-        ct *= 2;
+    while (col_tile_fits(c, ct * 2, sizeof(cplx<T>))) ct *= 2;
     return ct;
+}
+int fft_col_tile(const hs_ctx* c) {
+    return c->dtype == HS_F32 ? col_group<float>(c) : col_group<double>(c);
+}
+bool fft_col_tile_ok(const hs_ctx* c, int ct) {
+    return col_tile_fits(c, ct, c->dtype == HS_F32 ? sizeof(cplx<float>) : sizeof(cplx<double>));
 }
 static size_t row_lds(const hs_ctx* c, int rows, size_t csz) {
     return (size_t)rows * (c->Kx + (c->Kx >> 4)) * csz;

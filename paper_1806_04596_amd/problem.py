@@ -32,7 +32,11 @@ class Problem:
     """
 
     def __init__(self, nx: int, ny: int, channels, dtype: str = "f32", levels: int = 4, n_db: int = 8,
-                 tile: int = 0, device: int = 0, stream=None, gram_mode: str = "f64"):
+                 tile: int = 0, device: int = 0, stream=None, gram_mode: str = "f64", autotune: bool = False,
+                 tune_cache: str | None = None, tuning: dict | None = None):
+        """autotune: pick the batching decomposition with hs_autotune (timed on this GPU,
+        cached in tune_cache, default the package's tuning_cache.jsonl); tuning: an
+        explicit decomposition (hs_set_tuning fields) instead."""
         torch = _require_gpu()
         self.torch = torch
         self.lib = L.load()
@@ -68,8 +72,22 @@ class Problem:
             self.counts.append(M)
             self.nblocks.append(len(bp) - 1)
             self._block_ptrs.append(bp.copy())
+        if tuning:
+            t = L.Tuning(**{k: int(v) for k, v in tuning.items() if k != "ms"})
+            self._chk(self.lib.hs_set_tuning(ctx, C.byref(t)), "hs_set_tuning")
         ws = C.c_size_t()
         self._chk(self.lib.hs_plan(ctx, C.byref(ws)), "hs_plan")
+        if autotune:
+            tb = C.c_size_t()
+            self._chk(self.lib.hs_autotune_bytes(ctx, C.byref(tb)), "hs_autotune_bytes")
+            tmp = torch.empty(tb.value + 256, dtype=torch.uint8, device=self.device)
+            cache = (tune_cache or L.TUNING_CACHE).encode()
+            chosen = L.Tuning()
+            torch.cuda.synchronize(self.device)
+            self._chk(self.lib.hs_autotune(ctx, C.c_void_p((tmp.data_ptr() + 255) // 256 * 256), tb.value, cache,
+                                           C.byref(chosen)), "hs_autotune")
+            del tmp
+            self._chk(self.lib.hs_plan(ctx, C.byref(ws)), "hs_plan")
         self.ws_bytes = ws.value
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -102,6 +120,11 @@ class Problem:
     @staticmethod
     def _p(t):
         return C.c_void_p(t.data_ptr()) if t is not None else None
+
+    def tuning(self):
+        t = L.Tuning()
+        self._chk(self.lib.hs_get_tuning(self.ctx, C.byref(t)), "hs_get_tuning")
+        return {k: getattr(t, k) for k, _ in L.Tuning._fields_}
 
     def info(self):
         i = L.Info()

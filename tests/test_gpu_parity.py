@@ -7,7 +7,8 @@ import pytest
 
 import workloads as W
 from oracle import nufft, pd, prox, wavelets
-from gpu_cases import TOL, check_rel, check_rel_pc, gpu_case, host, oracle_case, rel, rel_per_channel, split, to_dev
+from gpu_cases import (TOL, check_rel, check_rel_pc, gpu_case, host, oracle_case, oracle_data, rel,
+                       rel_per_channel, split, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -470,3 +471,42 @@ def test_continuous_preconditioner(dtype):
     for l in range(cfg.L):
         check_rel(vg[l], ref.v[l], TOL[dtype], f"v[{l}] after one iteration")
     prob.close()
+
+
+def test_autotuned_and_explicit_decompositions(tmp_path):
+    """The batching decomposition (tile edge, gridding split, degridding unit, FFT
+    column tile) chosen by the autotuner, taken from its cache, or set explicitly:
+    every choice gives the same operator (Phi and Phi^dagger against the oracle)."""
+    import paper_1806_04596_amd as H
+    from paper_1806_04596_amd.workload import build_problem
+    cfg, inp, op = oracle_case("cube64_L5")
+    cache = str(tmp_path / "tune.jsonl")
+    rng = np.random.default_rng(80)
+    X = inp["X0"] + 0.1 * rng.standard_normal(inp["X0"].shape)
+    y = rng.standard_normal(sum(len(u) for u in op.uv)) + 1j * rng.standard_normal(sum(len(u) for u in op.uv))
+
+    def check(prob):
+        Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+        ref = op.phi(X)
+        assert max(rel(Y[l], ref[l]) for l in range(cfg.L)) <= TOL["f32"]
+        check_rel_pc(host(prob.phi_adj(to_dev(prob, y, complex_=True))), op.phi_adj(split(y, prob.counts)),
+                     TOL["f32"], "Phi^dagger")
+
+    data = oracle_data("cube64_L5")
+    p1, _, _ = build_problem(cfg, inp, W.make_measurements, dtype="f32", data=data, autotune=True, tune_cache=cache)
+    t1 = p1.tuning()
+    assert t1["tile"] in (8, 16, 32) and t1["ms"] > 0 and t1["grid_split"] in (512, 1024, 2048)
+    check(p1)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and '"key": "64x64x5_M' in lines[0]
+    p2, _, _ = build_problem(cfg, inp, W.make_measurements, dtype="f32", data=data, autotune=True, tune_cache=cache)
+    t2 = p2.tuning()
+    assert t2.pop("ms") == pytest.approx(t1.pop("ms"), abs=1e-5) and t2 == t1     # a cache hit: no new timing
+    assert len(open(cache).read().splitlines()) == 1
+    p3, _, _ = build_problem(cfg, inp, W.make_measurements, dtype="f32", data=data,
+                             tuning=dict(tile=8, grid_split=512, degrid_batches=2, fft_col_tile=2))
+    t3 = p3.tuning()
+    assert (t3["tile"], t3["grid_split"], t3["degrid_batches"], t3["fft_col_tile"]) == (8, 512, 2, 2)
+    check(p3)
+    for p in (p1, p2, p3):
+        p.close()
