@@ -74,7 +74,11 @@ enum { HS_GRAM_F64 = 0, HS_GRAM_F32 = 1, HS_GRAM_BF16_SPLIT = 2 };
  * dtype: HS_F32 or HS_F64.  tile: gridding tile edge (0 = automatic; else a
  *   power of two in 8..32 with 2*nx/tile >= 3 and 2*ny/tile >= 3).
  * device: HIP device ordinal; stream: hipStream_t (NULL = default stream).
- * gram_mode: HS_GRAM_F64 / HS_GRAM_F32 / HS_GRAM_BF16_SPLIT (above). */
+ * gram_mode: HS_GRAM_F64 / HS_GRAM_F32 / HS_GRAM_BF16_SPLIT (above).
+ * per_channel: 0 = batched execution (every operator one launch over all
+ *   channels, the PD iteration replayed from a captured HIP graph); nonzero =
+ *   plain execution (the channel-separable operators launched channel by
+ *   channel, the iteration eager), the comparator of the batched path. */
 typedef struct {
     int32_t nx, ny, L;
     int32_t oversamp;
@@ -86,6 +90,7 @@ typedef struct {
     int32_t device;
     void* stream;
     int32_t gram_mode;
+    int32_t per_channel;
 } hs_problem_desc;
 
 /* Sizes after hs_plan. */

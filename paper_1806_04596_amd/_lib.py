@@ -26,7 +26,7 @@ STATUS = {0: "HS_OK", -1: "HS_ERR_INVALID_ARG", -2: "HS_ERR_SHAPE", -3: "HS_ERR_
 class ProblemDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("L", C.c_int32), ("oversamp", C.c_int32), ("J", C.c_int32),
                 ("levels", C.c_int32), ("n_db", C.c_int32), ("dtype", C.c_int32), ("tile", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p), ("gram_mode", C.c_int32)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("gram_mode", C.c_int32), ("per_channel", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -225,19 +225,39 @@ static hs_status bind_impl(hs_ctx* c) {
 }
 
 // ------------------------------------------------------------- operator bodies
+// F Z of X into the grid: all channels in one launch per pass, or (plain execution,
+// lc >= 0) channel lc only.
+template <typename T>
+static void fft_fwd(hs_ctx* c, const T* X, int lc = -1) {
+    const int L = lc < 0 ? c->L : 1, l0 = lc < 0 ? 0 : lc;
+    launch_fft_rows_fwd<T>(c, X, L, l0);
+    launch_fft_cols_fwd<T>(c, L, l0);
+}
+
 template <typename T>
 static void phi_impl(hs_ctx* c, const T* X, cplx<T>* Y) {
-    launch_fft_rows_fwd<T>(c, X, c->L);
-    launch_fft_cols_fwd<T>(c, c->L);
-    launch_degrid_plain<T>(c, Y);
+    if (!c->per_channel) {
+        fft_fwd<T>(c, X);
+        launch_degrid_plain<T>(c, Y);
+        return;
+    }
+    for (int l = 0; l < c->L; ++l) {
+        fft_fwd<T>(c, X, l);
+        launch_degrid_plain<T>(c, Y, l);
+    }
 }
 
 // grid-order visibility values (already weighted) -> Re Z^T F^H G^T vals
 template <typename T>
-static void adj_from_grid_order(hs_ctx* c, const cplx<T>* vals, const T* weight, T* X) {
-    launch_grid_pull<T>(c, vals, weight);
-    launch_fft_cols_adj<T>(c, c->L);
-    launch_fft_rows_adj<T>(c, X, c->L);
+static void adj_from_grid_order(hs_ctx* c, const cplx<T>* vals, const T* weight, T* X, int lc = -1) {
+    const int L = lc < 0 ? c->L : 1, l0 = lc < 0 ? 0 : lc;
+    if (lc < 0 && c->per_channel) {
+        for (int l = 0; l < c->L; ++l) adj_from_grid_order<T>(c, vals, weight, X, l);
+        return;
+    }
+    launch_grid_pull<T>(c, vals, weight, lc);
+    launch_fft_cols_adj<T>(c, L, l0);
+    launch_fft_rows_adj<T>(c, X, L, l0);
 }
 
 template <typename T>
@@ -258,11 +278,21 @@ struct PhaseMarks {
 // and F^H Z^T into adj if given.
 template <typename T>
 static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const PhaseMarks& pm = PhaseMarks(),
-                           bool fft_fwd = true, hipEvent_t after_degrid = nullptr) {
-    if (fft_fwd) {
-        launch_fft_rows_fwd<T>(c, Xt, c->L);
-        launch_fft_cols_fwd<T>(c, c->L);
+                           bool do_fft_fwd = true, hipEvent_t after_degrid = nullptr) {
+    if (c->per_channel) {
+        // plain execution: the whole chain channel by channel, one launch per kernel and channel
+        for (int l = 0; l < c->L; ++l) {
+            fft_fwd<T>(c, Xt, l);
+            launch_degrid_dual_v<T>(c, v, l);
+            launch_bins_and_roots<T>(c, l);
+            launch_dual_apply_v<T>(c, v, l);
+            if (adj) adj_from_grid_order<T>(c, v, (const T*)c->d.vis_theta, adj, l);
+        }
+        for (int k = HS_PH_FFT_FWD; k <= HS_PH_FFT_ADJ; ++k) pm.mark(c, k + 1);
+        if (after_degrid) (void)hipEventRecord(after_degrid, c->stream);
+        return;
     }
+    if (do_fft_fwd) fft_fwd<T>(c, Xt);
     pm.mark(c, HS_PH_FFT_FWD + 1);
     launch_degrid_dual_v<T>(c, v);
     pm.mark(c, HS_PH_DEGRID + 1);
@@ -332,8 +362,7 @@ static void pd_iter_forked(hs_ctx* c) {
     (void)hipEventRecord(c->ev_fork, main);
     if (nuc && NUC_START == 0) { (void)hipStreamWaitEvent(c->side[0], c->ev_fork, 0); branch_nuc(); }
     if (sp && L21_START == 0) { (void)hipStreamWaitEvent(c->side[1], c->ev_fork, 0); branch_l21(); }
-    launch_fft_rows_fwd<T>(c, Xt, c->L);
-    launch_fft_cols_fwd<T>(c, c->L);
+    fft_fwd<T>(c, Xt);
     if ((nuc && NUC_START == 1) || (sp && L21_START == 1)) {
         (void)hipEventRecord(c->ev_mid, main);
         if (nuc && NUC_START == 1) { (void)hipStreamWaitEvent(c->side[0], c->ev_mid, 0); branch_nuc(); }
@@ -385,10 +414,17 @@ static hs_status op_norm_impl(hs_ctx* c, int max_it, double tol, const T* x0, do
     std::vector<double> lam(c->L, 0.0), prev(c->L, 0.0);
     int it = 0;
     for (it = 1; it <= max_it; ++it) {
-        launch_fft_rows_fwd<T>(c, x, c->L);
-        launch_fft_cols_fwd<T>(c, c->L);
-        launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)d.vis_u);
-        adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, x);
+        if (c->per_channel) {
+            for (int l = 0; l < c->L; ++l) {
+                fft_fwd<T>(c, x, l);
+                launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)d.vis_u, l);
+                adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, x, l);
+            }
+        } else {
+            fft_fwd<T>(c, x);
+            launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)d.vis_u);
+            adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, x);
+        }
         launch_chan_norms<T>(c, x, d.chan_nrm);
         hs_status s = hip_check(c, hipMemcpyAsync(lam.data(), d.chan_nrm, c->L * 8, hipMemcpyDeviceToHost, c->stream),
                                 "hs_op_norm");
@@ -423,9 +459,15 @@ static hs_status dirty_mu_impl(hs_ctx* c, T* Xd, double* mu) {
     T* X = Xd ? Xd : (T*)d.img0;
     launch_fill<T>(c->stream, delta, T(0), LN);
     launch_set_center<T>(c, delta);
-    launch_fft_rows_fwd<T>(c, delta, c->L);
-    launch_fft_cols_fwd<T>(c, c->L);
-    launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)nullptr);
+    if (c->per_channel) {
+        for (int l = 0; l < c->L; ++l) {
+            fft_fwd<T>(c, delta, l);
+            launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)nullptr, l);
+        }
+    } else {
+        fft_fwd<T>(c, delta);
+        launch_degrid_grid_order<T>(c, (cplx<T>*)d.vwork, (const T*)nullptr);
+    }
     adj_from_grid_order<T>(c, (const cplx<T>*)d.vwork, (const T*)d.vis_theta, psf);
     launch_chan_max<T>(c, psf, d.chan_nrm);
     adj_from_grid_order<T>(c, (const cplx<T>*)d.vis_y, (const T*)d.vis_theta, X);
@@ -541,6 +583,7 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
     c->levels = d.levels;
     c->dtype = d.dtype;
     c->gram_mode = d.gram_mode;
+    c->per_channel = d.per_channel != 0;
     c->rsz = d.dtype == HS_F32 ? 4 : 8;
     c->stream = (hipStream_t)d.stream;
     c->device = d.device;
@@ -984,8 +1027,8 @@ hs_status hs_pd_iterate(hs_ctx* c, int32_t n) {
     if (!c->pd_ready) return fail(c, HS_ERR_INVALID_ARG, "call hs_pd_init first");
     if (n < 0) return fail(c, HS_ERR_INVALID_ARG, "n < 0");
     if (n == 0) return HS_OK;
-    if (c->stream == nullptr) {
-        // the legacy default stream cannot be captured: run eagerly
+    if (c->stream == nullptr || c->per_channel) {
+        // the legacy default stream cannot be captured, and the plain execution is eager
         for (int i = 0; i < n; ++i) HS_DISPATCH(c, pd_iter_impl<T>(c));
         c->t_iter += n;
         return launched(c, "hs_pd_iterate");

@@ -199,6 +199,10 @@ struct hs_ctx {
     std::vector<hs::DegridUnit> dunits;
     std::vector<hs::GridUnit> gunits;
     std::vector<hs::SplitTile> splits;
+    // per-channel ranges [off[l], off[l + 1]) of the work lists and bins (one launch
+    // per channel in the plain, unbatched execution)
+    std::vector<int64_t> dunit_off, gunit_off, split_off, bin_off;
+    bool per_channel = false;          // plain execution: one launch per channel, eager iteration
     int kb_terms = 0;
     std::vector<double> kb_c;          // power-series coefficients
     std::vector<double> kb_c64;        // FP64 coefficients (the FP64 power iteration of an FP32 context)
@@ -246,16 +250,18 @@ template <typename T> void launch_axpby(hipStream_t s, T* y, const T* x, T a, T 
 void fft_init_attrs();
 int fft_col_tile(const hs_ctx* c);              // columns per column-pass tile in use
 bool fft_col_tile_ok(const hs_ctx* c, int ct);  // ct fits the column passes of c
-template <typename T> void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L);
-template <typename T> void launch_fft_cols_fwd(hs_ctx* c, int L);
-template <typename T> void launch_fft_cols_adj(hs_ctx* c, int L);
-template <typename T> void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L);
-template <typename T> void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user);
-template <typename T> void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult);
-template <typename T> void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v);
-template <typename T> void launch_bins_and_roots(hs_ctx* c);
-template <typename T> void launch_dual_apply_v(hs_ctx* c, cplx<T>* v);
-template <typename T> void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight);
+// Channel ranges: the FFT launchers transform channels l0 .. l0 + L - 1; lc < 0 means
+// every channel, lc >= 0 channel lc only (the plain, one-launch-per-channel execution).
+template <typename T> void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L, int l0 = 0);
+template <typename T> void launch_fft_cols_fwd(hs_ctx* c, int L, int l0 = 0);
+template <typename T> void launch_fft_cols_adj(hs_ctx* c, int L, int l0 = 0);
+template <typename T> void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L, int l0 = 0);
+template <typename T> void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user, int lc = -1);
+template <typename T> void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult, int lc = -1);
+template <typename T> void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v, int lc = -1);
+template <typename T> void launch_bins_and_roots(hs_ctx* c, int lc = -1);
+template <typename T> void launch_dual_apply_v(hs_ctx* c, cplx<T>* v, int lc = -1);
+template <typename T> void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight, int lc = -1);
 template <typename T> void launch_gather_user(hs_ctx* c, const cplx<T>* in_user, cplx<T>* out_grid, bool times_theta);
 template <typename T> void launch_scatter_user(hs_ctx* c, const cplx<T>* in_grid, cplx<T>* out_user);
 template <typename T> void launch_proj_block(hs_ctx* c, int64_t pos0_user, int64_t Mb, int blk, cplx<T>* z);

@@ -344,6 +344,10 @@ hs_status build_plan(hs_ctx* c) {
     int64_t nruns = 0, npartial = 0;
     int64_t bin_base = 0;
     const int unit_max = DEG_THREADS * c->deg_batches;
+    c->dunit_off.assign(1, 0);
+    c->gunit_off.assign(1, 0);
+    c->split_off.assign(1, 0);
+    c->bin_off.assign(1, 0);
     for (int l = 0; l < L; ++l) {
         const Channel& ch = c->ch[l];
         ChanOrder o;
@@ -457,6 +461,10 @@ hs_status build_plan(hs_ctx* c) {
             }
         }
         bin_base += nbins_l;
+        c->dunit_off.push_back((int64_t)c->dunits.size());
+        c->gunit_off.push_back((int64_t)c->gunits.size());
+        c->split_off.push_back((int64_t)c->splits.size());
+        c->bin_off.push_back(bin_base);
     }
     c->nbins = bin_base;
     c->nruns = nruns;

@@ -421,35 +421,45 @@ void fft_init_attrs() {
     done = true;
 }
 
+// The transforms of channels l0 .. l0 + L - 1 (the channel index of each work-group
+// is relative to the offset base pointers).
 template <typename T>
-void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L) {
+void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L, int l0) {
     const int p = row_group(c);
     dim3 grid(c->ny / (2 * p), L);
     HS_FFT_LEN_SWITCH(c->Kx, (k_fft_rows_fwd<T, NN><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
-        X, (cplx<T>*)c->d.H, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
-        c->Hs, p)))
+        X + (size_t)l0 * c->N, (cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs, (const T*)c->d.sx, (const T*)c->d.sy,
+        (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Hs, p)))
 }
 template <typename T>
-void launch_fft_cols_fwd(hs_ctx* c, int L) {
+void launch_fft_cols_fwd(hs_ctx* c, int L, int l0) {
     const int ct = col_group<T>(c);
     dim3 grid((c->Wh + ct - 1) / ct, L);
     HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_fwd<T, NN><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.H, (cplx<T>*)c->d.grid, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
+        (const cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs, (cplx<T>*)c->d.grid + (size_t)l0 * c->Ky * c->Wg,
+        (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
 }
 template <typename T>
-void launch_fft_cols_adj(hs_ctx* c, int L) {
+void launch_fft_cols_adj(hs_ctx* c, int L, int l0) {
     const int ct = col_group<T>(c);
     dim3 grid((c->Wh + ct - 1) / ct, L);
     HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_adj<T, NN><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.grid, (cplx<T>*)c->d.H, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
+        (const cplx<T>*)c->d.grid + (size_t)l0 * c->Ky * c->Wg, (cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs,
+        (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
 }
 template <typename T>
-void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L) {
+void launch_fft_rows_adj(hs_ctx* c, T* Xout, int L, int l0) {
     const int p = row_group(c);
     dim3 grid(c->ny / (2 * p), L);
     HS_FFT_LEN_SWITCH(c->Kx, (k_fft_rows_adj<T, NN><<<grid, c->Kx * p / 16, row_lds(c, p, sizeof(cplx<T>)), c->stream>>>(
-        (const cplx<T>*)c->d.H, Xout, (const T*)c->d.sx, (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny,
-        c->Hs, p)))
+        (const cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs, Xout + (size_t)l0 * c->N, (const T*)c->d.sx,
+        (const T*)c->d.sy, (const cplx<T>*)c->d.tw_x, c->nx, c->ny, c->Hs, p)))
+}
+
+// Work-list range of channel lc (lc < 0: every channel).
+static inline void chan_range(const std::vector<int64_t>& off, int lc, int64_t& b, int64_t& n) {
+    if (lc < 0) { b = 0; n = off.back(); }
+    else { b = off[lc]; n = off[lc + 1] - off[lc]; }
 }
 
 // ------------------------------------------------------------- KB kernel
@@ -1034,23 +1044,27 @@ static KBPoly<T> kbpoly(const hs_ctx* c) {
 static inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <typename T>
-void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user) {
-    if (c->dunits.empty()) return;
+void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user, int lc) {
+    int64_t u0, nu;
+    chan_range(c->dunit_off, lc, u0, nu);
+    if (nu == 0) return;
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
-    k_degrid_plain<T, true, false><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
-        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+    k_degrid_plain<T, true, false><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
+        c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x,
         kbpoly<T>(c));
 }
 
 // Degrid into grid order with an extra per-visibility factor (used by the power iteration).
 template <typename T>
-void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult) {
-    if (c->dunits.empty()) return;
+void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult, int lc) {
+    int64_t u0, nu;
+    chan_range(c->dunit_off, lc, u0, nu);
+    if (nu == 0) return;
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
     auto launch = [&](auto kern) {
-        kern<<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
-            c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+        kern<<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
+            c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
             (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
     };
     if (mult) launch(k_degrid_plain<T, false, true>);
@@ -1058,40 +1072,53 @@ void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult) {
 }
 
 template <typename T>
-void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v) {
-    if (c->dunits.empty()) return;
+void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v, int lc) {
+    int64_t u0, nu;
+    chan_range(c->dunit_off, lc, u0, nu);
+    if (nu == 0) return;
     const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
-    k_degrid_dual<T><<<(unsigned)c->dunits.size(), DEG_THREADS, lds, c->stream>>>(
-        c->d.dunits, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
+    k_degrid_dual<T><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
+        c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
         c->d.chunk_run, c->d.run_slot, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
 }
 
 template <typename T>
-void launch_bins_and_roots(hs_ctx* c) {
-    if (c->nbins == 0) return;
-    k_bin_reduce<<<nblocks(c->nbins * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr, c->d.run_sum,
-                                                                       c->d.bin_S, (int)c->nbins);
-    k_block_roots<<<nblocks(c->nblk * 64, 256), 256, 0, c->stream>>>(
-        c->d.blk_bin_ptr, c->d.bin_S, c->d.bin_u, c->d.bin_f, c->dtype == HS_F32 ? 1 : 0, c->d.blk_eps, c->d.blk_lambda,
-        c->d.blk_rho2, c->d.blk_vartheta,
-        c->d.scal, (int)c->nblk, c->adaptive ? 1 : 0, c->lam1, c->lam2, c->lam3, c->vartheta_bar);
+void launch_bins_and_roots(hs_ctx* c, int lc) {
+    int64_t b0, nbn;
+    chan_range(c->bin_off, lc, b0, nbn);
+    const int64_t k0 = lc < 0 ? 0 : c->blk_off[lc];
+    const int64_t nk = lc < 0 ? c->nblk : c->blk_off[lc + 1] - c->blk_off[lc];
+    if (nbn > 0)
+        k_bin_reduce<<<nblocks(nbn * 64, 256), 256, 0, c->stream>>>(c->d.bin_run_ptr + b0, c->d.run_sum,
+                                                                     c->d.bin_S + 2 * b0, (int)nbn);
+    if (nk > 0)
+        k_block_roots<<<nblocks(nk * 64, 256), 256, 0, c->stream>>>(
+            c->d.blk_bin_ptr + k0, c->d.bin_S, c->d.bin_u, c->d.bin_f, c->dtype == HS_F32 ? 1 : 0, c->d.blk_eps + k0,
+            c->d.blk_lambda + k0, c->d.blk_rho2 + k0, c->d.blk_vartheta + k0,
+            c->d.scal, (int)nk, c->adaptive ? 1 : 0, c->lam1, c->lam2, c->lam3, c->vartheta_bar);
 }
 
 template <typename T>
-void launch_dual_apply_v(hs_ctx* c, cplx<T>* v) {
-    if (c->Mtot == 0) return;
-    k_dual_apply<T><<<nblocks(c->Mtot, 256), 256, 0, c->stream>>>(v, c->d.vis_bin, c->d.bin_f, c->Mtot);
+void launch_dual_apply_v(hs_ctx* c, cplx<T>* v, int lc) {
+    int64_t m0, nm;
+    chan_range(c->chan_off, lc, m0, nm);
+    if (nm == 0) return;
+    k_dual_apply<T><<<nblocks(nm, 256), 256, 0, c->stream>>>(v + m0, c->d.vis_bin + m0, c->d.bin_f, nm);
 }
 
 template <typename T>
-void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight) {
-    k_grid_pull<T><<<(unsigned)c->gunits.size(), 64, 0, c->stream>>>(
-        c->d.gunits, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight, (cplx<T>*)c->d.grid,
-        (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->gtiles_x, kbpoly<T>(c));
-    if (!c->splits.empty())
-        k_grid_merge<T><<<(unsigned)c->splits.size(), 256, 0, c->stream>>>(
-            c->d.splits, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->gtiles_x);
+void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight, int lc) {
+    int64_t g0, ng, s0, ns;
+    chan_range(c->gunit_off, lc, g0, ng);
+    chan_range(c->split_off, lc, s0, ns);
+    if (ng > 0)
+        k_grid_pull<T><<<(unsigned)ng, 64, 0, c->stream>>>(
+            c->d.gunits + g0, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight,
+            (cplx<T>*)c->d.grid, (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->gtiles_x, kbpoly<T>(c));
+    if (ns > 0)
+        k_grid_merge<T><<<(unsigned)ns, 256, 0, c->stream>>>(
+            c->d.splits + s0, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->gtiles_x);
 }
 
 template <typename T>
@@ -1114,17 +1141,17 @@ void launch_scatter_user(hs_ctx* c, const cplx<T>* in_grid, cplx<T>* out_user) {
 }
 
 #define HS_INST(T)                                                                          \
-    template void launch_fft_rows_fwd<T>(hs_ctx*, const T*, int);                           \
-    template void launch_fft_cols_fwd<T>(hs_ctx*, int);                                     \
-    template void launch_fft_cols_adj<T>(hs_ctx*, int);                                     \
-    template void launch_fft_rows_adj<T>(hs_ctx*, T*, int);                                 \
-    template void launch_degrid_plain<T>(hs_ctx*, cplx<T>*);                                \
-    template void launch_degrid_grid_order<T>(hs_ctx*, cplx<T>*, const T*);                 \
-    template void launch_degrid_dual_v<T>(hs_ctx*, cplx<T>*);                               \
-    template void launch_bins_and_roots<T>(hs_ctx*);                                        \
-    template void launch_dual_apply_v<T>(hs_ctx*, cplx<T>*);                                \
+    template void launch_fft_rows_fwd<T>(hs_ctx*, const T*, int, int);                      \
+    template void launch_fft_cols_fwd<T>(hs_ctx*, int, int);                                \
+    template void launch_fft_cols_adj<T>(hs_ctx*, int, int);                                \
+    template void launch_fft_rows_adj<T>(hs_ctx*, T*, int, int);                            \
+    template void launch_degrid_plain<T>(hs_ctx*, cplx<T>*, int);                           \
+    template void launch_degrid_grid_order<T>(hs_ctx*, cplx<T>*, const T*, int);            \
+    template void launch_degrid_dual_v<T>(hs_ctx*, cplx<T>*, int);                          \
+    template void launch_bins_and_roots<T>(hs_ctx*, int);                                   \
+    template void launch_dual_apply_v<T>(hs_ctx*, cplx<T>*, int);                           \
     template void launch_proj_block<T>(hs_ctx*, int64_t, int64_t, int, cplx<T>*);           \
-    template void launch_grid_pull<T>(hs_ctx*, const cplx<T>*, const T*);                   \
+    template void launch_grid_pull<T>(hs_ctx*, const cplx<T>*, const T*, int);              \
     template void launch_gather_user<T>(hs_ctx*, const cplx<T>*, cplx<T>*, bool);           \
     template void launch_scatter_user<T>(hs_ctx*, const cplx<T>*, cplx<T>*);
 HS_INST(float)

@@ -33,7 +33,7 @@ class Problem:
 
     def __init__(self, nx: int, ny: int, channels, dtype: str = "f32", levels: int = 4, n_db: int = 8,
                  tile: int = 0, device: int = 0, stream=None, gram_mode: str = "f64", autotune: bool = False,
-                 tune_cache: str | None = None, tuning: dict | None = None):
+                 tune_cache: str | None = None, tuning: dict | None = None, per_channel: bool = False):
         """autotune: pick the batching decomposition with hs_autotune (timed on this GPU,
         cached in tune_cache, default the package's tuning_cache.jsonl); tuning: an
         explicit decomposition (hs_set_tuning fields) instead."""
@@ -50,7 +50,8 @@ class Problem:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         desc = L.ProblemDesc(nx=nx, ny=ny, L=self.L, oversamp=2, J=8, levels=levels, n_db=n_db,
                              dtype=L.HS_F32 if dtype == "f32" else L.HS_F64, tile=tile, device=device,
-                             stream=C.c_void_p(self.stream.cuda_stream), gram_mode=L.GRAM_MODES[gram_mode])
+                             stream=C.c_void_p(self.stream.cuda_stream), gram_mode=L.GRAM_MODES[gram_mode],
+                             per_channel=1 if per_channel else 0)
         self.gram_mode = gram_mode
         ctx = C.c_void_p()
         L.check(self.lib.hs_create(C.byref(desc), C.byref(ctx)), None, "hs_create")

@@ -50,13 +50,15 @@ def oracle_data(name: str, precond: str = "density", **over):
 _gpu_cache = {}
 
 
-def gpu_case(name: str, dtype: str, precond: str = "density", tile: int = 0, gram_mode: str = "f64", **over):
-    key = (name, dtype, precond, tile, gram_mode, tuple(sorted(over.items())))
+def gpu_case(name: str, dtype: str, precond: str = "density", tile: int = 0, gram_mode: str = "f64",
+             per_channel: bool = False, **over):
+    key = (name, dtype, precond, tile, gram_mode, per_channel, tuple(sorted(over.items())))
     if key not in _gpu_cache:
         from paper_1806_04596_amd.workload import build_problem
         cfg, inp, _ = oracle_case(name, precond, **over)
         prob, X0, host = build_problem(cfg, inp, W.make_measurements, dtype=dtype, precond=precond, tile=tile,
-                                       data=oracle_data(name, precond, **over), gram_mode=gram_mode)
+                                       data=oracle_data(name, precond, **over), gram_mode=gram_mode,
+                                       per_channel=per_channel)
         _gpu_cache[key] = (prob, X0, host)
     return _gpu_cache[key]
 

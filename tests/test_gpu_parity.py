@@ -510,3 +510,37 @@ def test_autotuned_and_explicit_decompositions(tmp_path):
     check(p3)
     for p in (p1, p2, p3):
         p.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_plain_per_channel_execution(dtype):
+    """The plain execution (the channel-separable kernels launched channel by channel,
+    the iteration eager, no graph): Phi, Phi^dagger, the data dual, the power iteration
+    and one PD iteration against the oracle, as for the batched path."""
+    cfg, inp, op = oracle_case("cube64_L5")
+    prob, _, _ = gpu_case("cube64_L5", dtype, per_channel=True)
+    rng = np.random.default_rng(90)
+    X = inp["X0"] + 0.1 * rng.standard_normal(inp["X0"].shape)
+    Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
+    ref = op.phi(X)
+    assert max(rel(Y[l], ref[l]) for l in range(cfg.L)) <= TOL[dtype]
+    y = rng.standard_normal(prob.M) + 1j * rng.standard_normal(prob.M)
+    check_rel_pc(host(prob.phi_adj(to_dev(prob, y, complex_=True))), op.phi_adj(split(y, prob.counts)), TOL[dtype],
+                 "Phi^dagger")
+    x0 = W.synth.power_start(cfg).astype(np.float32).astype(np.float64)
+    _, per, _ = prob.op_norm(to_dev(prob, x0), max_it=20, tol=0.0)
+    _, ref_per, _ = pd.op_norm_phi(op, x0, max_it=20, tol=0.0)
+    check_rel(per, ref_per, TOL["f64"], "power iteration")
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    w = np.linspace(0.2, 1.0, cfg.L)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=w)
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    refit = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    g, beta, rho = _run_gpu_iteration(prob, st, prm, w, n=1)
+    for k in ("X", "Xt", "P", "A"):
+        check_rel(g[k], getattr(refit, k), TOL[dtype], k)
+    vg = split(g["v"], prob.counts)
+    for l in range(cfg.L):
+        check_rel(vg[l], refit.v[l], TOL[dtype], f"v[{l}]")
+    check_rel(rho, np.concatenate(refit.extra["rho"]), TOL[dtype], "rho")
