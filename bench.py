@@ -112,7 +112,10 @@ def _counter_means(path: str, counter: str):
         for r in csv.DictReader(f):
             if r["Counter_Name"] != counter:
                 continue
-            name = r["Kernel_Name"].replace("void ", "").split("(")[0].split("<")[0].split("::")[-1]
+            full = r["Kernel_Name"].replace("void ", "").split("(")[0]
+            name = full.split("<")[0].split("::")[-1]
+            if "<" in full:   # keep the element type apart: the FP64 comparator runs the same kernels
+                name += "<" + full.split("<", 1)[1].split(",")[0].split(">")[0].strip() + ">"
             sums[name] = sums.get(name, 0.0) + float(r["Counter_Value"])
             counts[name] = counts.get(name, 0) + 1
     return {k: sums[k] / counts[k] for k in sums}, counts
@@ -132,11 +135,12 @@ def write_traffic(fetch_csv: str, write_csv: str, workload: str):
     out = {"_reference": {"kernel": COPY_KERNEL, "bytes": CALIB_BYTES, "fetch_scale": f_scale, "write_scale": w_scale,
                           "workload": workload,
                           "note": "counter KiB per dispatch x 1024 x scale = HBM bytes per dispatch"}}
-    for phase, kern in PHASE_KERNEL.items():
+    for phase, kern0 in PHASE_KERNEL.items():
+        kern = kern0 + "<float>"      # the FP32 problem the bench times
         if kern in fm and kern in wm:
             fb, wb = fm[kern] * 1024 * f_scale, wm[kern] * 1024 * w_scale
             out[phase] = {"kernel": kern, "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
-                          "bytes_per_launch": round(fb + wb), "dispatches_per_phase": fc[kern] / max(1, fc.get("k_primal", 1)),
+                          "bytes_per_launch": round(fb + wb), "dispatches": fc[kern],
                           "src_hash": source_hash(PHASE_SRC[phase])}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:

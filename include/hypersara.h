@@ -239,6 +239,9 @@ hs_status hs_get_info(const hs_ctx* ctx, hs_info* info);
  *                   more entries is split and its partial blocks summed);
  *   degrid_batches: batches of 256 visibilities per degridding work unit;
  *   fft_col_tile:   columns per work-group of the FFT column passes (2..16);
+ *   grid_xcd_group, degrid_xcd_group: consecutive work units (which share input:
+ *                   neighbouring blocks and tiles) given to one XCD before the
+ *                   next, in 1..4096 (1: one unit per XCD in turn);
  *   ms:             measured time of this choice (0: not measured).
  * A 0 field means the library's default. */
 typedef struct {
@@ -246,14 +249,18 @@ typedef struct {
     int32_t grid_split;
     int32_t degrid_batches;
     int32_t fft_col_tile;
+    int32_t grid_xcd_group;
+    int32_t degrid_xcd_group;
     double ms;
 } hs_tuning;
 
 /* The decomposition in use (after hs_plan). */
 hs_status hs_get_tuning(const hs_ctx* ctx, hs_tuning* out);
 
-/* Sets the decomposition (validated); re-plans when the context is planned, after
- * which a workspace must be bound again (hs_plan reports its size). */
+/* Sets the decomposition (validated).  When the context is planned and the tile,
+ * grid_split or degrid_batches change it re-plans, after which a workspace must be
+ * bound again (hs_plan reports its size); the other fields are launch parameters
+ * and take effect at the next call, the bound state kept. */
 hs_status hs_set_tuning(hs_ctx* ctx, const hs_tuning* t);
 
 /* Bytes of the temporary workspace hs_autotune needs (the largest plan among the
@@ -264,8 +271,8 @@ hs_status hs_autotune_bytes(hs_ctx* ctx, size_t* bytes);
  * the data-fidelity branch of one iteration (forward FFT, degridding with the dual
  * step, projection, gridding, adjoint FFT) on the GPU for candidate
  * decompositions (coordinate descent over
- * the tile edge, the gridding split, the degridding unit size and the FFT column
- * tile), keeps the fastest and re-plans with it.  dev/bytes: a caller-allocated
+ * the tile edge, the gridding split, the degridding unit size, the FFT column
+ * tile and the two XCD groups), keeps the fastest and re-plans with it.  dev/bytes: a caller-allocated
  * temporary workspace of at least hs_autotune_bytes bytes, free to reuse after the
  * call.  cache_path (may be NULL): a JSON-lines file of earlier choices keyed by the
  * problem shape (nx, ny, L, visibilities, dtype); a hit skips the timing, a miss

@@ -37,7 +37,8 @@ class Info(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("tile", C.c_int32), ("grid_split", C.c_int32), ("degrid_batches", C.c_int32),
-                ("fft_col_tile", C.c_int32), ("ms", C.c_double)]
+                ("fft_col_tile", C.c_int32), ("grid_xcd_group", C.c_int32), ("degrid_xcd_group", C.c_int32),
+                ("ms", C.c_double)]
 
 
 class PDParams(C.Structure):

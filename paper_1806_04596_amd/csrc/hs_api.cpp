@@ -1195,6 +1195,8 @@ static hs_tuning tuning_of(const hs_ctx* c) {
     t.grid_split = c->grid_split;
     t.degrid_batches = c->deg_batches;
     t.fft_col_tile = fft_col_tile(c);
+    t.grid_xcd_group = c->grid_group;
+    t.degrid_xcd_group = c->deg_group;
     t.ms = c->tune_ms;
     return t;
 }
@@ -1212,10 +1214,14 @@ static hs_status apply_tuning(hs_ctx* c, const hs_tuning& t) {
         return fail(c, HS_ERR_INVALID_ARG, "tuning: degrid_batches in 1..64");
     if (t.fft_col_tile && !fft_col_tile_ok(c, t.fft_col_tile))
         return fail(c, HS_ERR_INVALID_ARG, "tuning: fft_col_tile must be a power of two that fits the column passes");
+    if (t.grid_xcd_group < 0 || t.grid_xcd_group > 4096 || t.degrid_xcd_group < 0 || t.degrid_xcd_group > 4096)
+        return fail(c, HS_ERR_INVALID_ARG, "tuning: XCD groups in 1..4096");
     c->tune_tile = t.tile;
     c->grid_split = t.grid_split ? t.grid_split : GRID_SPLIT;
     c->deg_batches = t.degrid_batches ? t.degrid_batches : DEG_BATCHES;
     c->fft_ct = t.fft_col_tile;
+    c->grid_group = t.grid_xcd_group ? t.grid_xcd_group : GRID_XCD_GROUP;
+    c->deg_group = t.degrid_xcd_group ? t.degrid_xcd_group : DEG_XCD_GROUP;
     c->tune_ms = t.ms;
     return HS_OK;
 }
@@ -1261,6 +1267,9 @@ static bool cache_lookup(const char* path, const std::string& key, hs_tuning& t)
             u.grid_split = (int)b;
             u.degrid_batches = (int)d;
             u.fft_col_tile = (int)e;
+            double gg = 0, dg = 0;   // absent in older entries: the defaults
+            if (num("grid_xcd_group", gg)) u.grid_xcd_group = (int)gg;
+            if (num("degrid_xcd_group", dg)) u.degrid_xcd_group = (int)dg;
             u.ms = ms;
             t = u;
             found = true;   // the last entry of the key wins
@@ -1272,8 +1281,11 @@ static bool cache_lookup(const char* path, const std::string& key, hs_tuning& t)
 static void cache_append(const char* path, const std::string& key, const hs_tuning& t) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"tile\": %d, \"grid_split\": %d, \"degrid_batches\": %d, \"fft_col_tile\": %d, \"ms\": %.5f}\n",
-                 key.c_str(), t.tile, t.grid_split, t.degrid_batches, t.fft_col_tile, t.ms);
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"tile\": %d, \"grid_split\": %d, \"degrid_batches\": %d, \"fft_col_tile\": %d, "
+                 "\"grid_xcd_group\": %d, \"degrid_xcd_group\": %d, \"ms\": %.5f}\n",
+                 key.c_str(), t.tile, t.grid_split, t.degrid_batches, t.fft_col_tile, t.grid_xcd_group,
+                 t.degrid_xcd_group, t.ms);
     std::fclose(f);
 }
 
@@ -1319,9 +1331,12 @@ hs_status hs_get_tuning(const hs_ctx* c, hs_tuning* out) {
 hs_status hs_set_tuning(hs_ctx* c, const hs_tuning* t) {
     HS_TRY_BEGIN
     if (!c || !t) return HS_ERR_INVALID_ARG;
+    const int T0 = c->tune_tile, g0 = c->grid_split, b0 = c->deg_batches;
     hs_status s = apply_tuning(c, *t);
     if (s) return s;
-    if (c->planned) return replan(c);
+    c->graph_valid = false;   // launch parameters are captured in the graph
+    // the FFT column tile and the XCD groups are launch parameters: no new plan
+    if (c->planned && (c->tune_tile != T0 || c->grid_split != g0 || c->deg_batches != b0)) return replan(c);
     return HS_OK;
     HS_TRY_END(c)
 }
@@ -1337,7 +1352,7 @@ hs_status hs_autotune_bytes(hs_ctx* c, size_t* bytes) {
     // the largest plan: each tile edge with the smallest units
     for (int T : {8, 16, 32}) {
         if (!tile_ok(c, T)) continue;
-        hs_tuning t{T, 512, 2, 0, 0.0};
+        hs_tuning t{T, 512, 2, 0, 0, 0, 0.0};
         s = apply_tuning(c, t);
         if (!s) s = build_plan(c);
         if (s) break;
@@ -1388,7 +1403,7 @@ hs_status hs_autotune(hs_ctx* c, void* dev, size_t bytes, const char* cache_path
         c->bound = false;
         return r;
     };
-    best = hs_tuning{0, GRID_SPLIT, DEG_BATCHES, 0, 0.0};
+    best = hs_tuning{0, GRID_SPLIT, DEG_BATCHES, 0, GRID_XCD_GROUP, DEG_XCD_GROUP, 0.0};
     double best_ms = 1e30;
     // coordinate descent: tile edge, gridding split, degridding unit, FFT column tile
     for (int T : {32, 16, 8}) {
@@ -1430,6 +1445,26 @@ hs_status hs_autotune(hs_ctx* c, void* dev, size_t bytes, const char* cache_path
             c->bound = false;
             if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = base; best.fft_col_tile = ct; }
         }
+    }
+    {
+        // XCD groups of the gridding and degridding units: launch parameters too
+        c->fft_ct = best.fft_col_tile;
+        for (int which = 0; which < 2; ++which)
+            for (int g : {1, 4, 16, 64}) {
+                hs_tuning t = best;
+                int& field = which ? t.degrid_xcd_group : t.grid_xcd_group;
+                if (field == g) continue;
+                field = g;
+                c->grid_group = t.grid_xcd_group;
+                c->deg_group = t.degrid_xcd_group;
+                double ms;
+                carve(c, (char*)dev);
+                c->bound = true;
+                s = c->dtype == HS_F32 ? time_ops<float>(c, ms) : time_ops<double>(c, ms);
+                c->bound = false;
+                if (s) return s;
+                if (ms < TUNE_MARGIN * best_ms) { best_ms = ms; best = t; }
+            }
     }
     best.ms = best_ms;
     s = apply_tuning(c, best);

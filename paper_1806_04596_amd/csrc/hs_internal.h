@@ -17,6 +17,8 @@ constexpr int MAX_L = 64;           // channels (Gram matrix edge)
 constexpr int DEG_THREADS = 256;    // degridding workgroup = one batch of visibilities
 constexpr int DEG_BATCHES = 4;      // default batches per degridding work unit (tunable)
 constexpr int GRID_SPLIT = 1024;    // default entries per gridding work unit (tunable)
+constexpr int GRID_XCD_GROUP = 64;  // default gridding units per XCD turn (tunable)
+constexpr int DEG_XCD_GROUP = 4;    // default degridding units per XCD turn (tunable)
 constexpr int MAX_DB = 8;
 constexpr int MAX_TAPS = 16;        // 2 * MAX_DB
 
@@ -189,6 +191,7 @@ struct hs_ctx {
     // tunables (hs_set_tuning / hs_autotune): tile edge (0 = rule), entries per gridding
     // unit, batches per degridding unit, columns per FFT column tile (0 = rule)
     int tune_tile = 0, grid_split = hs::GRID_SPLIT, deg_batches = hs::DEG_BATCHES, fft_ct = 0;
+    int grid_group = hs::GRID_XCD_GROUP, deg_group = hs::DEG_XCD_GROUP;   // XCD grouping of the work units
     double tune_ms = 0.0;
     int gtiles_x = 0, ngtiles = 0;                      // gridding blocks (GB x GB) in x, in all
     int Kh = 0, Wh = 0, Wg = 0, Hs = 0;                 // Kx/2, Kx/2 + 1, Kx/2 + 2 GR_MARGIN, Kx/2 + 16

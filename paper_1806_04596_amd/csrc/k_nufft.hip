@@ -239,6 +239,18 @@ __device__ __forceinline__ int xcd_pair_tile(int b, int nb) {
     return (q << 4) + ((r & 7) << 1) + (r >> 3);
 }
 
+// Work item of work-group b (of n) when consecutive items are dealt to the 8
+// XCDs in groups of G: work-groups are dispatched round-robin over the XCDs
+// (b mod 8 names the XCD, each has its own L2), and within each run of 8G
+// work-groups XCD x takes items [xG, xG + G) of the run, so neighbouring items
+// (which share input) meet in one L2.  G = 1 is the identity; the items of the
+// last incomplete run keep their index.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_group_item(int b, int n, int G) {
+    if (G <= 1 || b >= (n / (8 * G)) * 8 * G) return b;
+    const int s = b >> 3, k = s / G;
+    return k * 8 * G + (b & 7) * G + (s - k * G);
+}
+
 // Column pass of F over the half plane: columns kx in [0, Kx/2] in tiles of CT
 // adjacent columns (the last tile is partly idle), rows placed at
 // (j - ny/2) mod Ky.  The grid row has Wg cells, kx = 0 at cell T.
@@ -545,10 +557,12 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ mult,
     const int32_t* __restrict__ perm, cplx<T>* __restrict__ out, int Kh, int Ky, int Wg, int TT, int tiles_x,
-    KBPoly<T> kb) {
+    KBPoly<T> kb, int xg) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
-    const DegridUnit u = units[blockIdx.x];
+    // units are in tile order per channel: grouping keeps the halo a tile shares
+    // with its neighbours in one L2
+    const DegridUnit u = units[xcd_group_item(blockIdx.x, gridDim.x, xg)];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
@@ -582,10 +596,12 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const cplx<T>* __restrict__ grid, const T* __restrict__ theta, const T* __restrict__ uprec,
     const cplx<T>* __restrict__ yv, const int32_t* __restrict__ vbin, cplx<T>* __restrict__ v,
     const int32_t* __restrict__ chunk_run, const int32_t* __restrict__ run_slot, double* __restrict__ run_sum, int Kh, int Ky, int Wg, int TT, int tiles_x,
-    KBPoly<T> kb) {
+    KBPoly<T> kb, int xg) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* tileS = reinterpret_cast<cplx<T>*>(smem_raw);
-    const DegridUnit u = units[blockIdx.x];
+    // units are in tile order per channel: grouping keeps the halo a tile shares
+    // with its neighbours in one L2
+    const DegridUnit u = units[xcd_group_item(blockIdx.x, gridDim.x, xg)];
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
@@ -804,14 +820,16 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
     const GridUnit* __restrict__ units, const int32_t* __restrict__ glist, const int32_t* __restrict__ cell,
     const cplx<T>* __restrict__ frac, const cplx<T>* __restrict__ vals, const T* __restrict__ weight,
-    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int nbx, KBPoly<T> kb) {
+    cplx<T>* __restrict__ grid, cplx<T>* __restrict__ partial, int Ky, int Wg, int nbx, KBPoly<T> kb, int xg) {
     typedef typename GridAcc<T>::type acc_t;
     // entry e: sA[e][1 + j] = wy_e(j), sB[e][1 + j] = wx_e(j) v_e, zeros at 0 and KB_J + 1;
     // sd[e] = (dy, dx), the offsets of its first tap from the block origin
     __shared__ T sA[GR_BATCH * GR_WS];
     __shared__ cplx<T> sB[GR_BATCH * GR_WS];
     __shared__ int sd[2 * GR_BATCH];
-    const GridUnit u = units[blockIdx.x];
+    // gridding units are in block order (row-major per channel), and a visibility
+    // is listed by up to four neighbouring blocks: grouping keeps neighbours on one L2
+    const GridUnit u = units[xcd_group_item(blockIdx.x, gridDim.x, xg)];
     const int lane = threadIdx.x, il = lane & 15, kq = lane >> 4;
     // staging: lane (e, dim) = (lane % 32, lane / 32) evaluates one dimension of entry e
     const int se = lane & (GR_BATCH - 1), dim = lane / GR_BATCH;
@@ -1052,7 +1070,7 @@ void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user, int lc) {
     k_degrid_plain<T, true, false><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
         c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x,
-        kbpoly<T>(c));
+        kbpoly<T>(c), c->deg_group);
 }
 
 // Degrid into grid order with an extra per-visibility factor (used by the power iteration).
@@ -1065,7 +1083,8 @@ void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult, int lc) {
     auto launch = [&](auto kern) {
         kern<<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
             c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
-            (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+            (const T*)c->d.vis_theta, mult, nullptr, out, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c),
+            c->deg_group);
     };
     if (mult) launch(k_degrid_plain<T, false, true>);
     else launch(k_degrid_plain<T, false, false>);
@@ -1080,7 +1099,8 @@ void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v, int lc) {
     k_degrid_dual<T><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
         c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
-        c->d.chunk_run, c->d.run_slot, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c));
+        c->d.chunk_run, c->d.run_slot, c->d.run_sum, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x, kbpoly<T>(c),
+        c->deg_group);
 }
 
 template <typename T>
@@ -1115,7 +1135,7 @@ void launch_grid_pull(hs_ctx* c, const cplx<T>* vals, const T* weight, int lc) {
     if (ng > 0)
         k_grid_pull<T><<<(unsigned)ng, 64, 0, c->stream>>>(
             c->d.gunits + g0, c->d.glist, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, vals, weight,
-            (cplx<T>*)c->d.grid, (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->gtiles_x, kbpoly<T>(c));
+            (cplx<T>*)c->d.grid, (cplx<T>*)c->d.gpartial, c->Ky, c->Wg, c->gtiles_x, kbpoly<T>(c), c->grid_group);
     if (ns > 0)
         k_grid_merge<T><<<(unsigned)ns, 256, 0, c->stream>>>(
             c->d.splits + s0, (const cplx<T>*)c->d.gpartial, (cplx<T>*)c->d.grid, c->Ky, c->Wg, c->gtiles_x);

@@ -122,6 +122,18 @@ class Problem:
     def _p(t):
         return C.c_void_p(t.data_ptr()) if t is not None else None
 
+    def set_launch_tuning(self, **fields):
+        """Changes the launch-time fields of the decomposition (fft_col_tile,
+        grid_xcd_group, degrid_xcd_group); the plan and the bound state are kept."""
+        launch = ("fft_col_tile", "grid_xcd_group", "degrid_xcd_group")
+        bad = [k for k in fields if k not in launch]
+        if bad:
+            raise L.HSError(f"set_launch_tuning: {bad} shape the plan; pass them to the constructor")
+        cur = self.tuning()
+        cur.update({k: int(v) for k, v in fields.items()})
+        t = L.Tuning(**{k: v for k, v in cur.items()})
+        self._chk(self.lib.hs_set_tuning(self.ctx, C.byref(t)), "hs_set_tuning")
+
     def tuning(self):
         t = L.Tuning()
         self._chk(self.lib.hs_get_tuning(self.ctx, C.byref(t)), "hs_get_tuning")

@@ -475,7 +475,7 @@ def test_continuous_preconditioner(dtype):
 
 def test_autotuned_and_explicit_decompositions(tmp_path):
     """The batching decomposition (tile edge, gridding split, degridding unit, FFT
-    column tile) chosen by the autotuner, taken from its cache, or set explicitly:
+    column tile, XCD groups) chosen by the autotuner, taken from its cache, or set explicitly:
     every choice gives the same operator (Phi and Phi^dagger against the oracle)."""
     import paper_1806_04596_amd as H
     from paper_1806_04596_amd.workload import build_problem
@@ -503,11 +503,22 @@ def test_autotuned_and_explicit_decompositions(tmp_path):
     t2 = p2.tuning()
     assert t2.pop("ms") == pytest.approx(t1.pop("ms"), abs=1e-5) and t2 == t1     # a cache hit: no new timing
     assert len(open(cache).read().splitlines()) == 1
+    # XCD groups that leave an incomplete last run of units (the unit counts are not
+    # multiples of 8 G)
     p3, _, _ = build_problem(cfg, inp, W.make_measurements, dtype="f32", data=data,
-                             tuning=dict(tile=8, grid_split=512, degrid_batches=2, fft_col_tile=2))
+                             tuning=dict(tile=8, grid_split=512, degrid_batches=2, fft_col_tile=2,
+                                         grid_xcd_group=3, degrid_xcd_group=5))
     t3 = p3.tuning()
     assert (t3["tile"], t3["grid_split"], t3["degrid_batches"], t3["fft_col_tile"]) == (8, 512, 2, 2)
+    assert (t3["grid_xcd_group"], t3["degrid_xcd_group"]) == (3, 5)
     check(p3)
+    # launch-time fields change without a new plan
+    p3.set_launch_tuning(grid_xcd_group=1, degrid_xcd_group=16, fft_col_tile=4)
+    t4 = p3.tuning()
+    assert (t4["tile"], t4["fft_col_tile"], t4["grid_xcd_group"], t4["degrid_xcd_group"]) == (8, 4, 1, 16)
+    check(p3)
+    with pytest.raises(H.HSError):
+        p3.set_launch_tuning(tile=16)
     for p in (p1, p2, p3):
         p.close()
 
