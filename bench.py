@@ -39,6 +39,10 @@ def parse():
     p.add_argument("--gram-mode", default="f64", choices=["f64", "f32", "bf16_split"])
     p.add_argument("--norm-iters", type=int, default=1000,
                    help="power iterations for the step-size norm (relative tolerance 1e-10)")
+    p.add_argument("--precision", action="store_true",
+                   help="per-operator error of the FP32 context against the FP64 one on the whole cube")
+    p.add_argument("--drift-iters", type=int, default=0,
+                   help="also run both contexts this many PD iterations from zero and report the drift")
     p.add_argument("--phases-only", action="store_true",
                    help="only the eager per-phase timing (for rocprofv3 kernel traces and counters)")
     p.add_argument("--calib-copy", action="store_true",
@@ -218,6 +222,87 @@ def cpu_baseline(cfg, inputs, n_ch: int):
                       f"to the full cube"}
 
 
+def precision_report(prob, p64, cfg, X0, mu, tau, kappa3, drift_iters):
+    """Error of the FP32 context (its Gram mode included) against the FP64 context, per
+    operator on the whole cube: every input drawn in FP64 on the device (seeded), rounded
+    to FP32, and the same FP32 values given to both sides.  Relative errors: the whole
+    output and the largest per-channel one.  Then both contexts iterate from a zero state
+    and the relative error of X is reported along the run (the drift)."""
+    import numpy as np
+    import torch
+    dev = prob.device
+    g = torch.Generator(device=dev).manual_seed(77)
+    L = cfg.L
+
+    def rnd(*shape, cplx=False):
+        if cplx:
+            x = torch.complex(torch.randn(*shape, generator=g, device=dev, dtype=torch.float64),
+                              torch.randn(*shape, generator=g, device=dev, dtype=torch.float64))
+            x32 = x.to(torch.complex64).contiguous()
+            return x32, x32.to(torch.complex128).contiguous()
+        x32 = torch.randn(*shape, generator=g, device=dev, dtype=torch.float64).float().contiguous()
+        return x32, x32.double().contiguous()
+
+    def errs(a32, a64, chan_axis=0, counts=None):
+        a, b = a32.to(a64.dtype), a64
+        tot = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        if counts is not None:
+            off = np.concatenate([[0], np.cumsum(counts)])
+            per = [float(torch.linalg.vector_norm(a[off[l]:off[l + 1]] - b[off[l]:off[l + 1]]) /
+                         torch.linalg.vector_norm(b[off[l]:off[l + 1]])) for l in range(L) if counts[l]]
+        else:
+            per = [float(torch.linalg.vector_norm(a.select(chan_axis, l) - b.select(chan_axis, l)) /
+                         torch.linalg.vector_norm(b.select(chan_axis, l))) for l in range(L)]
+        return {"rel": tot, "max_per_channel": max(per)}
+
+    amp = float(X0.max())
+    rep = {}
+    x32, x64 = rnd(L, cfg.ny, cfg.nx)
+    X32 = (X0.float() * (1 + 0.05 * x32)).contiguous()
+    X64 = X32.double()
+    rep["phi"] = errs(prob.phi(X32), p64.phi(X64), counts=prob.counts)
+    y32, y64 = rnd(prob.M, cplx=True)
+    rep["phi_adj"] = errs(prob.phi_adj(y32), p64.phi_adj(y64))
+    rep["psi_adj"] = errs(prob.psi_adj(x32), p64.psi_adj(x64), chan_axis=1)
+    c32, c64 = rnd(9, L, cfg.ny, cfg.nx)
+    rep["psi"] = errs(prob.psi(c32), p64.psi(c64))
+    a32, a64 = rnd(9, L, cfg.ny, cfg.nx)
+    a32.mul_(0.05 * amp), a64.mul_(0.05 * amp)
+    rep["dual_l21"] = errs(prob.dual_l21(a32, X32, mu), p64.dual_l21(a64, X64, mu), chan_axis=1)
+    s = torch.linalg.svdvals(X64.reshape(L, -1).T).cpu().numpy()
+    w = np.sort(np.random.default_rng(78).uniform(0.0, 0.5 * s[0], L))
+    p32, p64_ = rnd(L, cfg.ny, cfg.nx)
+    p32.mul_(0.05 * amp), p64_.mul_(0.05 * amp)
+    rep["dual_nuclear"] = errs(prob.dual_nuclear(p32, X32, w), p64.dual_nuclear(p64_, X64, w))
+    _, sig32 = prob.prox_nuclear(X32.clone(), w)
+    _, sig64 = p64.prox_nuclear(X64.clone(), w)
+    rep["singular_values"] = {"rel": float(np.linalg.norm(sig32 - sig64) / np.linalg.norm(sig64)),
+                              "max_rel": float(np.max(np.abs(sig32 - sig64) / np.abs(sig64)))}
+    v32, v64 = rnd(prob.M, cplx=True)
+    v32.mul_(0.05), v64.mul_(0.05)
+    rep["dual_data"] = errs(prob.dual_data(v32, X32), p64.dual_data(v64, X64), counts=prob.counts)
+    torch.cuda.synchronize()
+    if drift_iters > 0:
+        for p in (prob, p64):
+            z = torch.zeros(L, cfg.ny, cfg.nx, dtype=p.tdtype, device=dev)
+            p.set_state(X=z, Xt=z.clone(), P=z.clone(), A=torch.zeros(9, L, cfg.ny, cfg.nx, dtype=p.tdtype, device=dev),
+                        v=torch.zeros(p.M, dtype=p.cdtype, device=dev))
+            p.pd_init(mu=mu, tau=tau, kappa3=kappa3)
+        trace, done = [], 0
+        for k in sorted({1, 10, 100, drift_iters}):
+            if k > drift_iters:
+                continue
+            prob.iterate(k - done)
+            p64.iterate(k - done)
+            done = k
+            e = errs(prob.get_state()["X"], p64.get_state()["X"])
+            trace.append({"iteration": k, "X_rel": e["rel"], "X_max_per_channel": e["max_per_channel"],
+                          "beta_f32": prob.stats()[0], "beta_f64": p64.stats()[0]})
+        rep["drift_from_zero"] = trace
+    torch.cuda.synchronize()
+    return rep
+
+
 def calib_copy():
     """Three device-to-device copies of CALIB_BYTES (the counter reference)."""
     import torch
@@ -353,6 +438,9 @@ def main():
         fp64 = {"kind": "plain FP64: per-channel launches, default decomposition, eager (no graph)",
                 "iters_per_s": round(v64, 3), "fp32_speedup": round(value / v64, 3),
                 "one_iter_rel_err_fp32_vs_fp64": rel}
+        if args.precision or args.drift_iters:
+            X0d = torch.as_tensor(X0, device=prob.device) if not torch.is_tensor(X0) else X0.to(prob.device)
+            fp64["precision"] = precision_report(prob, p64, cfg, X0d, mu, tau, kappa3, args.drift_iters)
         del p64
     if args.calib_copy:
         calib_copy()

@@ -8,7 +8,10 @@ The data y_raw, theta and eps of every channel are formed once by the oracle
 Channel-separable outputs (Phi, Phi^dagger, Psi^dagger, Psi, the data-fidelity
 dual) are compared element by element with the oracle on sampled channels
 (the smallest, a middle and the largest); the channel-coupled nuclear dual and
-one whole PD iteration are compared on the whole cube.  The oracle's
+one whole PD iteration are compared on the whole cube.  The 1024 cube runs with the
+nuclear prox's Gram matrix as a BF16 split (FP32 accumulation, FP64 eigen-solve);
+every test prints its relative errors, the per-operator error table of that
+precision pattern.  The oracle's
 per-channel work runs in a process pool (channels are independent)."""
 import multiprocessing
 import os
@@ -34,6 +37,15 @@ def pool():
         yield ex
 
 
+# the 1024 x 1024 x 32 cube runs in the mixed-precision pattern: FP32 operators, the
+# Gram matrix of the nuclear prox as a BF16 split with FP32 accumulation, FP64 eigen-solve
+GRAM = {"cube512_L60": "f64", "cube1024_L32": "bf16_split"}
+
+
+def _report(CFG, what, err):
+    print(f"{CFG.name} [{GRAM[CFG.name]} Gram] {what}: rel err {err:.2e}", flush=True)
+
+
 @pytest.fixture(scope="module", params=["cube512_L60", "cube1024_L32"])
 def big(request, pool):
     from paper_1806_04596_amd.workload import build_problem
@@ -43,7 +55,8 @@ def big(request, pool):
     S = sorted({int(np.argmin(counts)), CFG.L // 2, int(np.argmax(counts))})
     op, y_raw = pd.build_problem(CFG, inp, pool=pool)
     prob, X0, hd = build_problem(CFG, inp, W.make_measurements, dtype="f32",
-                                 data={"y_raw": y_raw, "theta": op.theta, "eps": op.eps})
+                                 data={"y_raw": y_raw, "theta": op.theta, "eps": op.eps},
+                                 gram_mode=GRAM[CFG.name])
     print(f"{CFG.name} full size: sampled channels {S}, M = {prob.M}", flush=True)
     yield {"cfg": CFG, "inp": inp, "prob": prob, "S": S, "op": op, "y_raw": y_raw}
     prob.close()
@@ -56,7 +69,7 @@ def test_phi_full_size(big):
     Y = split(host(prob.phi(to_dev(prob, X))), prob.counts)
     for l in S:
         ref = nufft.phi(X[l], op.uv[l], op.theta[l])
-        check_rel(Y[l], ref, TOL["f32"], f"Phi channel {l}")
+        _report(big["cfg"], f"Phi channel {l}", check_rel(Y[l], ref, TOL["f32"], f"Phi channel {l}"))
 
 
 def test_phi_adj_full_size(big):
@@ -68,7 +81,7 @@ def test_phi_adj_full_size(big):
     ys = split(y, prob.counts)
     for l in S:
         ref = nufft.phi_adj(ys[l], op.uv[l], op.theta[l], CFG.ny, CFG.nx)
-        check_rel(X[l], ref, TOL["f32"], f"Phi^dag channel {l}")
+        _report(CFG, f"Phi^dag channel {l}", check_rel(X[l], ref, TOL["f32"], f"Phi^dag channel {l}"))
 
 
 def test_psi_full_size(big):
@@ -79,13 +92,13 @@ def test_psi_full_size(big):
     C = host(prob.psi_adj(to_dev(prob, X)))
     ref = wavelets.psi_adj(X[S])
     for j, l in enumerate(S):
-        for d in range(9):
-            check_rel(C[d, l], ref[d, j], TOL["f32"], f"Psi^dag basis {d} channel {l}")
+        e = max(check_rel(C[d, l], ref[d, j], TOL["f32"], f"Psi^dag basis {d} channel {l}") for d in range(9))
+        _report(CFG, f"Psi^dag channel {l} (max over bases)", e)
     Cr = rng.standard_normal((9, CFG.L, CFG.ny, CFG.nx)).astype(np.float32)
     Xs = host(prob.psi(to_dev(prob, Cr)))
     ref = wavelets.psi(Cr[:, S].astype(np.float64))
     for j, l in enumerate(S):
-        check_rel(Xs[l], ref[j], TOL["f32"], f"Psi channel {l}")
+        _report(CFG, f"Psi channel {l}", check_rel(Xs[l], ref[j], TOL["f32"], f"Psi channel {l}"))
 
 
 def test_dual_nuclear_full_size(big):
@@ -98,7 +111,7 @@ def test_dual_nuclear_full_size(big):
     w = np.sort(rng.uniform(0.0, 0.5 * s[0], CFG.L))
     Pd = host(prob.dual_nuclear(to_dev(prob, P), to_dev(prob, X), w))
     ref = prox.dual_nuclear(P, X, w, "gram")
-    check_rel(Pd, ref, TOL["f32"], "P")
+    _report(CFG, "nuclear dual P (whole cube)", check_rel(Pd, ref, TOL["f32"], "P"))
 
 
 def test_dual_data_full_size(big):
@@ -115,7 +128,7 @@ def test_dual_data_full_size(big):
         for b in range(len(bp) - 1):
             sl = slice(bp[b], bp[b + 1])
             vr[sl], _ = prox.dual_data_block(vbar[sl], op.y[l][sl], op.u[l][sl], op.eps[l][b])
-        check_rel(vg[l], vr, TOL["f32"], f"v channel {l}")
+        _report(big["cfg"], f"data dual v channel {l}", check_rel(vg[l], vr, TOL["f32"], f"v channel {l}"))
 
 
 def _kappa3(op):
@@ -144,19 +157,19 @@ def test_pd_iteration_full_size_vs_oracle(big, pool):
     for k in ("X", "Xt", "P"):
         a = host(g[k])
         err = max(rel(a[l], getattr(ref, k)[l]) for l in range(CFG.L))
-        print(f"{CFG.name} one iteration {k}: max per-channel rel err {err:.2e}", flush=True)
+        _report(CFG, f"one iteration {k} (max per channel)", err)
         assert err <= tol, (k, err)
     A = host(g["A"])
     err = max(rel(A[d, l], ref.A[d, l]) for d in range(9) for l in range(CFG.L))
-    print(f"{CFG.name} one iteration A: max per-(basis, channel) rel err {err:.2e}", flush=True)
+    _report(CFG, "one iteration A (max per basis and channel)", err)
     assert err <= tol
     vg = split(host(g["v"]), prob.counts)
     err = max(rel(vg[l], ref.v[l]) for l in range(CFG.L))
-    print(f"{CFG.name} one iteration v: max per-channel rel err {err:.2e}", flush=True)
+    _report(CFG, "one iteration v (max per channel)", err)
     assert err <= tol
     _, rho, _ = prob.stats()
     err = rel(rho, np.concatenate(ref.extra["rho"]))
-    print(f"{CFG.name} one iteration rho: rel err {err:.2e}", flush=True)
+    _report(CFG, "one iteration rho", err)
     assert err <= tol
 
 
