@@ -315,6 +315,28 @@ hs_status hs_psi_adj(hs_ctx* ctx, const void* X, void* C);
 /* Psi: X = sum_d Psi_d C[d]. */
 hs_status hs_psi(hs_ctx* ctx, const void* C, void* X);
 
+/* Psi^dagger and Psi of nl contiguous channels (1 <= nl <= L; the dictionary is the
+ * same for every channel): X real [nl][ny][nx], C real [D][nl][ny][nx].  For callers
+ * that process the cube a few channels at a time (checkpointed gradients). */
+hs_status hs_psi_adj_n(hs_ctx* ctx, const void* X, void* C, int32_t nl);
+hs_status hs_psi_n(hs_ctx* ctx, const void* C, void* X, int32_t nl);
+
+/* The l2,1 norm of Sec. 2.3 (the joint-average-sparsity prior: the l2 norm of each row
+ * (d, pixel) of Psi^dagger X across the channels, summed, optionally weighted by wbar as
+ * in eq:weights-l21) built a chunk of channels at a time, and its gradient.
+ *   hs_l21_rowsq:      S[d][p] (device FP64 [D][ny][nx]) = (accumulate ? S : 0) + the sum
+ *                      over the chunk's nl channels of C[d][l][p]^2, C = [D][nl][ny][nx].
+ *   hs_l21_rowscale:   C[d][l][p] <- scale * wbar[d][p] * C[d][l][p] / sqrt(S[d][p]) for
+ *                      the chunk (0 on a zero row: the subgradient of least norm); with S
+ *                      summed over all channels this is the gradient of the norm with
+ *                      respect to the chunk's coefficients.  wbar: [D][ny][nx] or NULL.
+ *   hs_l21_from_rowsq: *value (host) = sum_{d,p} wbar[d][p] sqrt(S[d][p]), FP64, fixed
+ *                      summation order; synchronising.
+ * nl in 1..L; asynchronous on the context stream except hs_l21_from_rowsq. */
+hs_status hs_l21_rowsq(hs_ctx* ctx, const void* C, int32_t nl, double* S, int32_t accumulate);
+hs_status hs_l21_rowscale(hs_ctx* ctx, void* C, int32_t nl, const double* S, const void* wbar, double scale);
+hs_status hs_l21_from_rowsq(hs_ctx* ctx, const double* S, const void* wbar, double* value);
+
 /* --------------------------------------------------- proxes / dual updates */
 /* eq:prox-L21 in place: rows of length L at fixed (d, y, x) of A [D][L][ny][nx]
  * are shrunk by max(||a|| - t*wbar, 0)/||a||.  wbar: real [D][ny][nx] or NULL (ones). */

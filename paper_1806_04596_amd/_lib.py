@@ -92,6 +92,11 @@ SIGNATURES = {
     "hs_phi_adj": (C.c_int32, [ctxp, P, P]),
     "hs_psi_adj": (C.c_int32, [ctxp, P, P]),
     "hs_psi": (C.c_int32, [ctxp, P, P]),
+    "hs_psi_adj_n": (C.c_int32, [ctxp, P, P, C.c_int32]),
+    "hs_psi_n": (C.c_int32, [ctxp, P, P, C.c_int32]),
+    "hs_l21_rowsq": (C.c_int32, [ctxp, P, C.c_int32, P, C.c_int32]),
+    "hs_l21_rowscale": (C.c_int32, [ctxp, P, C.c_int32, P, P, C.c_double]),
+    "hs_l21_from_rowsq": (C.c_int32, [ctxp, P, P, C.POINTER(C.c_double)]),
     "hs_prox_l21": (C.c_int32, [ctxp, P, P, C.c_double]),
     "hs_dual_l21": (C.c_int32, [ctxp, P, P, P, C.c_double, P]),
     "hs_prox_nuclear": (C.c_int32, [ctxp, P, dptr, dptr]),

@@ -12,6 +12,11 @@ same pairs: Re Phi^dagger for the data term, Psi for the sparsity term):
 
 The backward passes call the other Function, so gradients of gradients
 (Hessian-vector products of a data-fidelity loss, for instance) work too.
+
+``l21_psi_adj`` is the l2,1 term of a loss, ||Psi^dagger X||_{2,1}, differentiated
+with checkpointed per-channel recomputation: only the per-row sums of squares are
+kept between forward and backward, and the coefficients are recomputed a few
+channels at a time.
 Every evaluation runs in the library's HIP kernels through a ``Problem``;
 tensors are in the problem's precision and device.
 """
@@ -77,6 +82,43 @@ class PsiFunction(torch.autograd.Function):
         return None, PsiAdjFunction.apply(ctx.prob, gX)
 
 
+class L21PsiAdjFunction(torch.autograd.Function):
+    """s = sum_r wbar_r ||(Psi^dagger X)_r||_2, the l2,1 norm of Sec. 2.3 (a row r is one
+    coefficient (d, pixel) across the L channels), with checkpointed per-channel
+    recomputation: the forward builds the per-row sums of squares S [D][ny][nx] (FP64)
+    `chunk` channels at a time and keeps only S; the backward recomputes each chunk's
+    coefficients, scales them by g wbar_r / ||row r|| (zero rows give zero, the
+    subgradient of least norm) and synthesises them into that chunk of the gradient.
+    Extra device memory: one chunk's coefficients [D][chunk][ny][nx] and S, instead of
+    the whole [D][L][ny][nx]."""
+
+    @staticmethod
+    def forward(ctx, prob, X, wbar, chunk):
+        X = _as(prob, X)
+        S = torch.empty((prob.D, prob.ny, prob.nx), dtype=torch.float64, device=prob.device)
+        for l0 in range(0, prob.L, chunk):
+            n = min(chunk, prob.L - l0)
+            prob.l21_rowsq(prob.psi_adj(X[l0:l0 + n]), S, accumulate=l0 > 0)
+        wb = None if wbar is None else _as(prob, wbar)
+        val = prob.l21_from_rowsq(S, wb)
+        ctx.prob, ctx.chunk, ctx.wbar = prob, chunk, wb
+        ctx.save_for_backward(X, S)
+        return torch.tensor(val, dtype=torch.float64, device=prob.device)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g):
+        X, S = ctx.saved_tensors
+        prob, chunk = ctx.prob, ctx.chunk
+        scale = float(g)
+        grad = torch.empty_like(X)
+        for l0 in range(0, prob.L, chunk):
+            n = min(chunk, prob.L - l0)
+            Cc = prob.l21_rowscale(prob.psi_adj(X[l0:l0 + n]), S, ctx.wbar, scale)
+            prob.psi(Cc, grad[l0:l0 + n])
+        return None, grad, None, None
+
+
 def phi(prob, X):
     return PhiFunction.apply(prob, X)
 
@@ -91,3 +133,11 @@ def psi_adj(prob, X):
 
 def psi(prob, Cc):
     return PsiFunction.apply(prob, Cc)
+
+
+def l21_psi_adj(prob, X, wbar=None, chunk=4):
+    """sum_r wbar_r ||(Psi^dagger X)_r||_2 with checkpointed per-channel recomputation
+    (`chunk` channels of coefficients alive at a time); differentiable in X."""
+    if chunk < 1:
+        raise ValueError("chunk must be >= 1")
+    return L21PsiAdjFunction.apply(prob, X, wbar, int(chunk))

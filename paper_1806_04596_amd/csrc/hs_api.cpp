@@ -755,23 +755,65 @@ hs_status hs_phi_adj(hs_ctx* c, const void* Y, void* X) {
     return launched(c, "hs_phi_adj");
 }
 
-hs_status hs_psi_adj(hs_ctx* c, const void* X, void* C) {
+hs_status hs_psi_adj_n(hs_ctx* c, const void* X, void* C, int32_t nl) {
     hs_status s = ready(c);
     if (s) return s;
     if (!X || !C) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
-    const size_t LN = (size_t)c->L * c->N;
+    if (nl < 1 || nl > c->L) return fail(c, HS_ERR_INVALID_ARG, "channel count must be in 1..L");
+    const size_t LN = (size_t)nl * c->N;
     hipMemcpyAsync(C, X, LN * c->rsz, hipMemcpyDeviceToDevice, c->stream);
-    HS_DISPATCH(c, launch_psi_adj<T>(c, (const T*)X, (T*)C + LN));
+    HS_DISPATCH(c, launch_psi_adj<T>(c, (const T*)X, (T*)C + LN, nl));
     return launched(c, "hs_psi_adj");
 }
 
-hs_status hs_psi(hs_ctx* c, const void* C, void* X) {
+hs_status hs_psi_adj(hs_ctx* c, const void* X, void* C) { return hs_psi_adj_n(c, X, C, c ? c->L : 0); }
+
+hs_status hs_psi_n(hs_ctx* c, const void* C, void* X, int32_t nl) {
     hs_status s = ready(c);
     if (s) return s;
     if (!X || !C) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
-    const size_t LN = (size_t)c->L * c->N;
-    HS_DISPATCH(c, launch_psi_sum<T>(c, (const T*)C + LN, (const T*)C, (T*)X));
+    if (nl < 1 || nl > c->L) return fail(c, HS_ERR_INVALID_ARG, "channel count must be in 1..L");
+    const size_t LN = (size_t)nl * c->N;
+    HS_DISPATCH(c, launch_psi_sum<T>(c, (const T*)C + LN, (const T*)C, (T*)X, nl));
     return launched(c, "hs_psi");
+}
+
+hs_status hs_psi(hs_ctx* c, const void* C, void* X) { return hs_psi_n(c, C, X, c ? c->L : 0); }
+
+hs_status hs_l21_rowsq(hs_ctx* c, const void* C, int32_t nl, double* S, int32_t accumulate) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!C || !S) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    if (nl < 1 || nl > c->L) return fail(c, HS_ERR_INVALID_ARG, "channel count must be in 1..L");
+    const size_t LN = (size_t)nl * c->N;
+    HS_DISPATCH(c, launch_l21_rowsq<T>(c, (const T*)C, (const T*)C + LN, nl, S, accumulate != 0));
+    return launched(c, "hs_l21_rowsq");
+}
+
+hs_status hs_l21_rowscale(hs_ctx* c, void* C, int32_t nl, const double* S, const void* wbar, double scale) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!C || !S || !std::isfinite(scale)) return fail(c, HS_ERR_INVALID_ARG, "bad argument");
+    if (nl < 1 || nl > c->L) return fail(c, HS_ERR_INVALID_ARG, "channel count must be in 1..L");
+    const size_t LN = (size_t)nl * c->N;
+    HS_DISPATCH(c, launch_l21_rowscale<T>(c, (T*)C, (T*)C + LN, nl, S, (const T*)wbar, scale));
+    return launched(c, "hs_l21_rowscale");
+}
+
+hs_status hs_l21_from_rowsq(hs_ctx* c, const double* S, const void* wbar, double* value) {
+    hs_status s = ready(c);
+    if (s) return s;
+    if (!S || !value) return fail(c, HS_ERR_INVALID_ARG, "null pointer");
+    int np = 0;
+    HS_DISPATCH(c, np = launch_l21_from_rowsq<T>(c, S, (const T*)wbar));
+    std::vector<double> part(np);
+    hipMemcpyAsync(part.data(), c->d.red_part, (size_t)np * 8, hipMemcpyDeviceToHost, c->stream);
+    s = hip_check(c, hipStreamSynchronize(c->stream), "hs_l21_from_rowsq");
+    if (s) return s;
+    double v = 0.0;
+    for (int k = 0; k < np; ++k) v += part[k];
+    *value = v;
+    return HS_OK;
 }
 
 hs_status hs_prox_l21(hs_ctx* c, void* A, const void* wbar, double t) {

@@ -270,8 +270,9 @@ template <typename T> void launch_scatter_user(hs_ctx* c, const cplx<T>* in_grid
 template <typename T> void launch_proj_block(hs_ctx* c, int64_t pos0_user, int64_t Mb, int blk, cplx<T>* z);
 
 // wavelets (k_wavelet.hip)
-template <typename T> void launch_psi_adj(hs_ctx* c, const T* X, T* Cout /*[n_db][L][N]; null -> coef*/);
-template <typename T> void launch_psi_sum(hs_ctx* c, const T* Cdb /*[n_db][L][N]*/, const T* C0, T* Xout);
+// nl: channels of the arrays (default: all L)
+template <typename T> void launch_psi_adj(hs_ctx* c, const T* X, T* Cout /*[n_db][L][N]; null -> coef*/, int nl = -1);
+template <typename T> void launch_psi_sum(hs_ctx* c, const T* Cdb /*[n_db][L][N]*/, const T* C0, T* Xout, int nl = -1);
 template <typename T> void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T* coef, const T* wbar, double thr, int mode);
 
 // nuclear (k_nuclear.hip)
@@ -287,6 +288,9 @@ template <typename T> void launch_chan_norms(hs_ctx* c, const T* X, double* out)
 template <typename T> void launch_chan_max(hs_ctx* c, const T* X, double* out);
 template <typename T> void launch_set_center(hs_ctx* c, T* X);
 template <typename T> int launch_l21_norm(hs_ctx* c, const T* X, const T* coef);
+template <typename T> void launch_l21_rowsq(hs_ctx* c, const T* X, const T* coef, int nl, double* S, bool acc);
+template <typename T> void launch_l21_rowscale(hs_ctx* c, T* X, T* coef, int nl, const double* S, const T* wbar, double scale);
+template <typename T> int launch_l21_from_rowsq(hs_ctx* c, const double* S, const T* wbar);
 template <typename T> void launch_chan_scale(hs_ctx* c, T* X, const double* nrm);
 template <typename T> void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);
 template <typename T> void launch_reweight_l1(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb);

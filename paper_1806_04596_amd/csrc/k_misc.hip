@@ -212,6 +212,58 @@ __global__ __launch_bounds__(256) void k_l21_norm(const T* __restrict__ X, const
     if (threadIdx.x == 0) part[(size_t)d * gridDim.x + blockIdx.x] = acc;
 }
 
+// Squared l2 norms of the rows of Psi^dag X (Sec. 2.3: a row is one coefficient of one
+// basis across the channels) over a chunk of nl channels, in FP64: X is the chunk's Dirac
+// basis [nl][N], coef its n_db wavelet bases [n_db][nl][N].  S[d][p] receives the sum
+// (acc = 0) or adds it (acc = 1); the channels are summed in order.
+template <typename T>
+__global__ void k_l21_rowsq(const T* __restrict__ X, const T* __restrict__ coef, int nl, int64_t N,
+                            double* __restrict__ S, int acc) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int d = blockIdx.y;
+    const T* src = (d == 0) ? X + p : coef + (size_t)(d - 1) * nl * N + p;
+    double n2 = 0.0;
+    for (int l = 0; l < nl; ++l) {
+        const double v = (double)src[(size_t)l * N];
+        n2 += v * v;
+    }
+    double* out = S + (size_t)d * N + p;
+    *out = acc ? *out + n2 : n2;
+}
+
+// Gradient of sum_r wbar_r ||c_r|| with respect to the coefficients of a chunk of nl
+// channels: c <- scale * wbar_r * c / ||c_r|| with ||c_r||^2 = S[d][p] from k_l21_rowsq
+// over all channels (0 on a zero row, the subgradient of least norm).  wbar may be null.
+template <typename T>
+__global__ void k_l21_rowscale(T* __restrict__ X, T* __restrict__ coef, int nl, int64_t N,
+                               const double* __restrict__ S, const T* __restrict__ wbar, double scale) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int d = blockIdx.y;
+    const double n2 = S[(size_t)d * N + p];
+    double f = n2 > 0.0 ? scale / sqrt(n2) : 0.0;
+    if (wbar) f *= (double)wbar[(size_t)d * N + p];
+    T* dst = (d == 0) ? X + p : coef + (size_t)(d - 1) * nl * N + p;
+    for (int l = 0; l < nl; ++l) dst[(size_t)l * N] = (T)(f * (double)dst[(size_t)l * N]);
+}
+
+// Partials of sum_{d,p} wbar[d][p] sqrt(S[d][p]) (the weighted l2,1 norm from the row
+// sums of squares), FP64, fixed reduction order; wbar may be null.
+template <typename T>
+__global__ __launch_bounds__(256) void k_l21_from_rowsq(const double* __restrict__ S, const T* __restrict__ wbar,
+                                                        int64_t N, double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int d = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+        const double r = sqrt(S[(size_t)d * N + p]);
+        acc += wbar ? (double)wbar[(size_t)d * N + p] * r : r;
+    }
+    acc = block_sum_256(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)d * gridDim.x + blockIdx.x] = acc;
+}
+
 // eq:weights-l21: wbar[d][p] = gb / (gb + ||(Psi^dag X)_{d,p}||) over the L channels.
 template <typename T>
 __global__ void k_reweight_l21(const T* __restrict__ X, const T* __restrict__ coef, T* __restrict__ wbar, double gb,
@@ -304,6 +356,27 @@ int launch_l21_norm(hs_ctx* c, const T* X, const T* coef) {
 }
 
 template <typename T>
+void launch_l21_rowsq(hs_ctx* c, const T* X, const T* coef, int nl, double* S, bool acc) {
+    dim3 g(nb(c->N, 256), c->D);
+    k_l21_rowsq<T><<<g, 256, 0, c->stream>>>(X, coef, nl, c->N, S, acc ? 1 : 0);
+}
+
+template <typename T>
+void launch_l21_rowscale(hs_ctx* c, T* X, T* coef, int nl, const double* S, const T* wbar, double scale) {
+    dim3 g(nb(c->N, 256), c->D);
+    k_l21_rowscale<T><<<g, 256, 0, c->stream>>>(X, coef, nl, c->N, S, wbar, scale);
+}
+
+// Partials of sum wbar sqrt(S) into red_part[0 .. D * 64); returns their number.
+template <typename T>
+int launch_l21_from_rowsq(hs_ctx* c, const double* S, const T* wbar) {
+    const int nch = 64;
+    dim3 g(nch, c->D);
+    k_l21_from_rowsq<T><<<g, 256, 0, c->stream>>>(S, wbar, c->N, c->d.red_part);
+    return nch * c->D;
+}
+
+template <typename T>
 void launch_reweight_l21(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb) {
     dim3 g(nb(c->N, 256), c->D);
     k_reweight_l21<T><<<g, 256, 0, c->stream>>>(X, coef, wbar, gb, c->L, c->N);
@@ -316,6 +389,9 @@ void launch_reweight_l1(hs_ctx* c, const T* X, const T* coef, T* wbar, double gb
 }
 
 #define HS_INST(T)                                                                 \
+    template void launch_l21_rowsq<T>(hs_ctx*, const T*, const T*, int, double*, bool);                 \
+    template void launch_l21_rowscale<T>(hs_ctx*, T*, T*, int, const double*, const T*, double);        \
+    template int launch_l21_from_rowsq<T>(hs_ctx*, const double*, const T*);                           \
     template void launch_reweight_l1<T>(hs_ctx*, const T*, const T*, T*, double);  \
     template void launch_fill<T>(hipStream_t, T*, T, int64_t);                     \
     template void launch_axpby<T>(hipStream_t, T*, const T*, T, T, int64_t);       \

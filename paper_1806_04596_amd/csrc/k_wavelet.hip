@@ -424,8 +424,9 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 // Psi_d^dagger for the n_db wavelet bases of X into Cout [n_db][L][N] (coef if null).
 // Intermediate approximations live in two compact slots of wtmp.
 template <typename T>
-void launch_psi_adj(hs_ctx* c, const T* X, T* Cout) {
+void launch_psi_adj(hs_ctx* c, const T* X, T* Cout, int nl) {
     if (c->n_db == 0) return;
+    const int L = nl > 0 ? nl : c->L;   // channels of X and Cout (the scratch slots hold c->L)
     T* out = Cout ? Cout : (T*)c->d.coef;
     T* slotA = (T*)c->d.wtmp;
     T* slotB = slotA + (size_t)c->n_db * c->L * (c->N / 4);
@@ -437,9 +438,9 @@ void launch_psi_adj(hs_ctx* c, const T* X, T* Cout) {
         const int tiles = ((hy + WV_TB - 1) / WV_TB) * ((hx + WV_TB - 1) / WV_TB);
         T* llout = (lev % 2 == 0) ? slotA : slotB;
         const int last = (lev == c->levels - 1) ? 1 : 0;
-        const int items = tiles * c->L * (lev == 0 ? 1 : c->n_db);
+        const int items = tiles * L * (lev == 0 ? 1 : c->n_db);
         dim3 g(std::min(items, 4096));
-        k_dwt_level<T><<<g, 256, 0, c->stream>>>(X, llin, out, llout, filt, c->L, c->nx, c->ny, mx, my,
+        k_dwt_level<T><<<g, 256, 0, c->stream>>>(X, llin, out, llout, filt, L, c->nx, c->ny, mx, my,
                                                  lev == 0 ? 1 : 0, last, c->n_db);
         llin = llout;
     }
@@ -447,8 +448,9 @@ void launch_psi_adj(hs_ctx* c, const T* X, T* Cout) {
 
 // Xout = C0 + sum_b Psi_b Cdb[b]; C0 (Dirac coefficients) may be null.
 template <typename T>
-void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout) {
-    const int64_t LN = (int64_t)c->L * c->N;
+void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout, int nl) {
+    const int L = nl > 0 ? nl : c->L;   // channels of the coefficients and Xout
+    const int64_t LN = (int64_t)L * c->N;
     if (c->n_db == 0) {
         k_psi_sum<T><<<nblk(LN, 256), 256, 0, c->stream>>>(nullptr, C0, Xout, 0, LN);
         return;
@@ -465,11 +467,11 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout) {
         // bases per work-group: as many as keep the grid at IDWT_MIN_WG or more, so the
         // next basis's window is fetched while this one is filtered
         int bpw = 1;
-        while (!fin && bpw < c->n_db && (int64_t)tiles * c->L * ((c->n_db + 2 * bpw - 1) / (2 * bpw)) >= IDWT_MIN_WG)
+        while (!fin && bpw < c->n_db && (int64_t)tiles * L * ((c->n_db + 2 * bpw - 1) / (2 * bpw)) >= IDWT_MIN_WG)
             bpw *= 2;
         const int nz = fin ? 1 : (c->n_db + bpw - 1) / bpw;
-        dim3 g(tiles, c->L, nz);
-        k_idwt_level<T><<<g, 256, 0, c->stream>>>(Cdb, llin, out, C0, filt, c->L, c->nx, c->ny, mx, my,
+        dim3 g(tiles, L, nz);
+        k_idwt_level<T><<<g, 256, 0, c->stream>>>(Cdb, llin, out, C0, filt, L, c->nx, c->ny, mx, my,
                                                   lev == c->levels - 1 ? 1 : 0, fin, c->n_db, bpw);
         llin = out;
     }
@@ -483,8 +485,8 @@ void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T* coef, const T* wbar,
 }
 
 #define HS_INST(T)                                                                   \
-    template void launch_psi_adj<T>(hs_ctx*, const T*, T*);                          \
-    template void launch_psi_sum<T>(hs_ctx*, const T*, const T*, T*);                \
+    template void launch_psi_adj<T>(hs_ctx*, const T*, T*, int);                     \
+    template void launch_psi_sum<T>(hs_ctx*, const T*, const T*, T*, int);           \
     template void launch_l21_dual<T>(hs_ctx*, T*, const T*, const T*, const T*, double, int);
 HS_INST(float)
 HS_INST(double)

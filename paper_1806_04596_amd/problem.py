@@ -183,19 +183,64 @@ class Problem:
         self._call("hs_phi_adj", self.lib.hs_phi_adj, self._p(Y), self._p(X))
         return X
 
+    def _nch(self, X, lead):
+        """Channel count of a cube ([n][ny][nx], lead = 0) or coefficient array
+        ([D][n][ny][nx], lead = 1) of 1..L channels."""
+        n = X.shape[lead] if X.dim() == 3 + lead else -1
+        if not 1 <= n <= self.L:
+            raise L.HSError(f"expected 1..{self.L} channels, got shape {tuple(X.shape)}")
+        return n
+
     def psi_adj(self, X, Cc=None):
-        self._check_cube(X)
-        Cc = self.empty_coef() if Cc is None else Cc
-        self._check_cube(Cc, (self.D, self.L, self.ny, self.nx))
-        self._call("hs_psi_adj", self.lib.hs_psi_adj, self._p(X), self._p(Cc))
+        """Psi^dagger of L channels, or of a chunk of n < L contiguous channels."""
+        n = self._nch(X, 0)
+        self._check_cube(X, (n, self.ny, self.nx))
+        Cc = self.torch.empty((self.D, n, self.ny, self.nx), dtype=self.tdtype, device=self.device) if Cc is None else Cc
+        self._check_cube(Cc, (self.D, n, self.ny, self.nx))
+        self._call("hs_psi_adj_n", self.lib.hs_psi_adj_n, self._p(X), self._p(Cc), n)
         return Cc
 
     def psi(self, Cc, X=None):
-        self._check_cube(Cc, (self.D, self.L, self.ny, self.nx))
-        X = self.empty_cube() if X is None else X
-        self._check_cube(X)
-        self._call("hs_psi", self.lib.hs_psi, self._p(Cc), self._p(X))
+        """Psi of L channels' coefficients, or of a chunk of n < L channels."""
+        n = self._nch(Cc, 1)
+        self._check_cube(Cc, (self.D, n, self.ny, self.nx))
+        X = self.torch.empty((n, self.ny, self.nx), dtype=self.tdtype, device=self.device) if X is None else X
+        self._check_cube(X, (n, self.ny, self.nx))
+        self._call("hs_psi_n", self.lib.hs_psi_n, self._p(Cc), self._p(X), n)
         return X
+
+    def _check_rowsq(self, S):
+        if S.dtype != self.torch.float64 or tuple(S.shape) != (self.D, self.ny, self.nx) or not S.is_contiguous() \
+                or S.device != self.device:
+            raise L.HSError(f"expected contiguous float64 {(self.D, self.ny, self.nx)} on {self.device}")
+
+    def l21_rowsq(self, Cc, S, accumulate=False):
+        """S (+)= the per-row sums of squares of the chunk's coefficients Cc [D][n][ny][nx]."""
+        n = self._nch(Cc, 1)
+        self._check_cube(Cc, (self.D, n, self.ny, self.nx))
+        self._check_rowsq(S)
+        self._call("hs_l21_rowsq", self.lib.hs_l21_rowsq, self._p(Cc), n, self._p(S), int(bool(accumulate)))
+        return S
+
+    def l21_rowscale(self, Cc, S, wbar=None, scale=1.0):
+        """Cc <- scale * wbar * Cc / ||row|| in place (the l2,1 gradient of the chunk)."""
+        n = self._nch(Cc, 1)
+        self._check_cube(Cc, (self.D, n, self.ny, self.nx))
+        self._check_rowsq(S)
+        if wbar is not None:
+            self._check_cube(wbar, (self.D, self.ny, self.nx))
+        self._call("hs_l21_rowscale", self.lib.hs_l21_rowscale, self._p(Cc), n, self._p(S), self._p(wbar),
+                   float(scale))
+        return Cc
+
+    def l21_from_rowsq(self, S, wbar=None):
+        """sum wbar * sqrt(S) (host float; synchronising)."""
+        self._check_rowsq(S)
+        if wbar is not None:
+            self._check_cube(wbar, (self.D, self.ny, self.nx))
+        v = C.c_double()
+        self._call("hs_l21_from_rowsq", self.lib.hs_l21_from_rowsq, self._p(S), self._p(wbar), C.byref(v))
+        return v.value
 
     def prox_l21(self, A, t, wbar=None):
         self._check_cube(A, (self.D, self.L, self.ny, self.nx))
