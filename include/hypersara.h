@@ -59,9 +59,14 @@ typedef struct hs_ctx hs_ctx;
  *   HS_GRAM_F32        FP32 products, FP32 accumulation within a slab of pixels,
  *                      FP64 across slabs;
  *   HS_GRAM_BF16_SPLIT each input z = z_hi + z_lo with both parts in BF16 and
- *                      C ~ Z_hi^T Z_hi + Z_hi^T Z_lo + Z_lo^T Z_hi (the correction
- *                      terms are the one refinement step), FP32 accumulation within
- *                      a slab, FP64 across slabs. */
+ *                      C ~ Z_hi^T Z_hi + Z_hi^T Z_lo + Z_lo^T Z_hi, FP32 accumulation
+ *                      within a slab, FP64 across slabs; then one refinement step.
+ * The refinement (a Rayleigh-Ritz step) forms H = (Z V)^T (Z V) from the data and the
+ * first eigenvectors V (FP64 products) and decomposes it again; the eigenvectors are
+ * V times those of H.  H carries rounding of order eps sigma_i sigma_j where C carries
+ * eps sigma_1^2, so the small singular values and their directions come out as
+ * accurate as from a direct SVD.  FP64 contexts always refine; FP32 contexts refine in
+ * the BF16-split mode only. */
 enum { HS_GRAM_F64 = 0, HS_GRAM_F32 = 1, HS_GRAM_BF16_SPLIT = 2 };
 
 /* Problem description (Sec. 2.1 data model, Sec. 2.3 dictionary).

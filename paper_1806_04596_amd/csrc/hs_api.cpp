@@ -310,12 +310,21 @@ static void dual_data_impl(hs_ctx* c, cplx<T>* v, const T* Xt, T* adj, const Pha
     }
 }
 
+// Eigen-decomposition of the Gram matrix of Z = P + Xt (Xt may be null), refined by a
+// Rayleigh-Ritz step where the context asks for it (the refinement counts as eig time).
+template <typename T>
+static void nuclear_eig(hs_ctx* c, const T* P, const T* Xt, int mode, bool force64,
+                        const PhaseMarks& pm = PhaseMarks()) {
+    launch_gram<T>(c, P, Xt, force64);
+    pm.mark(c, HS_PH_GRAM + 1);
+    launch_eig(c, mode);
+    if (eig_refined(c, force64)) launch_eig_refine<T>(c, P, Xt, mode);
+    pm.mark(c, HS_PH_EIG + 1);
+}
+
 template <typename T>
 static void dual_nuclear_impl(hs_ctx* c, T* P, const T* Xt, const PhaseMarks& pm = PhaseMarks()) {
-    launch_gram<T>(c, P, Xt);
-    pm.mark(c, HS_PH_GRAM + 1);
-    launch_eig(c, 0);
-    pm.mark(c, HS_PH_EIG + 1);
+    nuclear_eig<T>(c, P, Xt, 0, false, pm);
     launch_backproject<T>(c, P, P, Xt);
     pm.mark(c, HS_PH_BACKPROJ + 1);
 }
@@ -474,8 +483,7 @@ static hs_status dirty_mu_impl(hs_ctx* c, T* Xd, double* mu) {
     launch_chan_scale<T>(c, X, d.chan_nrm);
     if (!mu) return HS_OK;
     // nuclear norm from the FP64 eigen-decomposition of the L x L Gram matrix
-    launch_gram<T>(c, X, (const T*)nullptr, true);
-    launch_eig(c, 0);
+    nuclear_eig<T>(c, X, (const T*)nullptr, 0, true);
     std::vector<double> sg(MAX_L);
     hipMemcpyAsync(sg.data(), d.eig_sig, MAX_L * 8, hipMemcpyDeviceToHost, c->stream);
     launch_psi_adj<T>(c, X, nullptr);
@@ -852,7 +860,7 @@ hs_status hs_prox_nuclear(hs_ctx* c, void* X, const double* w, double* sigma_out
     std::vector<double> saved = c->w_host;
     s = upload_w(c, w);
     if (s) return s;
-    HS_DISPATCH(c, { launch_gram<T>(c, (const T*)X, nullptr); launch_eig(c, 1);
+    HS_DISPATCH(c, { nuclear_eig<T>(c, (const T*)X, (const T*)nullptr, 1, false);
                      launch_backproject<T>(c, (T*)X, (const T*)X, nullptr); });
     s = launched(c, "hs_prox_nuclear");
     if (s) return s;
@@ -1158,8 +1166,7 @@ static hs_status solve_reweight(hs_ctx* c, double gamma, double gamma_bar) {
             launch_reweight_l1<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
         } else {
             launch_reweight_l21<T>(c, (const T*)c->d.X, (const T*)c->d.coef, (T*)c->d.wbar, gamma_bar);
-            launch_gram<T>(c, (const T*)c->d.X, nullptr, true);
-            launch_eig(c, 0);
+            nuclear_eig<T>(c, (const T*)c->d.X, (const T*)nullptr, 0, true);
         }
     });
     hs_status s = launched(c, "hs_solve reweight");

@@ -279,6 +279,10 @@ template <typename T> void launch_l21_dual(hs_ctx* c, T* A, const T* Xt, const T
 // Gram of P + Xt (Xt may be null) in the context's Gram precision, or in FP64 when force64.
 template <typename T> void launch_gram(hs_ctx* c, const T* P, const T* Xt, bool force64 = false);
 void launch_eig(hs_ctx* c, int mode);
+// Rayleigh-Ritz refinement of the eigen-decomposition (FP64 contexts, and the BF16-split
+// Gram of FP32 contexts); eig_refined says whether a context applies it.
+template <typename T> void launch_eig_refine(hs_ctx* c, const T* P, const T* Xt, int mode);
+bool eig_refined(const hs_ctx* c, bool force64 = false);
 void launch_eig_reset(hs_ctx* c);
 template <typename T> void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2);
 

@@ -90,6 +90,92 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ P, const T* 
     }
 }
 
+// Refinement Gram H = (Z V)^T (Z V) = V^T Z^T Z V for the eigenvectors V of a first
+// eigen-decomposition (a Rayleigh-Ritz step): each 64-pixel slab S of Z (channels x
+// pixels, widened exactly to FP64) is first turned into T = V^T S on the FP64 matrix
+// cores, then T T^T is accumulated as in k_gram.  Entry (i, j) of H carries rounding
+// of the order of eps sigma_i sigma_j instead of eps sigma_1^2, so the eigenvectors of
+// H (nearly diagonal) refine those of the Gram matrix to the accuracy of a direct SVD.
+// V: [MAX_L][MAX_L] row a = channel, column j = mode; rows and columns >= L are those
+// of the identity, so the padded modes stay zero.
+template <typename T, bool HAS2>
+__global__ __launch_bounds__(256) void k_gram_rr(const T* __restrict__ P, const T* __restrict__ Xt,
+                                                 const double* __restrict__ V, double* __restrict__ part, int L,
+                                                 int64_t N, int64_t chunk) {
+    __shared__ double S[MAX_L][GR_SLAB + 2];
+    __shared__ double Tt[MAX_L][GR_SLAB + 2];
+    constexpr int PER = MAX_L * GR_SLAB / 256;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, kq = lane >> 4;
+    const int64_t p_begin = (int64_t)blockIdx.x * chunk;
+    const int64_t p_end = min(N, p_begin + chunk);
+    // A operand of T = V^T S for this wave's 16 modes: A[i][k] = V[4 st + k][16 wave + i]
+    double va[MAX_L / 4];
+#pragma unroll
+    for (int st = 0; st < MAX_L / 4; ++st) va[st] = V[(4 * st + kq) * MAX_L + 16 * wave + i];
+    double4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    T nv[PER], nv2[PER];
+    bool nin[PER];
+    auto load = [&](int64_t p0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            const int64_t pix = p0 + pp;
+            nin[k] = ch < L && pix < p_end;
+            const size_t idx = (size_t)min(ch, L - 1) * N + (size_t)min(pix, p_end - 1);
+            nv[k] = P[idx];
+            if (HAS2) nv2[k] = Xt[idx];
+        }
+    };
+    load(p_begin);
+    for (int64_t p0 = p_begin; p0 < p_end; p0 += GR_SLAB) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            const int ch = e / GR_SLAB, pp = e - ch * GR_SLAB;
+            T z = nv[k];
+            if (HAS2) z += nv2[k];
+            S[ch][pp] = nin[k] ? (double)z : 0.0;
+        }
+        __syncthreads();
+        if (p0 + GR_SLAB < p_end) load(p0 + GR_SLAB);
+        // T rows 16 wave .. + 15 (modes), all 64 pixel columns
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            double4_t t = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < MAX_L / 4; ++st)
+                t = __builtin_amdgcn_mfma_f64_16x16x4f64(va[st], S[4 * st + kq][16 * jb + i], t, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Tt[16 * wave + kq + 4 * r][16 * jb + i] = t[r];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GR_SLAB; kk += 4) {
+            const double a = Tt[wave * 16 + i][kk + kq];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const double b = Tt[jb * 16 + i][kk + kq];
+                acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double* out = part + (size_t)blockIdx.x * MAX_L * MAX_L;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + (lane >> 4) + 4 * r;
+            const int col = jb * 16 + (lane & 15);
+            out[row * MAX_L + col] = acc[jb][r];
+        }
+    }
+}
+
 // Gram partials in FP32 products (MODE 1) or BF16 split products (MODE 2) of an FP32
 // Z = P + Xt, accumulated in FP32 over the work-group's pixels; the partials are
 // summed in FP64 by k_gram_reduce.
@@ -216,12 +302,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // One workgroup of EIG_THREADS threads.  A (n x n, n = L rounded up to even) and V in LDS.
 // mode 0: f = min(1, w/s) (I - S*_w); mode 1: f = 1 - min(1, w/s) (S*_w / X).
 // warm: start from V = previous eigenvectors (A <- V^T C V).
+// Vbase (may be null): Cg is Vbase^T C Vbase (a refinement Gram); the eigenvectors
+// returned, stored and used for W are Vbase V.  Vbase may be Vg (it is read into LDS
+// before Vg is written), so neither is restrict-qualified.
 constexpr int EIG_THREADS = 1024;
 template <typename TW>
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ Cg, double* __restrict__ Vg,
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ Cg, double* Vg,
                                              double* __restrict__ sig_out, const double* __restrict__ w,
                                              TW* __restrict__ Wout, int L, int mode, int warm,
-                                             double* __restrict__ diag) {
+                                             double* __restrict__ diag, const double* Vbase) {
     __shared__ double A[MAX_L][MAX_L + 1];
     __shared__ double V[MAX_L][MAX_L + 1];
     __shared__ double Tm[MAX_L][MAX_L + 1];
@@ -359,6 +448,26 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const double* __restrict__ 
     // sort eigenvalues in decreasing order (rank by comparison, ties by index)
     if (tid < n) lam[tid] = A[tid][tid];
     __syncthreads();
+    if (Vbase) {
+        // refinement: the eigenvectors of C are Vbase V (this call decomposed Vbase^T C Vbase)
+        for (int e = tid; e < n * n; e += EIG_THREADS) {
+            const int i = e / n, j = e - i * n;
+            Tm[i][j] = Vbase[i * MAX_L + j];
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += EIG_THREADS) {
+            const int i = e / n, j = e - i * n;
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += Tm[i][k] * V[k][j];
+            A[i][j] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += EIG_THREADS) {
+            const int i = e / n, j = e - i * n;
+            V[i][j] = A[i][j];
+        }
+        __syncthreads();
+    }
     if (tid < L) {
         int rank = 0;
         const double li = lam[tid];
@@ -505,14 +614,36 @@ void launch_gram(hs_ctx* c, const T* P, const T* Xt, bool force64) {
     k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
 }
 
-void launch_eig(hs_ctx* c, int mode) {
-    const int warm = 1;  // eigV starts as the identity, so the first call is a cold start
+static void eig_call(hs_ctx* c, int mode, int warm, double* diag, const double* vbase) {
     if (c->dtype == HS_F32)
-        k_eig<float><<<1, EIG_THREADS, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (float*)c->d.Wmat,
-                                               c->L, mode, warm, c->d.scal + 8);
+        k_eig<float><<<1, EIG_THREADS, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc,
+                                                       (float*)c->d.Wmat, c->L, mode, warm, diag, vbase);
     else
-        k_eig<double><<<1, EIG_THREADS, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc, (double*)c->d.Wmat,
-                                                c->L, mode, warm, c->d.scal + 8);
+        k_eig<double><<<1, EIG_THREADS, 0, c->stream>>>(c->d.gram, c->d.eigV, c->d.eig_sig, c->d.w_nuc,
+                                                        (double*)c->d.Wmat, c->L, mode, warm, diag, vbase);
+}
+
+void launch_eig(hs_ctx* c, int mode) {
+    // eigV starts as the identity, so the first call is a cold start
+    eig_call(c, mode, 1, c->d.scal + 8, nullptr);
+}
+
+// The Rayleigh-Ritz refinement of the eigen-decomposition just computed (eigV): the
+// Gram of Z V in FP64 (k_gram_rr), decomposed from the identity, the eigenvectors
+// composed with V.  W, sigma and the stored eigenvectors are those of the refinement.
+template <typename T>
+void launch_eig_refine(hs_ctx* c, const T* P, const T* Xt, int mode) {
+    int64_t chunk = (c->N + NGRAM - 1) / NGRAM;
+    chunk = (chunk + GR_SLAB - 1) / GR_SLAB * GR_SLAB;
+    const int nparts = (int)((c->N + chunk - 1) / chunk);
+    if (Xt) k_gram_rr<T, true><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.eigV, c->d.gram_part, c->L, c->N, chunk);
+    else k_gram_rr<T, false><<<nparts, 256, 0, c->stream>>>(P, Xt, c->d.eigV, c->d.gram_part, c->L, c->N, chunk);
+    k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, c->stream>>>(c->d.gram_part, c->d.gram, nparts);
+    eig_call(c, mode, 0, nullptr, c->d.eigV);
+}
+
+bool eig_refined(const hs_ctx* c, bool force64) {
+    return c->dtype == HS_F64 || (!force64 && c->gram_mode == HS_GRAM_BF16_SPLIT);
 }
 
 template <typename T>
@@ -523,6 +654,8 @@ void launch_backproject(hs_ctx* c, T* out, const T* in1, const T* in2) {
     else k_backproject<T, false><<<nb, 256, 0, c->stream>>>(in1, in2, (const T*)c->d.Wmat, out, c->L, c->N);
 }
 
+template void launch_eig_refine<float>(hs_ctx*, const float*, const float*, int);
+template void launch_eig_refine<double>(hs_ctx*, const double*, const double*, int);
 template void launch_gram<float>(hs_ctx*, const float*, const float*, bool);
 template void launch_gram<double>(hs_ctx*, const double*, const double*, bool);
 template void launch_backproject<float>(hs_ctx*, float*, const float*, const float*);
@@ -588,7 +721,12 @@ static void na_launch(double* base, T* X, int64_t N, int L, hipStream_t st) {
     const int nparts = (int)((N + chunk - 1) / chunk);
     k_gram<T, false><<<nparts, 256, 0, st>>>(X, nullptr, part, L, N, chunk);
     k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, st>>>(part, C, nparts);
-    k_eig<T><<<1, EIG_THREADS, 0, st>>>(C, V, sig, w, (T*)Wm, L, 1, 0, nullptr);
+    k_eig<T><<<1, EIG_THREADS, 0, st>>>(C, V, sig, w, (T*)Wm, L, 1, 0, nullptr, nullptr);
+    if (sizeof(T) == 8) {   // FP64: the Rayleigh-Ritz refinement, as in an FP64 context
+        k_gram_rr<T, false><<<nparts, 256, 0, st>>>(X, nullptr, V, part, L, N, chunk);
+        k_gram_reduce<<<(MAX_L * MAX_L + GRR_E - 1) / GRR_E, 256, 0, st>>>(part, C, nparts);
+        k_eig<T><<<1, EIG_THREADS, 0, st>>>(C, V, sig, w, (T*)Wm, L, 1, 0, nullptr, V);
+    }
     const int64_t nt = (N + 15) / 16;
     const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(BP_WAVES, nt) / 4);
     k_backproject<T, false><<<nb, 256, 0, st>>>(X, nullptr, (const T*)Wm, X, L, N);

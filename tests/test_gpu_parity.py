@@ -195,6 +195,34 @@ def test_dual_data_parity(name, dtype):
     check_rel_pc(host(adj), adj_ref, TOL[dtype], "host(adj)")
 
 
+@pytest.mark.parametrize("mode", ["prox", "dual"])
+def test_nuclear_ill_conditioned_f64(mode):
+    """An ill-conditioned 65536 x 15 matrix (singular values 1e3 .. 1e-3, unit weights
+    that cut through the spectrum): the Gram route alone loses about eps sigma_1^2 /
+    sigma_j^2 on the small modes; with the Rayleigh-Ritz refinement of an FP64 context
+    the prox, the dual and every singular value match the oracle's SVD at the FP64 bar."""
+    cfg, inp, op = oracle_case("cube256_L15")
+    prob, _, _ = gpu_case("cube256_L15", "f64")
+    L, N = cfg.L, cfg.N
+    rng = np.random.default_rng(12)
+    U, _ = np.linalg.qr(rng.standard_normal((N, L)))
+    V, _ = np.linalg.qr(rng.standard_normal((L, L)))
+    s = np.logspace(3, -3, L)
+    X = ((U * s) @ V.T).T.reshape(L, cfg.ny, cfg.nx)
+    w = np.ones(L)
+    if mode == "prox":
+        Xd, sig = prob.prox_nuclear(to_dev(prob, X), w)
+        ref, s_ref = prox.prox_nuclear_svd(X, w)
+        e = check_rel(host(Xd), ref, TOL["f64"], "prox")
+        e_s = float(np.max(np.abs(sig - s_ref) / s_ref))
+        print(f"ill-conditioned prox: {e:.2e}, largest relative singular value error {e_s:.2e}")
+        assert e_s <= TOL["f64"]
+    else:
+        Pd = prob.dual_nuclear(to_dev(prob, np.zeros_like(X)), to_dev(prob, X), w)
+        e = check_rel(host(Pd), prox.dual_nuclear(np.zeros_like(X), X, w, "svd"), TOL["f64"], "dual")
+        print(f"ill-conditioned dual: {e:.2e}")
+
+
 @pytest.mark.parametrize("gram_mode", ["f32", "bf16_split"])
 @pytest.mark.parametrize("name", ["cube64_L5", "cube64_L4"])
 def test_nuclear_parity_low_precision_gram(name, gram_mode):
