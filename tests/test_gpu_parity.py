@@ -333,8 +333,9 @@ def test_pd_twenty_iterations_f64():
     for _ in range(20):
         ost = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
     g, beta, _ = _run_gpu_iteration(prob, st, prm, w, n=20)
-    check_rel(g["X"], ost.X, 1e-11, "g['X']")
-    assert abs(beta - ost.beta) <= 1e-10 * ost.beta
+    check_rel(g["X"], ost.X, TOL["f64"], "g['X']")
+    # beta is a difference of consecutive iterates relative to ||X||: 2 tol absolute
+    assert abs(beta - ost.beta) <= 2 * TOL["f64"]
 
 
 def test_graph_replays_match_oracle_each_time():

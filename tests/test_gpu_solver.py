@@ -49,12 +49,12 @@ def test_reweighted_solve_vs_oracle(dtype, prior):
     X, rep = prob.solve(2, 6, gamma_factor=0.8)
     assert rep["gamma"] == pytest.approx(0.64) and rep["gamma_bar"] == pytest.approx(0.64)
     wbar = host(prob.get_state(full=True, prior=prior)["wbar"])
-    tolw = 1e-11 if dtype == "f64" else TOL["f32"]
-    check_rel(wbar, oprm.wbar, tolw, "wbar")
+    tol = TOL[dtype]
+    check_rel(wbar, oprm.wbar, tol, "wbar")
     assert rep["iterations"] == 18 and rep["reweights"] == 2
-    tol = 1e-11 if dtype == "f64" else TOL["f32"]
     check_rel(host(X), ost.X, tol, "X")
-    assert abs(rep["final_beta"] - hist[-1]) <= tol * hist[-1]
+    # beta is a difference of consecutive iterates relative to ||X||: 2 tol absolute
+    assert abs(rep["final_beta"] - hist[-1]) <= 2 * tol
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
