@@ -60,9 +60,10 @@ struct SplitTile {
 // Chebyshev interpolant of phi on that tap's unit interval, in monomial form).
 // phi is even, so tap 7 - j is tap j at -t: only taps 0..3 are stored, each
 // split into its even and odd parts, p_j(+-t) = E_j(t^2) +- t O_j(t^2).
-// Degree per precision (maximum error 7e-8 in FP32, 6e-15 in FP64, relative to phi(0)).
+// Degree per precision (maximum error 1e-7 in FP32 Horner arithmetic, 6e-15 in FP64,
+// relative to phi(0); FP32 rounding dominates from degree 7 on).
 template <typename T> struct KBDeg;
-template <> struct KBDeg<float> { static constexpr int n = 8; };
+template <> struct KBDeg<float> { static constexpr int n = 7; };
 template <> struct KBDeg<double> { static constexpr int n = 13; };
 
 template <typename T>
