@@ -503,10 +503,16 @@ __device__ __forceinline__ void kb_weights(T f, const KBPoly<T>& P, T* w) {
 // g0 points at kx = 0 of the channel's grid (rows of Wg cells).  Cells beyond the
 // half plane (kx < 0 or kx > Kx/2) are the conjugates of their reflections
 // (Hermitian symmetry of the transform of a real image); y is periodic.
+// The staged grid window of a degridding tile: TT + 8 rows of TT + 8 cells at a row
+// stride of TT + 8 + DEG_PAD cells (the padding moves neighbouring rows to other LDS
+// banks).
+constexpr int DEG_PAD = 1;
+__host__ __device__ constexpr int deg_stride(int TT) { return TT + 8 + DEG_PAD; }
+
 template <typename T>
 __device__ __forceinline__ void stage_tile(cplx<T>* tileS, const cplx<T>* g0, int ox, int oy, int TT, int Kh, int Ky,
                                            int Wg) {
-    const int W = TT + 8;
+    const int W = TT + 8, S = deg_stride(TT);
     for (int e = threadIdx.x; e < W * W; e += blockDim.x) {
         const int ry = e / W, rx = e - ry * W;
         int gy = oy - 3 + ry;
@@ -522,7 +528,7 @@ __device__ __forceinline__ void stage_tile(cplx<T>* tileS, const cplx<T>* g0, in
             const cplx<T> w = g0[(size_t)my * Wg + mx];
             v = {w.re, -w.im};
         }
-        tileS[e] = v;
+        tileS[ry * S + rx] = v;
     }
 }
 
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
-    const int W = TT + 8;
+    const int W = deg_stride(TT);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // chunk j of the unit (DEG_CHUNK visibilities) is walked by wave j mod 4
     for (int j = wave; j * DEG_CHUNK < u.count; j += DEG_THREADS / DEG_CHUNK) {
@@ -605,7 +611,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const int ox = (u.tile % tiles_x) * TT, oy = (u.tile / tiles_x) * TT;
     stage_tile(tileS, grid + (size_t)u.l * Ky * Wg + GR_MARGIN, ox, oy, TT, Kh, Ky, Wg);
     __syncthreads();
-    const int W = TT + 8;
+    const int W = deg_stride(TT);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // lanes <= this one
     // chunk j of the unit (DEG_CHUNK visibilities) is walked by wave j mod 4
@@ -1066,7 +1072,7 @@ void launch_degrid_plain(hs_ctx* c, cplx<T>* out_user, int lc) {
     int64_t u0, nu;
     chan_range(c->dunit_off, lc, u0, nu);
     if (nu == 0) return;
-    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    const size_t lds = (size_t)(c->T + 8) * deg_stride(c->T) * sizeof(cplx<T>);
     k_degrid_plain<T, true, false><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
         c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, nullptr, c->d.vis_perm, out_user, c->Kh, c->Ky, c->Wg, c->T, c->tiles_x,
@@ -1079,7 +1085,7 @@ void launch_degrid_grid_order(hs_ctx* c, cplx<T>* out, const T* mult, int lc) {
     int64_t u0, nu;
     chan_range(c->dunit_off, lc, u0, nu);
     if (nu == 0) return;
-    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    const size_t lds = (size_t)(c->T + 8) * deg_stride(c->T) * sizeof(cplx<T>);
     auto launch = [&](auto kern) {
         kern<<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
             c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
@@ -1095,7 +1101,7 @@ void launch_degrid_dual_v(hs_ctx* c, cplx<T>* v, int lc) {
     int64_t u0, nu;
     chan_range(c->dunit_off, lc, u0, nu);
     if (nu == 0) return;
-    const size_t lds = (size_t)(c->T + 8) * (c->T + 8) * sizeof(cplx<T>);
+    const size_t lds = (size_t)(c->T + 8) * deg_stride(c->T) * sizeof(cplx<T>);
     k_degrid_dual<T><<<(unsigned)nu, DEG_THREADS, lds, c->stream>>>(
         c->d.dunits + u0, c->d.vis_cell, (const cplx<T>*)c->d.vis_frac, (const cplx<T>*)c->d.grid,
         (const T*)c->d.vis_theta, (const T*)c->d.vis_u, (const cplx<T>*)c->d.vis_y, c->d.vis_bin, v,
