@@ -605,6 +605,14 @@ hs_status hs_create(const hs_problem_desc* desc, hs_ctx** out) {
 
 hs_status hs_destroy(hs_ctx* c) {
     if (!c) return HS_ERR_INVALID_ARG;
+    // the context's work (graph replays, side streams) must be done before its graph,
+    // streams and events go away
+    if (c->gexec || c->side[0] || c->side[1]) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        for (int k = 0; k < 2; ++k)
+            if (c->side[k]) (void)hipStreamSynchronize(c->side[k]);
+    }
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
     for (int k = 0; k < 2; ++k) {
@@ -1047,7 +1055,13 @@ hs_status hs_pd_get_state(hs_ctx* c, const hs_state_ptrs* st) {
 }
 
 static hs_status pd_capture(hs_ctx* c) {
-    if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+    if (c->gexec) {
+        // replays of the old graph may still be in flight on the stream
+        hs_status s0 = hip_check(c, hipStreamSynchronize(c->stream), "before re-capture");
+        if (s0) return s0;
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
     if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
     hs_status s = HS_OK;
     for (int k = 0; k < 2 && !s; ++k) {
