@@ -820,7 +820,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Staged operands of one entry: its eight kernel values with a zero on each side,
 // so that an operand is a single LDS read at a clamped index (no masks).
 constexpr int GR_WS = KB_J + 2;
-constexpr int GR_BATCH = 32;   // entries staged per batch (two lanes per entry)
+constexpr int GR_BATCH = 64;   // entries staged per batch (one lane per entry)
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_grid_pull(
@@ -832,41 +832,35 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     // sd[e] = (dy, dx), the offsets of its first tap from the block origin
     __shared__ T sA[GR_BATCH * GR_WS];
     __shared__ cplx<T> sB[GR_BATCH * GR_WS];
-    __shared__ int sd[2 * GR_BATCH];
+    __shared__ int2 sd[GR_BATCH];
     // gridding units are in block order (row-major per channel), and a visibility
     // is listed by up to four neighbouring blocks: grouping keeps neighbours on one L2
     const GridUnit u = units[xcd_group_item(blockIdx.x, gridDim.x, xg)];
     const int lane = threadIdx.x, il = lane & 15, kq = lane >> 4;
-    // staging: lane (e, dim) = (lane % 32, lane / 32) evaluates one dimension of entry e
-    const int se = lane & (GR_BATCH - 1), dim = lane / GR_BATCH;
+    // staging: lane e evaluates both dimensions of entry e of the batch
+    const int se = lane;
     const int bx0 = (u.tile % nbx - 1) * GB, by0 = (u.tile / nbx) * GB;   // bx0 = -GB for the margin block
     const int32_t* gl = glist + u.g0;
     const int n = u.gn;
-    if (dim) {
-        sA[se * GR_WS] = T(0);
-        sA[se * GR_WS + KB_J + 1] = T(0);
-    } else {
-        sB[se * GR_WS] = cplx<T>{T(0), T(0)};
-        sB[se * GR_WS + KB_J + 1] = cplx<T>{T(0), T(0)};
-    }
+    sA[se * GR_WS] = T(0);
+    sA[se * GR_WS + KB_J + 1] = T(0);
+    sB[se * GR_WS] = cplx<T>{T(0), T(0)};
+    sB[se * GR_WS + KB_J + 1] = cplx<T>{T(0), T(0)};
     // two accumulator pairs (even and odd groups of four entries), so that
     // consecutive products do not wait on each other
     acc_t are0{}, aim0{}, are1{}, aim1{};
     // software pipeline: the next batch's entry data are loaded while this batch
     // is gridded, and the list positions of the one after
     int cc_n = 0;
-    T f_n = T(0);
+    cplx<T> f_n{T(0), T(0)};
     cplx<T> val_n{T(0), T(0)};
     T w_n = T(1);
     auto fetch = [&](int p) {
         if (p >= 0) {
             cc_n = cell[p];
-            const T* fp = reinterpret_cast<const T*>(frac + p);
-            f_n = fp[dim];
-            if (!dim) {
-                val_n = vals[p];
-                if (weight) w_n = weight[p];
-            }
+            f_n = frac[p];
+            val_n = vals[p];
+            if (weight) w_n = weight[p];
         }
     };
     int pos_n = se < n ? gl[se] : -1;
@@ -875,47 +869,43 @@ __global__ __launch_bounds__(64) void k_grid_pull(
     for (int base = 0; base < n; base += GR_BATCH) {
         const int pos = pos_n;
         const int cc = cc_n;
-        const T f = f_n;
+        const cplx<T> f = f_n;
         cplx<T> val = val_n;
         const T wt = w_n;
         pos_n = pos_nn;
         fetch(pos_n);
         pos_nn = base + 2 * GR_BATCH + se < n ? gl[base + 2 * GR_BATCH + se] : -1;
-        int d0 = 2 * GB;   // an empty slot: every tap falls outside the block
-        T w8[KB_J];
+        int dy = 2 * GB, dx = 2 * GB;   // an empty slot: every tap falls outside the block
+        T wx8[KB_J], wy8[KB_J];
         if (pos >= 0) {
-            if (dim) {
-                d0 = (cc >> 16) - 3 - by0;
-                if (d0 < -(KB_J - 1)) d0 += Ky;
-                if (d0 > GB - 1) d0 -= Ky;
-            } else {
-                d0 = (cc & 0x7FFF) - 3 - bx0;   // the half plane has no wrap in x
-            }
-            kb_weights(f, kb, w8);
+            dy = (cc >> 16) - 3 - by0;
+            if (dy < -(KB_J - 1)) dy += Ky;
+            if (dy > GB - 1) dy -= Ky;
+            dx = (cc & 0x7FFF) - 3 - bx0;   // the half plane has no wrap in x
+            kb_weights(f.re, kb, wx8);
+            kb_weights(f.im, kb, wy8);
         } else {
 #pragma unroll
-            for (int j = 0; j < KB_J; ++j) w8[j] = T(0);
+            for (int j = 0; j < KB_J; ++j) wx8[j] = wy8[j] = T(0);
         }
-        if (dim) {
-#pragma unroll
-            for (int j = 0; j < KB_J; ++j) sA[se * GR_WS + 1 + j] = w8[j];
-        } else {
-            if (weight) {
-                val.re *= wt;
-                val.im *= wt;
-            }
-            const T vr = val.re, vi = (cc & 0x8000) ? -val.im : val.im;   // reflected: conjugate value
-#pragma unroll
-            for (int j = 0; j < KB_J; ++j) sB[se * GR_WS + 1 + j] = cplx<T>{w8[j] * vr, w8[j] * vi};
+        if (weight) {
+            val.re *= wt;
+            val.im *= wt;
         }
-        sd[2 * se + (dim ^ 1)] = d0;   // (dy, dx)
+        const T vr = val.re, vi = (cc & 0x8000) ? -val.im : val.im;   // reflected: conjugate value
+#pragma unroll
+        for (int j = 0; j < KB_J; ++j) {
+            sA[se * GR_WS + 1 + j] = wy8[j];
+            sB[se * GR_WS + 1 + j] = cplx<T>{wx8[j] * vr, wx8[j] * vi};
+        }
+        sd[se] = int2{dy, dx};
         wave_lds_sync();
         const int ng = (min(GR_BATCH, n - base) + 3) >> 2;
         // row il of A is wy_e(il - dy_e) and column il of B is wx_e(il - dx_e) v_e:
         // the tap index clamped to [-1, KB_J] reads a zero outside the footprint
         auto step = [&](int q, acc_t& are, acc_t& aim) {
             const int e = 4 * q + kq;
-            const int2 d = *reinterpret_cast<const int2*>(&sd[2 * e]);
+            const int2 d = sd[e];
             const int iy = min(max(il - d.x, -1), KB_J) + 1;
             const int ix = min(max(il - d.y, -1), KB_J) + 1;
             const T a = sA[e * GR_WS + iy];
