@@ -195,6 +195,42 @@ def test_dual_data_parity(name, dtype):
     check_rel_pc(host(adj), adj_ref, TOL[dtype], "host(adj)")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("L", [63, 64])
+def test_maximum_channel_count(L, dtype):
+    """The largest channel counts (64: the full 64 x 64 Gram and eigen-solve; 63: padded
+    to an even order): the nuclear prox, its singular values and one whole PD iteration
+    against the oracle on a 32 x 32 x L cube of 700 visibilities per channel."""
+    cfg, inp, op = oracle_case("cube32_L3", L=L)
+    prob, _, _ = gpu_case("cube32_L3", dtype, L=L)
+    rng = np.random.default_rng(60 + L)
+    X = inp["X0"] + 0.01 * rng.standard_normal(inp["X0"].shape)
+    w = np.sort(rng.uniform(0.0, 0.5, L))
+    Xd, sig = prob.prox_nuclear(to_dev(prob, X), w)
+    ref, s_ref = prox.prox_nuclear_svd(X, w)
+    check_rel(host(Xd), ref, TOL[dtype], "prox")
+    check_rel(sig, s_ref, TOL[dtype], "singular values")
+    st = W.make_state(cfg, inp["X0"], prob.counts)
+    prm = pd.Params(mu=0.01, tau=0.33, kappa3=_kappa3(op), w=np.linspace(0.2, 1.0, L))
+    ost = pd.State(X=st["X"], Xt=st["Xt"], P=st["P"], A=st["A"], v=st["v"],
+                   eps=[e.copy() for e in op.eps], vartheta=[np.zeros(len(e), np.int64) for e in op.eps])
+    ref_it = pd.pd_iteration(ost, op, prm, (1.0, 1.0 / 9.0, prm.kappa3))
+    g, beta, rho = _run_gpu_iteration(prob, st, prm, prm.w)
+    for k in ("X", "Xt", "P"):
+        check_rel(g[k], getattr(ref_it, k), TOL[dtype], k)
+    check_rel(g["A"], ref_it.A, TOL[dtype], "A")
+    check_rel(rho, np.concatenate(ref_it.extra["rho"]), TOL[dtype], "rho")
+
+
+def test_channel_count_above_maximum_is_refused():
+    import paper_1806_04596_amd as H
+    cfg, inp, op = oracle_case("cube32_L3")
+    chans = [dict(uv=op.uv[0], y_raw=np.zeros(len(op.uv[0]), complex), theta=np.ones(len(op.uv[0])),
+                  block_ptr=op.block_ptr[0], eps=op.eps[0])] * 65
+    with pytest.raises(H.HSError):
+        H.Problem(cfg.nx, cfg.ny, chans, dtype="f32")
+
+
 @pytest.mark.parametrize("mode", ["prox", "dual"])
 def test_nuclear_ill_conditioned_f64(mode):
     """An ill-conditioned 65536 x 15 matrix (singular values 1e3 .. 1e-3, unit weights
