@@ -14,18 +14,46 @@ namespace hs {
 //
 // Analysis, one launch per level: a work item is a TB x TB tile of each of the
 // four subbands of one channel (and one basis, below level 0); its
-// (2TB + 14)^2 input window (periodic wrap) is staged in LDS, filtered along
-// rows then columns in LDS, and the three detail subbands go to their Mallat
-// positions; the approximation goes to a compact buffer for the next level (or
-// to its Mallat place at the last level).  At level 0 the input X is shared by
-// every basis, so one item loops over the bases and reads X once.  Work-groups
-// loop over items and load the next item's window into registers while the
-// current one is filtered.
-constexpr int WV_TB = 16;   // analysis output tile per subband
-constexpr int WV_TO = 32;   // synthesis output tile
+// (2TB + NT - 2)^2 input window (periodic wrap) is staged in LDS with 16-byte
+// loads, filtered along rows then columns in LDS, and the three detail subbands
+// go to their Mallat positions; the approximation goes to a compact buffer for
+// the next level (or to its Mallat place at the last level).  At level 0 the
+// input X is shared by every basis, so one item loops over the bases and reads X
+// once.  Work-groups loop over items and load the next item's window into
+// registers while the current one is filtered.
+//
+// Both filter passes are register-blocked: a thread reads the inputs of a run of
+// adjacent outputs once (16-byte LDS reads along rows) and forms every output of
+// the run as an FMA chain with uniform (scalar) taps, so the unrolled loops carry
+// no index arithmetic.  Row pass: runs of 4 outputs (a and d) along a row.
+// Column pass: runs of TB^2/128 outputs down a column, one task per thread.
 constexpr int WV_HALO = 14; // 2 * 8 - 2
-constexpr int WV_W = WV_TO / 2 + 8;   // synthesis coefficient window per subband
 constexpr int64_t IDWT_MIN_WG = 2048;  // smallest synthesis grid worth looping bases for
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+// 16-byte LDS / global accesses of n = 16 / sizeof(T) consecutive elements
+template <typename T>
+__device__ __forceinline__ void ld16(const T* p, T* out) {
+    const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(p);
+    if constexpr (Vec16<T>::n == 4) { out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w; }
+    else { out[0] = v.x; out[1] = v.y; }
+}
+template <typename T>
+__device__ __forceinline__ void st16(T* p, const T* in) {
+    typename Vec16<T>::type v;
+    if constexpr (Vec16<T>::n == 4) { v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3]; }
+    else { v.x = in[0]; v.y = in[1]; }
+    *reinterpret_cast<typename Vec16<T>::type*>(p) = v;
+}
+
+// Analysis tiling per precision: TB outputs per subband and dimension, LDS row
+// strides SI (input window) and ST (row-filtered a | d), multiples of 16 bytes.
+template <typename T> struct DwtCfg;
+template <> struct DwtCfg<float> { static constexpr int TB = 32, SI = 84, ST = 68; };
+template <> struct DwtCfg<double> { static constexpr int TB = 16, SI = 50, ST = 34; };
 
 // Tile of work item t (of n): work-groups are dispatched round-robin over the 8
 // XCDs, each with its own L2, so t mod 8 names the XCD; when n is a multiple of 8
@@ -57,61 +85,81 @@ __device__ __forceinline__ int wrap_idx(int k, int n) {
         default: FN<T, 16>(__VA_ARGS__); break;         \
     }
 
-constexpr int WV_WI = 2 * WV_TB + WV_HALO;   // analysis input window edge
-
-// Analysis rows: a | d for every needed input row (2 TB + NT - 2 rows).
+// Analysis rows: a | d for every window row the column pass needs (2 TB + NT - 2
+// rows).  Task (r, q): outputs 4q .. 4q + 3 of row r from inputs 8q .. 8q + NT + 5.
 template <typename T, int NT>
-__device__ __forceinline__ void dwt_rows(const T* __restrict__ f, const T (*inS)[WV_WI + 1], T (*tmpS)[2 * WV_TB + 1]) {
-    constexpr int TB = WV_TB, NR = 2 * TB + NT - 2;
-    T h[NT], g[NT];
+__device__ __forceinline__ void dwt_rows(const T* __restrict__ f, const T* inS, T* tmpS) {
+    using C = DwtCfg<T>;
+    constexpr int TB = C::TB, R = 4, RUNS = TB / R, NR = 2 * TB + NT - 2;
+    constexpr int VW = Vec16<T>::n, NX = 2 * R + NT - 2, NXV = (NX + VW - 1) / VW * VW;
+    static_assert(2 * R * (RUNS - 1) + NXV <= C::SI, "row reads stay inside the padded row");
+    for (int t = threadIdx.x; t < NR * RUNS; t += 256) {
+        const int r = t / RUNS, q = t % RUNS;
+        const T* src = inS + r * C::SI + 2 * R * q;
+        T x[NXV];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        h[j] = f[j];
-        g[j] = f[16 + j];
-    }
-    for (int e = threadIdx.x; e < NR * TB; e += blockDim.x) {
-        const int r = e / TB, kx = e - r * TB;
-        T a = T(0), d = T(0);
+        for (int k = 0; k < NXV; k += VW) ld16(src + k, x + k);
+        T a[R], d[R];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const T x = inS[r][2 * kx + j];
-            a += h[j] * x;
-            d += g[j] * x;
+        for (int o = 0; o < R; ++o) {
+            T sa = T(0), sd = T(0);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                sa = fma(f[j], x[2 * o + j], sa);
+                sd = fma(f[16 + j], x[2 * o + j], sd);
+            }
+            a[o] = sa;
+            d[o] = sd;
         }
-        tmpS[r][kx] = a;
-        tmpS[r][TB + kx] = d;
+        T* dst = tmpS + r * C::ST + R * q;
+#pragma unroll
+        for (int k = 0; k < R; k += VW) {
+            st16(dst + k, a + k);
+            st16(dst + TB + k, d + k);
+        }
     }
 }
 
-// Analysis columns: the four subbands of output (ky, kx), written to their places.
+// Analysis columns: thread t owns column c = t mod 2TB of the row-filtered tile (a
+// for c < TB, d above) and the run of RC = TB^2/128 output rows starting at
+// RC (t / 2TB); the low-pass of the run goes to LL (a) or to the (low y, high x)
+// subband (d), the high-pass to (high y, low x) or (high y, high x).
 template <typename T, int NT>
-__device__ __forceinline__ void dwt_cols(const T* __restrict__ f, const T (*tmpS)[2 * WV_TB + 1], T* __restrict__ cb,
+__device__ __forceinline__ void dwt_cols(const T* __restrict__ f, const T* tmpS, T* __restrict__ cb,
                                          T* __restrict__ llb, int ky0, int kx0, int hx, int hy, int nx, int last) {
-    constexpr int TB = WV_TB;
-    T h[NT], g[NT];
+    using C = DwtCfg<T>;
+    constexpr int TB = C::TB, RC = TB * TB / 128, NX = 2 * RC + NT - 2;
+    static_assert(2 * TB * (TB / RC) == 256, "one column task per thread");
+    const int c = threadIdx.x % (2 * TB), q = threadIdx.x / (2 * TB);
+    const bool hi = c >= TB;
+    const int gx = kx0 + (hi ? c - TB : c);
+    T x[NX];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        h[j] = f[j];
-        g[j] = f[16 + j];
-    }
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-        const int ky = e / TB, kx = e - ky * TB;
-        T aa = T(0), da = T(0), ad = T(0), dd = T(0);
+    for (int k = 0; k < NX; ++k) x[k] = tmpS[(2 * RC * q + k) * C::ST + c];
+    T lo[RC], hg[RC];
+#pragma unroll
+    for (int o = 0; o < RC; ++o) {
+        T sl = T(0), sh = T(0);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const T lo = tmpS[2 * ky + j][kx], hi = tmpS[2 * ky + j][TB + kx];
-            aa += h[j] * lo;
-            da += g[j] * lo;
-            ad += h[j] * hi;
-            dd += g[j] * hi;
+            sl = fma(f[j], x[2 * o + j], sl);
+            sh = fma(f[16 + j], x[2 * o + j], sh);
         }
-        const int gy = ky0 + ky, gx = kx0 + kx;
-        if (gy < hy && gx < hx) {
-            cb[(size_t)gy * nx + hx + gx] = ad;
-            cb[(size_t)(hy + gy) * nx + gx] = da;
-            cb[(size_t)(hy + gy) * nx + hx + gx] = dd;
-            if (last) cb[(size_t)gy * nx + gx] = aa;
-            else llb[(size_t)gy * hx + gx] = aa;
+        lo[o] = sl;
+        hg[o] = sh;
+    }
+    if (gx >= hx) return;
+    // low-pass destination: LL (compact slot, or its Mallat place at the last level)
+    // for a columns, the (low y, high x) detail for d columns
+    T* p1 = hi ? cb + hx + gx : (last ? cb + gx : llb + gx);
+    const int s1 = (!hi && !last) ? hx : nx;
+    T* p2 = cb + (size_t)hy * nx + (hi ? hx : 0) + gx;
+    const int gy0 = ky0 + RC * q;
+#pragma unroll
+    for (int o = 0; o < RC; ++o) {
+        if (gy0 + o < hy) {
+            p1[(size_t)(gy0 + o) * s1] = lo[o];
+            p2[(size_t)(gy0 + o) * nx] = hg[o];
         }
     }
 }
@@ -121,29 +169,41 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
                                                    T* __restrict__ coef, T* __restrict__ llout,
                                                    const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                    int lev0, int last, int n_db) {
-    constexpr int TB = WV_TB, WI = WV_WI, NW = (WI * WI + 255) / 256;
-    __shared__ T inS[WI][WI + 1];
-    __shared__ T tmpS[WI][2 * TB + 1];
+    using C = DwtCfg<T>;
+    constexpr int TB = C::TB, VW = Vec16<T>::n;
+    constexpr int WMAX = 2 * TB + WV_HALO;            // widest window edge (16 taps)
+    constexpr int NG = (WMAX + VW - 1) / VW;          // 16-byte groups per window row
+    constexpr int NW = (WMAX * NG + 255) / 256;       // groups per thread
+    static_assert(NG * VW <= C::SI, "window rows fit the LDS row");
+    __shared__ __align__(16) T inS[WMAX * C::SI];
+    __shared__ __align__(16) T tmpS[WMAX * C::ST];
     const int hx = mx >> 1, hy = my >> 1;
     const int ntx = (hx + TB - 1) / TB, nty = (hy + TB - 1) / TB, ntiles = ntx * nty;
     const size_t N = (size_t)nx * ny;
     const int tid = threadIdx.x;
     // work items: (tile, channel) at level 0 (all bases share the window), else (tile, channel, basis)
     const int nitems = ntiles * L * (lev0 ? 1 : n_db);
-    T win[NW];
+    T win[NW * VW];
     auto fetch = [&](int item) {
         const int tile = xcd_band(item % ntiles, ntiles), rest = item / ntiles;
         const int l = rest % L, b = rest / L;
         const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
         const T* src = lev0 ? X + (size_t)l * N : llin + ((size_t)b * L + l) * (size_t)my * mx;
         const int stride = lev0 ? nx : mx;
+        const int rows = 2 * TB + 2 * (lev0 ? n_db : b + 1) - 2;   // window rows this item filters
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             const int e = tid + 256 * k;
-            if (e < WI * WI) {
-                const int r = e / WI, cc = e - r * WI;
-                const int gy = wrap_idx(2 * ky0 + r, my), gx = wrap_idx(2 * kx0 + cc, mx);
-                win[k] = src[(size_t)gy * stride + gx];
+            const int r = e / NG, g = e - r * NG;
+            if (r < rows) {
+                const T* row = src + (size_t)wrap_idx(2 * ky0 + r, my) * stride;
+                if (mx >= VW) {
+                    // mx and the group start are multiples of VW: a group never straddles the wrap
+                    ld16(row + wrap_idx(2 * kx0 + VW * g, mx), win + VW * k);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < VW; ++i) win[VW * k + i] = row[wrap_idx(2 * kx0 + VW * g + i, mx)];
+                }
             }
         }
     };
@@ -155,11 +215,13 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
         const int ky0 = (tile / ntx) * TB, kx0 = (tile % ntx) * TB;
         const int b_first = lev0 ? 0 : rest / L;
         const int b_last = lev0 ? n_db : b_first + 1;
+        const int rows = 2 * TB + 2 * (lev0 ? n_db : b_first + 1) - 2;
         __syncthreads();   // the previous item is done with inS and tmpS
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             const int e = tid + 256 * k;
-            if (e < WI * WI) inS[e / WI][e % WI] = win[k];
+            const int r = e / NG, g = e - r * NG;
+            if (r < rows) st16(inS + r * C::SI + VW * g, win + VW * k);
         }
         __syncthreads();
         if (item + (int)gridDim.x < nitems) fetch(item + gridDim.x);   // in flight during the filters
@@ -177,63 +239,82 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
 
 // Synthesis, one launch per level (coarse to fine): a workgroup owns a TO x TO
 // tile of the synthesised region, stages windows of the four subbands
-// (approximation from the coarser synthesis, or from C at the coarsest level),
-// inverts along y then x in LDS, and writes a compact approximation for the
-// next finer level.  At level 0 it loops over the bases and writes
-// Xout = C0 + sum_b Psi_b C_b once.  Outputs 2p and 2p + 1 of a filter pass
-// read the same coefficients (even taps for the first, odd for the second).
-// Each thread owns a short run of adjacent outputs: it reads the coefficients
-// the run needs once into registers and forms every output as a chain of
-// FMAs, so the inner loops carry no index arithmetic.
+// (approximation from the coarser synthesis, or from C at the coarsest level)
+// with 16-byte loads, inverts along y then x in LDS, and writes a compact
+// approximation for the next finer level.  At level 0 it loops over the bases and
+// writes Xout = C0 + sum_b Psi_b C_b once.  Outputs 2p and 2p + 1 of a filter
+// pass read the same coefficients (even taps for the first, odd for the second).
+// Each thread owns a run of adjacent outputs: it reads the coefficients the run
+// needs once into registers and forms every output as a chain of FMAs, so the
+// inner loops carry no index arithmetic.
+//
+// LDS layout: S[sy][r][sx * W + c] holds the W x W window of subband (sy, sx), the
+// two x-subbands side by side in one row, so the column pass walks one contiguous
+// range of lanes per row; Tm[m][sx * W + c] holds the column-inverted rows, the
+// low-x half then the high-x half, read by the row pass with 16-byte reads.
+template <typename T> struct IdwtCfg;
+// TO output tile edge, P output pairs per column task, Q output pairs per row task,
+// row strides SW (S) and ST (Tm), multiples of 16 bytes
+template <> struct IdwtCfg<float> { static constexpr int TO = 64, P = 4, Q = 4, SW = 84, ST = 84; };
+template <> struct IdwtCfg<double> { static constexpr int TO = 32, P = 2, Q = 2, SW = 50, ST = 50; };
 
-// Column (y) inverse: thread t < 192 owns x-subband sx, window column wx and
-// the output rows 2p, 2p + 1 for p in [p0, p0 + 4).
-constexpr int IDWT_YP = 4;
+// Column (y) inverse: task (run, column) forms rows 2p, 2p + 1 for the P values of
+// p in the run, in one window column of either x-subband; only the columns the row
+// pass reads are formed (window columns 9 - NH .. W - 1 of each half).
 template <typename T, int NT>
-__device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T (*S)[WV_W][WV_W + 1],
-                                       T (*Tm)[WV_TO][WV_W + 1], int sx, int wx, int p0) {
-    constexpr int NH = NT / 2, NR = NH + IDWT_YP - 1;
-    T a[NR], d[NR];
-    const int r0 = p0 + 9 - NH;   // first window row of the run
+__device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T* S, T* Tm) {
+    using C = IdwtCfg<T>;
+    constexpr int TO = C::TO, W = TO / 2 + 8, P = C::P, RUNS = TO / 2 / P, NH = NT / 2;
+    constexpr int C0 = 9 - NH, NCOL = W - C0, NA = NH + P - 1;
+    for (int t = threadIdx.x; t < RUNS * 2 * NCOL; t += 256) {
+        const int run = t / (2 * NCOL), idx = t - run * 2 * NCOL;
+        const int cc = idx < NCOL ? C0 + idx : W + C0 + (idx - NCOL);
+        const int r0 = P * run + C0;
+        T a[NA], d[NA];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        a[k] = S[sx][r0 + k][wx];
-        d[k] = S[2 + sx][r0 + k][wx];
-    }
-#pragma unroll
-    for (int j = 0; j < IDWT_YP; ++j) {
-        T xe = T(0), xo = T(0);
-#pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const int k = j - i + NH - 1;   // row p0 + j - i + 8
-            xe = fma(f[2 * i], a[k], xe);
-            xe = fma(f[16 + 2 * i], d[k], xe);
-            xo = fma(f[2 * i + 1], a[k], xo);
-            xo = fma(f[16 + 2 * i + 1], d[k], xo);
+        for (int k = 0; k < NA; ++k) {
+            a[k] = S[(r0 + k) * C::SW + cc];
+            d[k] = S[(W + r0 + k) * C::SW + cc];
         }
-        Tm[sx][2 * (p0 + j)][wx] = xe;
-        Tm[sx][2 * (p0 + j) + 1][wx] = xo;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            T xe = T(0), xo = T(0);
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const int k = j - i + NH - 1;   // window row p + 8 - i
+                xe = fma(f[2 * i], a[k], xe);
+                xe = fma(f[16 + 2 * i], d[k], xe);
+                xo = fma(f[2 * i + 1], a[k], xo);
+                xo = fma(f[16 + 2 * i + 1], d[k], xo);
+            }
+            Tm[(2 * (P * run + j)) * C::ST + cc] = xe;
+            Tm[(2 * (P * run + j) + 1) * C::ST + cc] = xo;
+        }
     }
 }
 
-// Row (x) inverse: thread t owns output row m and columns 2q0 .. 2q0 + 3.
+// Row (x) inverse: task (m, q) forms output columns 2p, 2p + 1 of row m for the Q
+// values of p in run q, from window columns Qq .. Qq + Q + 7 of both halves.
 template <typename T, int NT>
-__device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV_TO][WV_W + 1], int m, int q0,
-                                       T (&res)[4]) {
-    constexpr int NH = NT / 2, NC = NH + 1;
-    T a[NC], d[NC];
-    const int c0 = q0 + 9 - NH;
+__device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T* Tm, int t, T* res) {
+    using C = IdwtCfg<T>;
+    constexpr int TO = C::TO, W = TO / 2 + 8, Q = C::Q, XR = TO / 2 / Q, NH = NT / 2, VW = Vec16<T>::n;
+    constexpr int NA = Q + 8;
+    static_assert(NA % VW == 0 && W % VW == 0 && Q % VW == 0, "16-byte row reads");
+    const int m = t / XR, q = t - (t / XR) * XR;
+    const T* row = Tm + m * C::ST + Q * q;
+    T a[NA], d[NA];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        a[k] = Tm[0][m][c0 + k];
-        d[k] = Tm[1][m][c0 + k];
+    for (int k = 0; k < NA; k += VW) {
+        ld16(row + k, a + k);
+        ld16(row + W + k, d + k);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < Q; ++j) {
         T xe = T(0), xo = T(0);
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const int k = j - i + NH - 1;   // column q0 + j - i + 8
+            const int k = j + 8 - i;   // window column p + 8 - i
             xe = fma(f[2 * i], a[k], xe);
             xe = fma(f[16 + 2 * i], d[k], xe);
             xo = fma(f[2 * i + 1], a[k], xo);
@@ -245,15 +326,19 @@ __device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T (*Tm)[WV
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
                                                     T* __restrict__ out, const T* __restrict__ C0,
                                                     const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                     int coarsest, int final_level, int n_db, int bpw) {
-    constexpr int TO = WV_TO, W = WV_W;
-    static_assert(TO * TO == 4 * 256, "four outputs per thread");
-    static_assert(2 * W * (TO / 2) == IDWT_YP * 192, "y runs on three waves");
-    __shared__ T S[4][W][W + 1];           // subband (sy*2 + sx)
-    __shared__ T Tm[2][TO][W + 1];         // after the column inverse, per x-subband
+    using Cf = IdwtCfg<T>;
+    constexpr int TO = Cf::TO, W = TO / 2 + 8, Q = Cf::Q, XR = TO / 2 / Q, VW = Vec16<T>::n;
+    constexpr int G = W / VW;                       // 16-byte groups per subband window row
+    constexpr int NG = 4 * W * G;                   // groups of the four windows
+    constexpr int NE = (NG + 255) / 256;            // groups per thread
+    constexpr int NXT = TO * XR / 256;              // row-pass tasks per thread
+    static_assert(TO * XR % 256 == 0 && 2 * W <= Cf::SW && 2 * W <= Cf::ST, "tiling");
+    __shared__ __align__(16) T S[2 * W * Cf::SW];
+    __shared__ __align__(16) T Tm[TO * Cf::ST];
     const int hx = mx >> 1, hy = my >> 1;
     const int ntx = (mx + TO - 1) / TO;
     const int tile = xcd_band(blockIdx.x, gridDim.x);
@@ -265,94 +350,112 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
     if (kylo < 0) kylo += hy;
     int kxlo = (m0x / 2 - 8) % hx;
     if (kxlo < 0) kxlo += hx;
-    // thread roles in the two filter passes
-    const bool ylive = tid < 192;
-    const int yc = tid % 48, ysx = yc / W, ywx = yc - ysx * W, yp0 = (tid / 48) * IDWT_YP;
-    const int xm = tid >> 3, xq0 = 2 * (tid & 7);
-    T acc[4] = {T(0), T(0), T(0), T(0)};
-    const int b_first = final_level ? 0 : (int)blockIdx.z * bpw;
-    const int b_last = final_level ? n_db : min(b_first + bpw, n_db);
-    // This thread's window elements: the same offsets in every basis, computed once.
-    // Element i comes from the coarser approximation (llin) when it is in subband 0
-    // below the coarsest level, else from the coefficient image.
-    constexpr int NE = (4 * W * W + 255) / 256;
-    int off[NE];
-    unsigned from_ll = 0u, live = 0u;
+    // Group e = ((sy W + r) 2 + sx) G + g: VW elements of window row r of subband
+    // (sy, sx), columns VW g ..; the same offsets serve every basis, so they are
+    // formed once.  A group comes from the coarser approximation (llin) when it is
+    // in subband (0, 0) below the coarsest level, else from the coefficient image.
+    const bool vec = hx >= VW;   // hx and the group starts are multiples of VW
+    int goff[NE], loff[NE];
+    unsigned from_ll = 0u;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
         const int e = tid + 256 * i;
-        off[i] = 0;
-        if (e < 4 * W * W) {
-            const int sb = e / (W * W), rem = e - sb * (W * W);
-            const int r = rem / W, cc = rem - r * W;
-            const int sy = sb >> 1, sx = sb & 1;
-            const int ky = wrap_idx(kylo + r, hy), kx = wrap_idx(kxlo + cc, hx);
-            live |= 1u << i;
-            if (sb == 0 && !coarsest) {
-                from_ll |= 1u << i;
-                off[i] = ky * hx + kx;
-            } else {
-                off[i] = (sy * hy + ky) * nx + sx * hx + kx;
-            }
+        const int rr = e / G, g = e - rr * G;
+        const int sx = rr & 1, row = rr >> 1, sy = row / W, r = row - sy * W;
+        loff[i] = row * Cf::SW + sx * W + VW * g;
+        const int ky = wrap_idx(kylo + r, hy), kx = vec ? wrap_idx(kxlo + VW * g, hx) : 0;
+        if (sy == 0 && sx == 0 && !coarsest) {
+            from_ll |= 1u << i;
+            goff[i] = ky * hx + kx;
+        } else {
+            goff[i] = (sy * hy + ky) * nx + sx * hx + kx;
         }
     }
     // the window of the next basis is loaded into registers while this one is filtered
-    T nxt[NE];
+    T nxt[NE * VW];
     auto fetch = [&](int b) {
         const T* Cb = C + ((size_t)b * L + l) * N;
         const T* LLb = coarsest ? Cb : llin + ((size_t)b * L + l) * (size_t)hy * hx;
 #pragma unroll
-        for (int i = 0; i < NE; ++i)
-            if ((live >> i) & 1u) nxt[i] = ((from_ll >> i) & 1u) ? LLb[off[i]] : Cb[off[i]];
-    };
-    fetch(b_first);
-    for (int b = b_first; b < b_last; ++b) {
-        T* Sf = &S[0][0][0];
-#pragma unroll
         for (int i = 0; i < NE; ++i) {
-            const int e = tid + 256 * i;
-            if ((live >> i) & 1u) {
-                const int sb = e / (W * W), rem = e - sb * (W * W);
-                Sf[(sb * W + rem / W) * (W + 1) + rem % W] = nxt[i];
+            if (tid + 256 * i < NG) {
+                const T* src = ((from_ll >> i) & 1u) ? LLb : Cb;
+                if (vec) {
+                    ld16(src + goff[i], nxt + VW * i);
+                } else {
+                    // coarse levels narrower than one group: element by element
+                    const int e = tid + 256 * i, g = e % G;
+#pragma unroll
+                    for (int k = 0; k < VW; ++k) nxt[VW * i + k] = src[goff[i] + wrap_idx(kxlo + VW * g + k, hx)];
+                }
             }
         }
+    };
+    T acc[NXT * 2 * Q];
+#pragma unroll
+    for (int k = 0; k < NXT * 2 * Q; ++k) acc[k] = T(0);
+    const int b_first = final_level ? 0 : (int)blockIdx.z * bpw;
+    const int b_last = final_level ? n_db : min(b_first + bpw, n_db);
+    fetch(b_first);
+    for (int b = b_first; b < b_last; ++b) {
+#pragma unroll
+        for (int i = 0; i < NE; ++i)
+            if (tid + 256 * i < NG) st16(S + loff[i], nxt + VW * i);
         __syncthreads();
         if (b + 1 < b_last) fetch(b + 1);
         const T* f = filt + b * 32;
-        if (ylive) {
-            WV_DISPATCH(b, idwt_y, f, S, Tm, ysx, ywx, yp0)
-        }
+        WV_DISPATCH(b, idwt_y, f, S, Tm)
         __syncthreads();
-        T res[4];
-        WV_DISPATCH(b, idwt_x, f, Tm, xm, xq0, res)
-        if (final_level) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc[k] += res[k];
-        } else {
-            const int gy = m0y + xm, gx = m0x + 2 * xq0;
-            T* o = out + ((size_t)b * L + l) * (size_t)my * mx + (size_t)gy * mx + gx;
-            if (gy < my) {
+        for (int u = 0; u < NXT; ++u) {
+            const int t = tid + 256 * u;
+            T res[2 * Q];
+            WV_DISPATCH(b, idwt_x, f, Tm, t, res)
+            if (final_level) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (gx + k < mx) o[k] = res[k];
+                for (int k = 0; k < 2 * Q; ++k) acc[2 * Q * u + k] += res[k];
+            } else {
+                const int gy = m0y + t / XR, gx = m0x + 2 * Q * (t % XR);
+                T* o = out + ((size_t)b * L + l) * (size_t)my * mx + (size_t)gy * mx + gx;
+                if (gy < my) {
+                    if (gx + 2 * Q <= mx) {
+#pragma unroll
+                        for (int k = 0; k < 2 * Q; k += VW) st16(o + k, res + k);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 2 * Q; ++k)
+                            if (gx + k < mx) o[k] = res[k];
+                    }
+                }
             }
         }
         __syncthreads();
     }
     if (final_level) {
-        // mx is a power of two, so for mx >= 4 the four outputs are all in or all out
-        const int gy = m0y + xm, gx = m0x + 2 * xq0;
-        const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
-        if (gy < my && mx >= 4 && gx < mx) {
-            T v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = (C0 ? C0[idx + k] : T(0)) + acc[k];
+        for (int u = 0; u < NXT; ++u) {
+            const int t = tid + 256 * u;
+            const int gy = m0y + t / XR, gx = m0x + 2 * Q * (t % XR);
+            if (gy >= my) continue;
+            const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
+            T* a = acc + 2 * Q * u;
+            if (gx + 2 * Q <= mx) {
+                if (C0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) out[idx + k] = v[k];
-        } else if (gy < my) {
+                    for (int k = 0; k < 2 * Q; k += VW) {
+                        T c0[VW];
+                        ld16(C0 + idx + k, c0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (gx + k < mx) out[idx + k] = (C0 ? C0[idx + k] : T(0)) + acc[k];
+                        for (int i = 0; i < VW; ++i) a[k + i] += c0[i];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 2 * Q; k += VW) st16(out + idx + k, a + k);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 2 * Q; ++k)
+                    if (gx + k < mx) out[idx + k] = (C0 ? C0[idx + k] : T(0)) + a[k];
+            }
         }
     }
 }
@@ -435,7 +538,8 @@ void launch_psi_adj(hs_ctx* c, const T* X, T* Cout, int nl) {
     for (int lev = 0; lev < c->levels; ++lev) {
         const int mx = c->nx >> lev, my = c->ny >> lev;
         const int hx = mx / 2, hy = my / 2;
-        const int tiles = ((hy + WV_TB - 1) / WV_TB) * ((hx + WV_TB - 1) / WV_TB);
+        constexpr int TB = DwtCfg<T>::TB;
+        const int tiles = ((hy + TB - 1) / TB) * ((hx + TB - 1) / TB);
         T* llout = (lev % 2 == 0) ? slotA : slotB;
         const int last = (lev == c->levels - 1) ? 1 : 0;
         const int items = tiles * L * (lev == 0 ? 1 : c->n_db);
@@ -461,7 +565,8 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout, int nl) {
     const T* llin = nullptr;
     for (int lev = c->levels - 1; lev >= 0; --lev) {
         const int mx = c->nx >> lev, my = c->ny >> lev;
-        const int tiles = ((my + WV_TO - 1) / WV_TO) * ((mx + WV_TO - 1) / WV_TO);
+        constexpr int TO = IdwtCfg<T>::TO;
+        const int tiles = ((my + TO - 1) / TO) * ((mx + TO - 1) / TO);
         const int fin = (lev == 0) ? 1 : 0;
         T* out = fin ? Xout : ((lev % 2 == 1) ? slotA : slotB);
         // bases per work-group: as many as keep the grid at IDWT_MIN_WG or more, so the
