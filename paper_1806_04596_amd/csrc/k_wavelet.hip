@@ -30,23 +30,23 @@ namespace hs {
 constexpr int WV_HALO = 14; // 2 * 8 - 2
 constexpr int64_t IDWT_MIN_WG = 2048;  // smallest synthesis grid worth looping bases for
 
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <typename T> struct Pack16;
+template <> struct Pack16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Pack16<double> { using type = double2; static constexpr int n = 2; };
 
 // 16-byte LDS / global accesses of n = 16 / sizeof(T) consecutive elements
 template <typename T>
 __device__ __forceinline__ void ld16(const T* p, T* out) {
-    const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(p);
-    if constexpr (Vec16<T>::n == 4) { out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w; }
+    const typename Pack16<T>::type v = *reinterpret_cast<const typename Pack16<T>::type*>(p);
+    if constexpr (Pack16<T>::n == 4) { out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w; }
     else { out[0] = v.x; out[1] = v.y; }
 }
 template <typename T>
 __device__ __forceinline__ void st16(T* p, const T* in) {
-    typename Vec16<T>::type v;
-    if constexpr (Vec16<T>::n == 4) { v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3]; }
+    typename Pack16<T>::type v;
+    if constexpr (Pack16<T>::n == 4) { v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3]; }
     else { v.x = in[0]; v.y = in[1]; }
-    *reinterpret_cast<typename Vec16<T>::type*>(p) = v;
+    *reinterpret_cast<typename Pack16<T>::type*>(p) = v;
 }
 
 // Analysis tiling per precision: TB outputs per subband and dimension, LDS row
@@ -91,7 +91,7 @@ template <typename T, int NT>
 __device__ __forceinline__ void dwt_rows(const T* __restrict__ f, const T* inS, T* tmpS) {
     using C = DwtCfg<T>;
     constexpr int TB = C::TB, R = 4, RUNS = TB / R, NR = 2 * TB + NT - 2;
-    constexpr int VW = Vec16<T>::n, NX = 2 * R + NT - 2, NXV = (NX + VW - 1) / VW * VW;
+    constexpr int VW = Pack16<T>::n, NX = 2 * R + NT - 2, NXV = (NX + VW - 1) / VW * VW;
     static_assert(2 * R * (RUNS - 1) + NXV <= C::SI, "row reads stay inside the padded row");
     for (int t = threadIdx.x; t < NR * RUNS; t += 256) {
         const int r = t / RUNS, q = t % RUNS;
@@ -158,8 +158,8 @@ __device__ __forceinline__ void dwt_cols(const T* __restrict__ f, const T* tmpS,
 #pragma unroll
     for (int o = 0; o < RC; ++o) {
         if (gy0 + o < hy) {
-            p1[(size_t)(gy0 + o) * s1] = lo[o];
-            p2[(size_t)(gy0 + o) * nx] = hg[o];
+            __builtin_nontemporal_store(lo[o], p1 + (size_t)(gy0 + o) * s1);
+            __builtin_nontemporal_store(hg[o], p2 + (size_t)(gy0 + o) * nx);
         }
     }
 }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
                                                    const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                    int lev0, int last, int n_db) {
     using C = DwtCfg<T>;
-    constexpr int TB = C::TB, VW = Vec16<T>::n;
+    constexpr int TB = C::TB, VW = Pack16<T>::n;
     constexpr int WMAX = 2 * TB + WV_HALO;            // widest window edge (16 taps)
     constexpr int NG = (WMAX + VW - 1) / VW;          // 16-byte groups per window row
     constexpr int NW = (WMAX * NG + 255) / 256;       // groups per thread
@@ -254,9 +254,10 @@ __global__ __launch_bounds__(256) void k_dwt_level(const T* __restrict__ X, cons
 // low-x half then the high-x half, read by the row pass with 16-byte reads.
 template <typename T> struct IdwtCfg;
 // TO output tile edge, P output pairs per column task, Q output pairs per row task,
-// row strides SW (S) and ST (Tm), multiples of 16 bytes
-template <> struct IdwtCfg<float> { static constexpr int TO = 64, P = 4, Q = 4, SW = 84, ST = 84; };
-template <> struct IdwtCfg<double> { static constexpr int TO = 32, P = 2, Q = 2, SW = 50, ST = 50; };
+// row strides SW (S) and ST (Tm), multiples of 16 bytes; NTH threads per work-group
+// and WPE, the waves per SIMD the register allocation is held to
+template <> struct IdwtCfg<float> { static constexpr int TO = 64, P = 4, Q = 4, SW = 84, ST = 84, NTH = 256, WPE = 3; };
+template <> struct IdwtCfg<double> { static constexpr int TO = 32, P = 2, Q = 2, SW = 50, ST = 50, NTH = 256, WPE = 4; };
 
 // Column (y) inverse: task (run, column) forms rows 2p, 2p + 1 for the P values of
 // p in the run, in one window column of either x-subband; only the columns the row
@@ -266,7 +267,7 @@ __device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T* S, T* T
     using C = IdwtCfg<T>;
     constexpr int TO = C::TO, W = TO / 2 + 8, P = C::P, RUNS = TO / 2 / P, NH = NT / 2;
     constexpr int C0 = 9 - NH, NCOL = W - C0, NA = NH + P - 1;
-    for (int t = threadIdx.x; t < RUNS * 2 * NCOL; t += 256) {
+    for (int t = threadIdx.x; t < RUNS * 2 * NCOL; t += C::NTH) {
         const int run = t / (2 * NCOL), idx = t - run * 2 * NCOL;
         const int cc = idx < NCOL ? C0 + idx : W + C0 + (idx - NCOL);
         const int r0 = P * run + C0;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void idwt_y(const T* __restrict__ f, const T* S, T* T
 template <typename T, int NT>
 __device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T* Tm, int t, T* res) {
     using C = IdwtCfg<T>;
-    constexpr int TO = C::TO, W = TO / 2 + 8, Q = C::Q, XR = TO / 2 / Q, NH = NT / 2, VW = Vec16<T>::n;
+    constexpr int TO = C::TO, W = TO / 2 + 8, Q = C::Q, XR = TO / 2 / Q, NH = NT / 2, VW = Pack16<T>::n;
     constexpr int NA = Q + 8;
     static_assert(NA % VW == 0 && W % VW == 0 && Q % VW == 0, "16-byte row reads");
     const int m = t / XR, q = t - (t / XR) * XR;
@@ -326,17 +327,18 @@ __device__ __forceinline__ void idwt_x(const T* __restrict__ f, const T* Tm, int
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
+__global__ __launch_bounds__(IdwtCfg<T>::NTH, IdwtCfg<T>::WPE) void k_idwt_level(const T* __restrict__ C, const T* __restrict__ llin,
                                                     T* __restrict__ out, const T* __restrict__ C0,
                                                     const T* __restrict__ filt, int L, int nx, int ny, int mx, int my,
                                                     int coarsest, int final_level, int n_db, int bpw) {
     using Cf = IdwtCfg<T>;
-    constexpr int TO = Cf::TO, W = TO / 2 + 8, Q = Cf::Q, XR = TO / 2 / Q, VW = Vec16<T>::n;
+    constexpr int TO = Cf::TO, W = TO / 2 + 8, Q = Cf::Q, XR = TO / 2 / Q, VW = Pack16<T>::n;
     constexpr int G = W / VW;                       // 16-byte groups per subband window row
     constexpr int NG = 4 * W * G;                   // groups of the four windows
-    constexpr int NE = (NG + 255) / 256;            // groups per thread
-    constexpr int NXT = TO * XR / 256;              // row-pass tasks per thread
-    static_assert(TO * XR % 256 == 0 && 2 * W <= Cf::SW && 2 * W <= Cf::ST, "tiling");
+    constexpr int NTH = Cf::NTH;
+    constexpr int NE = (NG + NTH - 1) / NTH;        // groups per thread
+    constexpr int NXT = TO * XR / NTH;              // row-pass tasks per thread
+    static_assert(TO * XR % NTH == 0 && 2 * W <= Cf::SW && 2 * W <= Cf::ST, "tiling");
     __shared__ __align__(16) T S[2 * W * Cf::SW];
     __shared__ __align__(16) T Tm[TO * Cf::ST];
     const int hx = mx >> 1, hy = my >> 1;
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     unsigned from_ll = 0u;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NTH * i;
         const int rr = e / G, g = e - rr * G;
         const int sx = rr & 1, row = rr >> 1, sy = row / W, r = row - sy * W;
         loff[i] = row * Cf::SW + sx * W + VW * g;
@@ -378,13 +380,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const T* LLb = coarsest ? Cb : llin + ((size_t)b * L + l) * (size_t)hy * hx;
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-            if (tid + 256 * i < NG) {
+            if (tid + NTH * i < NG) {
                 const T* src = ((from_ll >> i) & 1u) ? LLb : Cb;
                 if (vec) {
                     ld16(src + goff[i], nxt + VW * i);
                 } else {
                     // coarse levels narrower than one group: element by element
-                    const int e = tid + 256 * i, g = e % G;
+                    const int e = tid + NTH * i, g = e % G;
 #pragma unroll
                     for (int k = 0; k < VW; ++k) nxt[VW * i + k] = src[goff[i] + wrap_idx(kxlo + VW * g + k, hx)];
                 }
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int b = b_first; b < b_last; ++b) {
 #pragma unroll
         for (int i = 0; i < NE; ++i)
-            if (tid + 256 * i < NG) st16(S + loff[i], nxt + VW * i);
+            if (tid + NTH * i < NG) st16(S + loff[i], nxt + VW * i);
         __syncthreads();
         if (b + 1 < b_last) fetch(b + 1);
         const T* f = filt + b * 32;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NXT; ++u) {
-            const int t = tid + 256 * u;
+            const int t = tid + NTH * u;
             T res[2 * Q];
             WV_DISPATCH(b, idwt_x, f, Tm, t, res)
             if (final_level) {
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (final_level) {
 #pragma unroll
         for (int u = 0; u < NXT; ++u) {
-            const int t = tid + 256 * u;
+            const int t = tid + NTH * u;
             const int gy = m0y + t / XR, gx = m0x + 2 * Q * (t % XR);
             if (gy >= my) continue;
             const size_t idx = (size_t)l * N + (size_t)gy * nx + gx;
@@ -500,8 +502,8 @@ __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restr
 #pragma unroll
     for (int l = 0; l < MAX_L; ++l) {
         const size_t o = (size_t)(l < L ? l : L - 1) * N;
-        z[l] = Ad[o];
-        if (HAS_S) z2[l] = Sd[o];
+        z[l] = __builtin_nontemporal_load(Ad + o);
+        if (HAS_S) z2[l] = __builtin_nontemporal_load(Sd + o);
     }
     double n2 = 0.0;
 #pragma unroll
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(256) void k_l21(T* __restrict__ A, const T* __restr
     const T ft = (T)f;
 #pragma unroll
     for (int l = 0; l < MAX_L; ++l)
-        if (l < L) Ad[(size_t)l * N] = z[l] * ft;
+        if (l < L) __builtin_nontemporal_store(z[l] * ft, Ad + (size_t)l * N);
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -576,7 +578,7 @@ void launch_psi_sum(hs_ctx* c, const T* Cdb, const T* C0, T* Xout, int nl) {
             bpw *= 2;
         const int nz = fin ? 1 : (c->n_db + bpw - 1) / bpw;
         dim3 g(tiles, L, nz);
-        k_idwt_level<T><<<g, 256, 0, c->stream>>>(Cdb, llin, out, C0, filt, L, c->nx, c->ny, mx, my,
+        k_idwt_level<T><<<g, IdwtCfg<T>::NTH, 0, c->stream>>>(Cdb, llin, out, C0, filt, L, c->nx, c->ny, mx, my,
                                                   lev == c->levels - 1 ? 1 : 0, fin, c->n_db, bpw);
         llin = out;
     }
