@@ -125,6 +125,32 @@ def test_psi_parity_shapes(shape, dtype):
     check_rel_pc(Xs, wavelets.psi(Cr), TOL[dtype], "Xs")
 
 
+# Level counts and dictionary sizes other than 4 levels of db1..db8: one and two
+# levels, five levels of a 32 x 64 image and six of a 128^2 one (coarsest bands of
+# 1 x 2 and 2 x 2 coefficients, narrower than one 16-byte group), and one or three
+# Daubechies bases (a shorter shared input window at the finest level).
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nx,ny,levels,n_db", [(64, 64, 1, 8), (64, 128, 2, 3), (128, 128, 6, 8), (32, 64, 5, 1)])
+def test_psi_parity_levels_and_bases(nx, ny, levels, n_db, dtype):
+    import paper_1806_04596_amd as H
+    rng = np.random.default_rng(21)
+    chans = [dict(uv=rng.uniform(-0.4, 0.4, (64, 2)), y_raw=np.zeros(64), theta=np.ones(64),
+                  block_ptr=np.array([0, 64]), eps=np.ones(1)) for _ in range(2)]
+    prob = H.Problem(nx, ny, chans, dtype=dtype, levels=levels, n_db=n_db)
+    try:
+        X = _seeded((2, ny, nx), 9)
+        C = host(prob.psi_adj(to_dev(prob, X)))
+        ref = wavelets.psi_adj(X, levels, n_db)
+        assert C.shape == ref.shape
+        for d in range(1 + n_db):
+            check_rel_pc(C[d], ref[d], TOL[dtype], f"C[{d}]")
+        Cr = _seeded(ref.shape, 10)
+        Xs = host(prob.psi(to_dev(prob, Cr)))
+        check_rel_pc(Xs, wavelets.psi(Cr, levels), TOL[dtype], "Xs")
+    finally:
+        prob.close()
+
+
 def test_psi_perfect_reconstruction_f64():
     prob, _, _ = gpu_case("cube128x64_L4", "f64")
     X = _seeded((prob.L, prob.ny, prob.nx), 7)
