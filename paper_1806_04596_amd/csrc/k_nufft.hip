@@ -254,6 +254,21 @@ __device__ __forceinline__ int xcd_group_item(int b, int n, int G) {
 // Column pass of F over the half plane: columns kx in [0, Kx/2] in tiles of CT
 // adjacent columns (the last tile is partly idle), rows placed at
 // (j - ny/2) mod Ky.  The grid row has Wg cells, kx = 0 at cell T.
+template <typename T> struct NV2;
+template <> struct NV2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NV2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ cplx<T> ldnt_c(const cplx<T>* p) {
+    const typename NV2<T>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename NV2<T>::type*>(p));
+    return cplx<T>{v[0], v[1]};
+}
+template <typename T>
+__device__ __forceinline__ void stnt_c(cplx<T>* p, const cplx<T>& c) {
+    typename NV2<T>::type v;
+    v[0] = c.re; v[1] = c.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<typename NV2<T>::type*>(p));
+}
+
 template <typename T, int Ky>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
                                                        const cplx<T>* __restrict__ tw, int ny, int Kh,
@@ -273,7 +288,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
             return (live && j < ny) ? Hl[(size_t)j * Hs] : cplx<T>{T(0), T(0)};
         },
         [&](int q, const cplx<T>& v) {
-            if (live) Gl[(size_t)q * Wg] = v;
+            if (live) stnt_c(Gl + (size_t)q * Wg, v);
         });
 }
 
@@ -357,8 +372,8 @@ __global__ __launch_bounds__(512) void k_fft_rows_adj(const cplx<T>* __restrict_
             if (i >= Kx) i -= Kx;
             if (i < nx) {
                 const T w = sx[i];
-                Xa[i] = v.re * w * sya;
-                Xb[i] = v.im * w * syb;
+                __builtin_nontemporal_store(v.re * w * sya, Xa + i);
+                __builtin_nontemporal_store(v.im * w * syb, Xb + i);
             }
         });
 }
@@ -926,7 +941,7 @@ __global__ __launch_bounds__(64) void k_grid_pull(
         const int row = grid_mfma_row<T>(lane, r);
         const cplx<T> v{are0[r] + are1[r], aim0[r] + aim1[r]};
         if (u.nsplit == 1)
-            grid[(size_t)u.l * Ky * Wg + (size_t)(by0 + row) * Wg + GR_MARGIN + bx0 + il] = v;
+            stnt_c(grid + (size_t)u.l * Ky * Wg + (size_t)(by0 + row) * Wg + GR_MARGIN + bx0 + il, v);
         else
             partial[(size_t)(u.partial + u.split) * GB * GB + row * GB + il] = v;
     }
