@@ -63,7 +63,10 @@ def test_pd_200_iterations_f64_vs_oracle():
     for l in range(cfg.L):
         check_rel(vg[l], st.v[l], tol, f"v[{l}]")
     check_rel(rho, np.concatenate(st.extra["rho"]), tol, "rho")
-    assert abs(beta - st.beta) <= tol * st.beta
+    # beta = ||X_t - X_{t-1}|| / ||X_t|| is a difference of consecutive iterates: the bar on
+    # X (relative to ||X||) bounds its absolute error by 2 tol, whatever beta's size
+    print(f"{name} {n} iterations beta: {beta:.15e} (oracle {st.beta:.15e})", flush=True)
+    assert abs(beta - st.beta) <= 2 * tol
 
 
 def test_pd_500_iterations_f64_vs_stored_oracle_run():
