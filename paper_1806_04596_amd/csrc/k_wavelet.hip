@@ -2,10 +2,11 @@
 // l2,1 dual update (Algorithm 2; eq:prox-L21).
 //
 // Each Daubechies basis is the periodised orthonormal 2-D Mallat transform.  One
-// launch covers every (basis, channel) pair of one level and one direction, so a
-// level costs two coalesced passes (rows along x, then columns along y) over
-// the LL region of all n_db * L images.  Synthesis runs coarse to fine through a
-// scratch pyramid and the final sum over bases is a single fused pass.
+// launch covers every (basis, channel) pair of one level and one direction; a
+// work-group filters one tile along rows then columns in LDS, so each level reads
+// its input and writes its output once (plus the tile halos, read through the
+// L2).  Synthesis runs coarse to fine through a scratch pyramid, and its finest
+// level sums the bases and the Dirac term in the same pass.
 #include "hs_internal.h"
 
 namespace hs {
