@@ -618,6 +618,38 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_plain(
 
 // Phase 1 of the data dual (Algorithm 2): g = Theta G u, d = v + U (g - y)
 // (= vbar - U y) stored in v; per-run FP64 sums of |d|^2 and |y - g|^2.
+// Segmented inclusive sums of two FP64 values over the 64 lanes of a wave (lane
+// `head` starts this lane's segment), by DPP lane moves instead of LDS permutes:
+// row shifts by 1, 2, 4, 8 sum each 16-lane row from max(head, row start), then
+// the last lane of row 0 is broadcast into row 1 (and that of row 2 into row 3),
+// and the last lane of row 1, by then complete, into rows 2 and 3; a lane adds a
+// moved value only when its segment reaches back to the source lane.  Lanes that
+// a move does not reach receive zero.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int RMASK>
+__device__ __forceinline__ void seg_step(double& a0, double& a1, bool take) {
+    const double y0 = dpp_f64<CTRL, RMASK>(a0), y1 = dpp_f64<CTRL, RMASK>(a1);
+    if (take) {
+        a0 += y0;
+        a1 += y1;
+    }
+}
+__device__ __forceinline__ void seg_scan2(double& a0, double& a1, int lane, int head) {
+    seg_step<0x111, 0xF>(a0, a1, (lane & 15) >= 1 && lane - 1 >= head);    // row_shr:1
+    seg_step<0x112, 0xF>(a0, a1, (lane & 15) >= 2 && lane - 2 >= head);    // row_shr:2
+    seg_step<0x114, 0xF>(a0, a1, (lane & 15) >= 4 && lane - 4 >= head);    // row_shr:4
+    seg_step<0x118, 0xF>(a0, a1, (lane & 15) >= 8 && lane - 8 >= head);    // row_shr:8
+    // row_bcast:15 into rows 1 and 3 (sources: lanes 15 and 47)
+    seg_step<0x142, 0xA>(a0, a1, ((lane >> 4) & 1) && head <= (lane & ~15) - 1);
+    // row_bcast:31 into rows 2 and 3 (source: lane 31)
+    seg_step<0x143, 0xC>(a0, a1, lane >= 32 && head <= 31);
+}
+
 template <typename T>
 __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
     const DegridUnit* __restrict__ units, const int32_t* __restrict__ cell, const cplx<T>* __restrict__ frac,
@@ -666,14 +698,7 @@ __global__ __launch_bounds__(DEG_THREADS) void k_degrid_dual(
         const int bprev = __shfl_up(bin, 1);
         const unsigned long long heads = __ballot(act && (lane == 0 || bin != bprev));
         const int head = 63 - __builtin_clzll(heads & le);   // first lane of this lane's run
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double y0 = __shfl_up(a0, off), y1 = __shfl_up(a1, off);
-            if (lane - off >= head) {
-                a0 += y0;
-                a1 += y1;
-            }
-        }
+        seg_scan2(a0, a1, lane, head);
         const bool last = lane == 63 || !act || ((heads >> (lane + 1)) & 1ull) || (i + 1 >= u.count);
         if (act && last) {
             const int slot = run_slot[chunk_run[u.chunk0 + j] + __popcll(heads & le) - 1];
