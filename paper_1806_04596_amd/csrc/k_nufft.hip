@@ -269,10 +269,10 @@ __device__ __forceinline__ void stnt_c(cplx<T>* p, const cplx<T>& c) {
     __builtin_nontemporal_store(v, reinterpret_cast<typename NV2<T>::type*>(p));
 }
 
-template <typename T, int Ky>
+template <typename T, int Ky, bool NT>
 __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict__ H, cplx<T>* __restrict__ G,
                                                        const cplx<T>* __restrict__ tw, int ny, int Kh,
-                                                       int Hs, int Wg, int CT, int nt) {
+                                                       int Hs, int Wg, int CT) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const int l = blockIdx.y;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
     const bool live = c <= Kh;
     const cplx<T>* Hl = H + (size_t)l * ny * Hs + c;
     cplx<T>* Gl = G + (size_t)l * Ky * Wg + GR_MARGIN + c;
-    // nt: the grid rows go out as non-temporal stores (the launcher sets it when a
+    // NT: the grid rows go out as non-temporal stores (the launcher picks it when a
     // tile's row segment is at least 64 bytes; narrower segments reach memory as
     // partial lines and are slower that way)
     fft_run_ct<T, false, false, Ky>(buf, u, s, CT, tw,
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(512) void k_fft_cols_fwd(const cplx<T>* __restrict_
         },
         [&](int q, const cplx<T>& v) {
             if (live) {
-                if (nt) stnt_c(Gl + (size_t)q * Wg, v);
+                if constexpr (NT) stnt_c(Gl + (size_t)q * Wg, v);
                 else Gl[(size_t)q * Wg] = v;
             }
         });
@@ -438,7 +438,8 @@ template <typename T, int NN>
 static void fft_attrs_len() {
     const size_t b = 160 * 1024;
     set_lds(k_fft_rows_fwd<T, NN>, b);
-    set_lds(k_fft_cols_fwd<T, NN>, b);
+    set_lds(k_fft_cols_fwd<T, NN, false>, b);
+    set_lds(k_fft_cols_fwd<T, NN, true>, b);
     set_lds(k_fft_cols_adj<T, NN>, b);
     set_lds(k_fft_rows_adj<T, NN>, b);
 }
@@ -467,11 +468,17 @@ void launch_fft_rows_fwd(hs_ctx* c, const T* X, int L, int l0) {
 template <typename T>
 void launch_fft_cols_fwd(hs_ctx* c, int L, int l0) {
     const int ct = col_group<T>(c);
-    const int nt = ct * (int)sizeof(cplx<T>) >= 64 ? 1 : 0;
+    const bool nt = ct * (int)sizeof(cplx<T>) >= 64;
     dim3 grid((c->Wh + ct - 1) / ct, L);
-    HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_fwd<T, NN><<<grid, c->Ky * ct / 16, (size_t)c->Ky * ct * sizeof(cplx<T>), c->stream>>>(
-        (const cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs, (cplx<T>*)c->d.grid + (size_t)l0 * c->Ky * c->Wg,
-        (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct, nt)))
+    const cplx<T>* H = (const cplx<T>*)c->d.H + (size_t)l0 * c->ny * c->Hs;
+    cplx<T>* G = (cplx<T>*)c->d.grid + (size_t)l0 * c->Ky * c->Wg;
+    const size_t lds = (size_t)c->Ky * ct * sizeof(cplx<T>);
+    if (nt)
+        HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_fwd<T, NN, true><<<grid, c->Ky * ct / 16, lds, c->stream>>>(
+            H, G, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
+    else
+        HS_FFT_LEN_SWITCH(c->Ky, (k_fft_cols_fwd<T, NN, false><<<grid, c->Ky * ct / 16, lds, c->stream>>>(
+            H, G, (const cplx<T>*)c->d.tw_y, c->ny, c->Kh, c->Hs, c->Wg, ct)))
 }
 template <typename T>
 void launch_fft_cols_adj(hs_ctx* c, int L, int l0) {
