@@ -829,6 +829,31 @@ __global__ void k_dual_apply(cplx<T>* __restrict__ v, const int32_t* __restrict_
     v[i] = d;
 }
 
+// The same, two visibilities per thread (v + 2i 16-byte aligned for FP32: the
+// caller passes an even start).
+template <typename T>
+__global__ void k_dual_apply2(cplx<T>* __restrict__ v, const int32_t* __restrict__ vbin,
+                              const double* __restrict__ bin_f, int64_t M) {
+    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i + 1 < M) {
+        const int2 b = *reinterpret_cast<const int2*>(vbin + i);
+        const T f0 = (T)bin_f[b.x], f1 = (T)bin_f[b.y];
+        cplx<T> d0 = v[i], d1 = v[i + 1];
+        d0.re *= f0;
+        d0.im *= f0;
+        d1.re *= f1;
+        d1.im *= f1;
+        v[i] = d0;
+        v[i + 1] = d1;
+    } else if (i < M) {
+        const T f = (T)bin_f[vbin[i]];
+        cplx<T> d = v[i];
+        d.re *= f;
+        d.im *= f;
+        v[i] = d;
+    }
+}
+
 // ---------------------------------------------------------- gridding (pull)
 // Output-stationary gridding on the matrix cores.  One wave owns a GB x GB
 // (16 x 16) output block and consumes every visibility whose 8 x 8 footprint
@@ -1174,7 +1199,10 @@ void launch_dual_apply_v(hs_ctx* c, cplx<T>* v, int lc) {
     int64_t m0, nm;
     chan_range(c->chan_off, lc, m0, nm);
     if (nm == 0) return;
-    k_dual_apply<T><<<nblocks(nm, 256), 256, 0, c->stream>>>(v + m0, c->d.vis_bin + m0, c->d.bin_f, nm);
+    if (m0 % 2 == 0)
+        k_dual_apply2<T><<<nblocks((nm + 1) / 2, 256), 256, 0, c->stream>>>(v + m0, c->d.vis_bin + m0, c->d.bin_f, nm);
+    else
+        k_dual_apply<T><<<nblocks(nm, 256), 256, 0, c->stream>>>(v + m0, c->d.vis_bin + m0, c->d.bin_f, nm);
 }
 
 template <typename T>
